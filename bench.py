@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the MCSF hot path on one MI355X.
+
+A step is one whole call of the filter (bf_vec_ex: min/max reduction, order
+rule, whitening, term draws, term upload, fused kernel) over the
+4096x4096x3 sigma_s=10 K=256 workload, input resident in HBM.  Prints one
+JSON line with Mpix/s, the fused kernel's roofline position (HIP events around
+each launch) and the FP64 oracle's rate on the host as a CPU baseline.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s at 4096^2x3 σs=10 K=256 (FP32 vs FP16) + p50/p99 serving latency"
+PEAK_FP32_VALU = 157.3      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
+PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: the same without packed-FP32 issue
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops_per_pixel(d, R, K):
+    """Per output pixel: K x [4d (phase + modulation) + 8(d+1)(2R+1) (two
+    separable passes over 2(d+1) real channels) + 4(d+1) (demodulation)]."""
+    return K * (4 * d + 8 * (d + 1) * (2 * R + 1) + 4 * (d + 1))
+
+
+def cpu_baseline(f, C, sigma_s, K, seed, N, crop=256, k_sample=8):
+    """The oracle's separable MCSF (FP64 numpy, single thread) on a centred
+    crop with the first k_sample of the same terms; rate scaled to K terms."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import mcsf as O
+    H, W, d = f.shape
+    y0, x0 = (H - crop) // 2, (W - crop) // 2
+    sub = f[y0:y0 + crop, x0:x0 + crop].astype(np.float64)
+    _, w = O.sample_terms(C, N, k_sample, seed)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.mcsf_separable(sub, sigma_s, w)
+        dt = time.perf_counter() - t0
+    rate = crop * crop * (k_sample / K) / dt / 1e6
+    return {"value": rate, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"{crop}x{crop} centre crop, first {k_sample} of the {K} terms "
+                      f"(rate scaled to {K} terms), separable FP64 oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="voronoi4096_d3_s10_K256")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-kernel-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (calibrates the "
+                         "FETCH_SIZE/WRITE_SIZE counters against known traffic) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "the filter shards by image strips or by requests, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1605_02164_amd as P
+    from synth import workload
+
+    if args.copy_kernel_mib:
+        n = args.copy_kernel_mib * (1 << 20) // 4
+        a = torch.ones(n, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_kernel_mib} MiB")
+        return
+
+    log(f"generating workload {args.workload}")
+    f, C, p = workload(args.workload)
+    H, W, d = f.shape
+    sigma_s, K, seed = p["sigma_s"], p["K"], p["term_seed"]
+    R = int(math.ceil(3 * sigma_s))
+    dev = torch.device("cuda:0")
+    fg = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(fg)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step():
+        _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=out, precision=args.precision,
+                           stream=stream, time_kernel=True, return_opts=True)
+        return o.N_used, o.kernel_ms
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        N, _ = step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        N, ms = step()
+        kms.append(ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = H * W * args.steps / dt / 1e6
+    kernel_ms = float(np.mean(kms))
+    flops = algorithmic_flops_per_pixel(d, R, K) * H * W
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    log(f"N={N} step {1e3 * dt / args.steps:.2f} ms, kernel {kernel_ms:.2f} ms, "
+        f"{achieved:.2f} TFLOP/s algorithmic")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        cpu = cpu_baseline(f, C, sigma_s, K, seed, N)
+        log(f"cpu baseline {cpu['value']:.4g} Mpix/s ({cpu['sample']})")
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16 storage, f32 accumulate",
+                  "bf16": "bf16 storage, f32 accumulate"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "H": H, "W": W, "d": d, "sigma_s": sigma_s,
+                   "window": 2 * R + 1, "K": K, "N": N, "C": "0.08^2 I" if d == 3 else "SPD",
+                   "precision": args.precision},
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"mcsf_fused_fp32<{d}>",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VALU,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU,
+            "frac_vs_nonpacked_fma": achieved / PEAK_FP32_NONPACKED,
+            "traffic": None,
+            "flops_per_launch": flops,
+            "kernel_ms": kernel_ms,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+"""Thin Python binding of libbfvec (ctypes).
+
+Argument marshalling only: every step of the filter runs inside the native
+library (include/bfvec.h).  torch supplies device memory and streams.  The
+binding fails loudly when the library has not been built; there is no
+fallback implementation.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbfvec.so")
+
+BF_OK, BF_EINVAL, BF_ENOTSPD, BF_ENOMEM, BF_EDEVICE, BF_EUNSUPPORTED, BF_EBUSY = range(7)
+BF_FP32, BF_FP16, BF_BF16 = 0, 1, 2
+PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
+
+# Every symbol declared in include/bfvec.h.
+EXPORTS = [
+    "bf_opts_init", "bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten",
+    "bf_sample_terms", "bf_choose_N", "bf_minmax", "bf_direct",
+    "bf_last_error", "bf_version",
+]
+
+
+class BfError(RuntimeError):
+    """A libbfvec call returned a nonzero status."""
+
+    def __init__(self, code, msg):
+        super().__init__(f"libbfvec error {code}: {msg}")
+        self.code = code
+
+
+class bf_opts(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("center", ctypes.c_int),
+        ("tile_h", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("num_out", ctypes.c_void_p),
+        ("z_out", ctypes.c_void_p),
+        ("N_used", ctypes.c_int),
+        ("time_kernel", ctypes.c_int),
+        ("kernel_ms", ctypes.c_float),
+        ("reserved", ctypes.c_int * 5),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbfvec.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} not found: build it first (python -m paper_1605_02164_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+    L.bf_opts_init.argtypes = [ctypes.POINTER(bf_opts)]
+    L.bf_opts_init.restype = None
+    L.bf_vec.argtypes = [P, I, I, I, D, P, I, U64, P]
+    L.bf_vec_ex.argtypes = [P, I, I, I, D, P, I, U64, P, ctypes.POINTER(bf_opts)]
+    L.bf_vec_terms.argtypes = [P, I, I, I, D, P, P, I, P, ctypes.POINTER(bf_opts)]
+    L.bf_whiten.argtypes = [I, P, P]
+    L.bf_sample_terms.argtypes = [I, P, I, I, U64, P, P]
+    L.bf_choose_N.argtypes = [I, P, P, P, ctypes.POINTER(I)]
+    L.bf_minmax.argtypes = [P, I, I, I, P, P, P]
+    L.bf_direct.argtypes = [P, I, I, I, D, P, P]
+    L.bf_last_error.argtypes = []
+    L.bf_last_error.restype = ctypes.c_char_p
+    L.bf_version.argtypes = []
+    for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_sample_terms",
+                 "bf_choose_N", "bf_minmax", "bf_direct", "bf_version"):
+        getattr(L, name).restype = I
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != BF_OK:
+        raise BfError(rc, lib().bf_last_error().decode())
+
+
+def _host_f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_image(f, out):
+    import torch
+    if not (f.is_cuda and f.dtype == torch.float32 and f.dim() == 3 and f.is_contiguous()):
+        raise ValueError("f must be a contiguous (H, W, d) float32 CUDA tensor")
+    if out is None:
+        out = torch.empty_like(f)
+    elif not (out.is_cuda and out.dtype == torch.float32 and out.shape == f.shape
+              and out.is_contiguous()):
+        raise ValueError("out must be a contiguous float32 CUDA tensor shaped like f")
+    return out
+
+
+def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
+              num_out=None, z_out=None, time_kernel=False):
+    o = bf_opts()
+    lib().bf_opts_init(ctypes.byref(o))
+    o.N = int(N)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.center = 1 if center else 0
+    o.tile_h = int(tile_h)
+    o.stream = stream
+    o.num_out = None if num_out is None else num_out.data_ptr()
+    o.z_out = None if z_out is None else z_out.data_ptr()
+    o.time_kernel = 1 if time_kernel else 0
+    return o
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def bf_vec(f, sigma_s, C, K, seed, out=None):
+    """The filter on a (H, W, d) float32 CUDA tensor; synchronous, default
+    options (automatic order, FP32).  Returns out."""
+    out = _check_image(f, out)
+    H, W, d = f.shape
+    Ch = _host_f64(C, (d, d))
+    _check(lib().bf_vec(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
+                        int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr()))
+    return out
+
+
+def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
+              tile_h=0, stream=None, num_out=None, z_out=None, time_kernel=False,
+              return_opts=False):
+    """The filter with options, queued on ``stream`` (torch stream; default:
+    current stream).  Returns (out, N_used), or (out, opts) with
+    ``return_opts`` (opts.kernel_ms holds the fused-kernel time when
+    ``time_kernel`` is set)."""
+    out = _check_image(f, out)
+    H, W, d = f.shape
+    Ch = _host_f64(C, (d, d))
+    o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
+                  time_kernel)
+    _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
+                           int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
+    return (out, o) if return_opts else (out, o.N_used)
+
+
+def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center=True,
+                 tile_h=0, stream=None, num_out=None, z_out=None):
+    """The filter with an explicit (K, d) float64 term table and optional
+    weights.  Returns out."""
+    out = _check_image(f, out)
+    H, W, d = f.shape
+    wh = _host_f64(w)
+    if wh.ndim != 2 or wh.shape[1] != d:
+        raise ValueError("w must be (K, d)")
+    K = wh.shape[0]
+    wt = None if weights is None else _host_f64(weights, (K,))
+    o = make_opts(0, precision, center, tile_h, _stream_handle(stream), num_out, z_out)
+    _check(lib().bf_vec_terms(f.data_ptr(), H, W, d, float(sigma_s), _ptr(wh),
+                              None if wt is None else _ptr(wt), K, out.data_ptr(),
+                              ctypes.byref(o)))
+    return out
+
+
+def bf_whiten(C):
+    """Host whitening: W with W^T W = C^{-1}."""
+    Ch = _host_f64(C)
+    d = Ch.shape[0]
+    W = np.empty((d, d))
+    _check(lib().bf_whiten(d, _ptr(Ch), _ptr(W)))
+    return W
+
+
+def bf_sample_terms(C, N, K, seed):
+    """Host draws: returns (Y int32 (K, d), w float64 (K, d))."""
+    Ch = _host_f64(C)
+    d = Ch.shape[0]
+    Y = np.empty((K, d), dtype=np.int32)
+    w = np.empty((K, d))
+    _check(lib().bf_sample_terms(d, _ptr(Ch), int(N), int(K),
+                                 int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(Y), _ptr(w)))
+    return Y, w
+
+
+def bf_choose_N(W, lo, hi):
+    """Host order rule from the whitening and per-channel extrema."""
+    Wh = _host_f64(W)
+    d = Wh.shape[0]
+    lo32 = np.ascontiguousarray(np.asarray(lo, dtype=np.float32))
+    hi32 = np.ascontiguousarray(np.asarray(hi, dtype=np.float32))
+    N = ctypes.c_int(0)
+    _check(lib().bf_choose_N(d, _ptr(Wh), _ptr(lo32), _ptr(hi32), ctypes.byref(N)))
+    return N.value
+
+
+def bf_minmax(f, stream=None):
+    """Per-channel (lo, hi) of a CUDA image, as float32 numpy arrays."""
+    _check_image(f, None)
+    H, W, d = f.shape
+    lo = np.empty(d, dtype=np.float32)
+    hi = np.empty(d, dtype=np.float32)
+    _check(lib().bf_minmax(f.data_ptr(), H, W, d, _ptr(lo), _ptr(hi),
+                           _stream_handle(stream)))
+    return lo, hi
+
+
+def bf_direct(f, sigma_s, C, out=None):
+    """Direct GPU evaluation of eqs. (BF)/(normal) (exact Gaussian range kernel)."""
+    out = _check_image(f, out)
+    H, W, d = f.shape
+    Ch = _host_f64(C, (d, d))
+    _check(lib().bf_direct(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), out.data_ptr()))
+    return out
+
+
+def version():
+    return lib().bf_version()

@@ -1,0 +1,425 @@
+// C entry points of libbfvec that touch the device: bf_vec, bf_vec_ex,
+// bf_vec_terms, bf_minmax, bf_direct; plus the min/max reduction and the
+// direct-filter kernels.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "bfvec.h"
+#include "host.h"
+#include "mcsf_common.h"
+
+namespace bfvec {
+
+namespace {
+
+constexpr size_t kLdsLimit = 160 * 1024;
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(BF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                         \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Per-channel min/max (used by the order rule and for centring).
+// ---------------------------------------------------------------------------
+
+constexpr int kMMThreads = 256;
+
+__global__ __launch_bounds__(kMMThreads) void minmax_partial(const float* f, size_t npx, int d,
+                                                             float* part) {
+  __shared__ float s_lo[8][kMMThreads], s_hi[8][kMMThreads];
+  __shared__ int s_bad[kMMThreads];
+  float lo[8], hi[8];
+  for (int m = 0; m < 8; ++m) {
+    lo[m] = INFINITY;
+    hi[m] = -INFINITY;
+  }
+  int bad = 0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
+    for (int m = 0; m < d; ++m) {
+      const float v = f[p * d + m];
+      bad |= !isfinite(v);
+      lo[m] = fminf(lo[m], v);
+      hi[m] = fmaxf(hi[m], v);
+    }
+  }
+  for (int m = 0; m < 8; ++m) {
+    s_lo[m][threadIdx.x] = lo[m];
+    s_hi[m][threadIdx.x] = hi[m];
+  }
+  s_bad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = kMMThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int m = 0; m < 8; ++m) {
+        s_lo[m][threadIdx.x] = fminf(s_lo[m][threadIdx.x], s_lo[m][threadIdx.x + w]);
+        s_hi[m][threadIdx.x] = fmaxf(s_hi[m][threadIdx.x], s_hi[m][threadIdx.x + w]);
+      }
+      s_bad[threadIdx.x] |= s_bad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float* o = part + (size_t)blockIdx.x * 17;
+    for (int m = 0; m < 8; ++m) {
+      o[m] = s_lo[m][0];
+      o[8 + m] = s_hi[m][0];
+    }
+    o[16] = (float)s_bad[0];
+  }
+}
+
+__global__ __launch_bounds__(64) void minmax_final(const float* part, int nparts, float* res) {
+  // one wave: lane m < 8 reduces minima of channel m, lanes 8..15 maxima,
+  // lane 16 the non-finite flag
+  const int l = threadIdx.x;
+  if (l < 17) {
+    float v = l < 8 ? INFINITY : (l < 16 ? -INFINITY : 0.0f);
+    for (int i = 0; i < nparts; ++i) {
+      const float x = part[(size_t)i * 17 + l];
+      v = l < 8 ? fminf(v, x) : (l < 16 ? fmaxf(v, x) : fmaxf(v, x));
+    }
+    res[l] = v;
+  }
+}
+
+int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStream_t st) {
+  const size_t npx = (size_t)H * W;
+  const int nparts = (int)std::min<size_t>(1024, (npx + kMMThreads - 1) / kMMThreads);
+  float* dbuf = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&dbuf, ((size_t)nparts * 17 + 17) * sizeof(float), st),
+          "hipMallocAsync(minmax)");
+  float* res = dbuf + (size_t)nparts * 17;
+  hipLaunchKernelGGL(minmax_partial, dim3(nparts), dim3(kMMThreads), 0, st, f, npx, d, dbuf);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(minmax_final, dim3(1), dim3(64), 0, st, dbuf, nparts, res);
+    e = hipGetLastError();
+  }
+  float h[17];
+  if (e == hipSuccess) e = hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipFreeAsync(dbuf, st);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "min/max reduction");
+  if (h[16] != 0.0f) return fail(BF_EINVAL, "f contains NaN or infinity");
+  for (int m = 0; m < d; ++m) {
+    lo[m] = h[m];
+    hi[m] = h[8 + m];
+  }
+  return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Strip height: as tall as LDS allows, split evenly over the image height,
+// lowered while there are fewer strips than compute units.
+// ---------------------------------------------------------------------------
+
+int choose_strip_height(int d, int R, int H, int W, int requested, int* TH) {
+  const int Hr = (H + kB - 1) / kB * kB;
+  int maxTH = 0;
+  for (int th = kB; th <= Hr; th += kB)
+    if (fused_lds_bytes(d, R, th) <= kLdsLimit) maxTH = th;
+  if (maxTH == 0)
+    return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
+  if (requested > 0) {
+    const int th = (requested + kB - 1) / kB * kB;
+    if (th > maxTH) return fail(BF_EUNSUPPORTED, "requested tile_h exceeds the LDS budget");
+    *TH = th;
+    return BF_OK;
+  }
+  const int nsx = (W + kTW - 1) / kTW;
+  int n = (H + maxTH - 1) / maxTH;
+  int th = ((H + n - 1) / n + kB - 1) / kB * kB;
+  const int floor_th = std::max(kB, (2 * R + kB - 1) / kB * kB);
+  while ((long)nsx * ((H + th - 1) / th) < 256 && th > floor_th) {
+    ++n;
+    th = std::max(floor_th, ((H + n - 1) / n + kB - 1) / kB * kB);
+  }
+  *TH = th;
+  return BF_OK;
+}
+
+int check_opts(const bf_opts* o) {
+  if (o->N < 0 || o->N > 65536) return fail(BF_EINVAL, "opts.N must be 0 (auto) or in [1, 65536]");
+  if (o->precision != BF_FP32 && o->precision != BF_FP16 && o->precision != BF_BF16)
+    return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16 or BF_BF16");
+  if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
+  if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
+  return BF_OK;
+}
+
+// Checks that need no device work: window size, precision, strip height.
+int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
+  const int R = window_radius(sigma_s);
+  if (R > kRMax) return fail(BF_EUNSUPPORTED, "sigma_s too large: window radius above 40");
+  if (o->precision != BF_FP32)
+    return fail(BF_EUNSUPPORTED, "this build handles precision BF_FP32 only");
+  return choose_strip_height(d, R, H, W, o->tile_h, TH);
+}
+
+// Launch the fused filter for a host FP64 term table (radians per unit).
+int run_terms(const float* f, int H, int W, int d, double sigma_s, const double* w,
+              const double* weights, int K, float* out, bf_opts* o, const float* lo,
+              const float* hi, int TH) {
+  hipStream_t st = (hipStream_t)o->stream;
+  const int R = window_radius(sigma_s);
+
+  const int NP = d + 1;
+  const int ntp = ntaps_padded(R);
+  const int taps_al = (ntp + 3) / 4 * 4;
+  const double two_pi = 6.283185307179586476925286766559;
+  // host staging: terms | weights | taps
+  const size_t n_terms = (size_t)K * NP, n_w = weights ? (size_t)K : 0;
+  std::vector<float> hbuf(n_terms + n_w + taps_al, 0.0f);
+  for (int t = 0; t < K; ++t)
+    for (int m = 0; m < d; ++m) hbuf[(size_t)t * NP + m] = (float)(w[(size_t)t * d + m] / two_pi);
+  if (weights)
+    for (int t = 0; t < K; ++t) hbuf[n_terms + t] = (float)weights[t];
+  const std::vector<double> taps = spatial_taps(sigma_s);
+  for (int u = 0; u < 2 * R + 1; ++u) hbuf[n_terms + n_w + u] = (float)taps[u];
+
+  FusedArgs a{};
+  a.f = f;
+  a.out = out;
+  a.num_out = o->num_out;
+  a.z_out = o->z_out;
+  for (int m = 0; m < 8; ++m)
+    a.cen[m] = (o->center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
+  a.H = H;
+  a.W = W;
+  a.K = K;
+  a.R = R;
+  a.ntp = ntp;
+  a.taps_al = taps_al;
+  a.TH = TH;
+  a.nsx = (W + kTW - 1) / kTW;
+  a.nsy = (H + TH - 1) / TH;
+  a.SW = stage_width(R);
+  a.lag = (2 * R + kB - 1) / kB;
+  a.RSB = a.lag + 1;
+  a.CRB = a.lag + 2;
+  a.steps = a.lag + TH / kB;
+
+  float* dbuf = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&dbuf, hbuf.size() * sizeof(float), st), "hipMallocAsync(terms)");
+  hipError_t e = hipMemcpyAsync(dbuf, hbuf.data(), hbuf.size() * sizeof(float),
+                                hipMemcpyHostToDevice, st);
+  a.terms = dbuf;
+  a.weights = weights ? dbuf + n_terms : nullptr;
+  a.taps = dbuf + n_terms + n_w;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (e == hipSuccess && o->time_kernel) {
+    e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    if (e == hipSuccess) e = hipEventRecord(ev0, st);
+  }
+  if (e == hipSuccess) e = launch_fused_fp32(d, a, st);
+  if (e == hipSuccess && o->time_kernel) {
+    e = hipEventRecord(ev1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+    o->kernel_ms = ms;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  hipError_t e2 = hipFreeAsync(dbuf, st);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) return hip_fail(e, "fused MCSF launch");
+  return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Direct evaluation of eqs. (BF)/(normal) with the Gaussian range kernel.
+// One thread per output pixel; neighbours read through the cache hierarchy.
+// ---------------------------------------------------------------------------
+
+struct DirectArgs {
+  const float* f;
+  float* out;
+  float Wm[64];     // whitening, row-major d x d
+  float taps[96 * 2 + 1];
+  int H, W, R;
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void direct_bf(DirectArgs a) {
+  const int x = blockIdx.x * 16 + (threadIdx.x % 16);
+  const int y = blockIdx.y * 16 + (threadIdx.x / 16);
+  if (x >= a.W || y >= a.H) return;
+  float fi[D];
+  for (int m = 0; m < D; ++m) fi[m] = a.f[((size_t)y * a.W + x) * D + m];
+  float num[D];
+  for (int m = 0; m < D; ++m) num[m] = 0.0f;
+  float Z = 0.0f;
+  for (int jy = -a.R; jy <= a.R; ++jy) {
+    const int yy = y - jy;
+    if (yy < 0 || yy >= a.H) continue;
+    const float wy = a.taps[jy + a.R];
+    for (int jx = -a.R; jx <= a.R; ++jx) {
+      const int xx = x - jx;
+      if (xx < 0 || xx >= a.W) continue;
+      const float* fj = a.f + ((size_t)yy * a.W + xx) * D;
+      float v[D], dl[D];
+      for (int m = 0; m < D; ++m) {
+        v[m] = fj[m];
+        dl[m] = v[m] - fi[m];
+      }
+      float q = 0.0f;
+      for (int k = 0; k < D; ++k) {
+        float z = 0.0f;
+        for (int m = 0; m < D; ++m) z = fmaf(a.Wm[k * D + m], dl[m], z);
+        q = fmaf(z, z, q);
+      }
+      const float wgt = wy * a.taps[jx + a.R] * expf(-0.5f * q);
+      Z += wgt;
+      for (int m = 0; m < D; ++m) num[m] = fmaf(wgt, v[m], num[m]);
+    }
+  }
+  for (int m = 0; m < D; ++m) a.out[((size_t)y * a.W + x) * D + m] = num[m] / Z;
+}
+
+template <int D>
+hipError_t launch_direct(const DirectArgs& a, hipStream_t st) {
+  dim3 grid((a.W + 15) / 16, (a.H + 15) / 16);
+  hipLaunchKernelGGL(direct_bf<D>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace bfvec
+
+using namespace bfvec;
+
+extern "C" {
+
+int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double* C, int K,
+              uint64_t seed, float* out, bf_opts* o) {
+  clear_error();
+  bf_opts def;
+  if (!o) {
+    bf_opts_init(&def);
+    o = &def;
+  }
+  int rc = check_common(f, H, W, d, sigma_s, out);
+  if (rc) return rc;
+  if (K < 1 || K > 65536) return fail(BF_EINVAL, "K must be in [1, 65536]");
+  if (!C) return fail(BF_EINVAL, "C must be non-null");
+  if ((rc = check_opts(o))) return rc;
+  double Wm[64];
+  if ((rc = whiten(d, C, Wm))) return rc;
+  int TH = 0;
+  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH))) return rc;
+  float lo[8] = {0}, hi[8] = {0};
+  if (o->N == 0 || o->center) {
+    if ((rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
+  }
+  int N = o->N;
+  if (N == 0 && (rc = choose_order(d, Wm, lo, hi, &N))) return rc;
+  o->N_used = N;
+  std::vector<double> w((size_t)K * d);
+  const double sqn = std::sqrt((double)N);
+  for (int t = 0; t < K; ++t) {
+    int Y[8];
+    for (int m = 0; m < d; ++m) Y[m] = N - 2 * binomial_draw(seed, t, m, N);
+    for (int j = 0; j < d; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += (double)Y[k] * Wm[k * d + j];
+      w[(size_t)t * d + j] = s / sqn;
+    }
+  }
+  return run_terms(f, H, W, d, sigma_s, w.data(), nullptr, K, out, o, lo, hi, TH);
+}
+
+int bf_vec(const float* f, int H, int W, int d, double sigma_s, const double* C, int K,
+           uint64_t seed, float* out) {
+  bf_opts o;
+  bf_opts_init(&o);
+  int rc = bf_vec_ex(f, H, W, d, sigma_s, C, K, seed, out, &o);
+  if (rc) return rc;
+  hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return BF_OK;
+}
+
+int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const double* w,
+                 const double* weights, int K, float* out, bf_opts* o) {
+  clear_error();
+  bf_opts def;
+  if (!o) {
+    bf_opts_init(&def);
+    o = &def;
+  }
+  int rc = check_common(f, H, W, d, sigma_s, out);
+  if (rc) return rc;
+  if (K < 1 || K > (1 << 24)) return fail(BF_EINVAL, "K must be in [1, 2^24]");
+  if (!w) return fail(BF_EINVAL, "w must be non-null");
+  if ((rc = check_opts(o))) return rc;
+  for (size_t i = 0; i < (size_t)K * d; ++i)
+    if (!std::isfinite(w[i])) return fail(BF_EINVAL, "w must be finite");
+  if (weights)
+    for (int t = 0; t < K; ++t)
+      if (!(weights[t] >= 0.0) || !std::isfinite(weights[t]))
+        return fail(BF_EINVAL, "weights must be finite and nonnegative");
+  int TH = 0;
+  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH))) return rc;
+  float lo[8] = {0}, hi[8] = {0};
+  if (o->center && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
+  o->N_used = o->N;
+  return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, lo, hi, TH);
+}
+
+int bf_minmax(const float* f, int H, int W, int d, float* lo, float* hi, void* stream) {
+  clear_error();
+  if (!f || !lo || !hi) return fail(BF_EINVAL, "null argument");
+  if (H < 1 || W < 1 || d < 1 || d > 8) return fail(BF_EINVAL, "bad image shape");
+  return run_minmax(f, H, W, d, lo, hi, (hipStream_t)stream);
+}
+
+int bf_direct(const float* f, int H, int W, int d, double sigma_s, const double* C, float* out) {
+  clear_error();
+  int rc = check_common(f, H, W, d, sigma_s, out);
+  if (rc) return rc;
+  if (!C) return fail(BF_EINVAL, "C must be non-null");
+  double Wm[64];
+  if ((rc = whiten(d, C, Wm))) return rc;
+  const int R = window_radius(sigma_s);
+  if (R > 96) return fail(BF_EUNSUPPORTED, "window radius above 96");
+  DirectArgs a{};
+  a.f = f;
+  a.out = out;
+  for (int i = 0; i < d * d; ++i) a.Wm[i] = (float)Wm[i];
+  const std::vector<double> taps = spatial_taps(sigma_s);
+  for (int u = 0; u < 2 * R + 1; ++u) a.taps[u] = (float)taps[u];
+  a.H = H;
+  a.W = W;
+  a.R = R;
+  hipError_t e;
+  switch (d) {
+    case 1: e = launch_direct<1>(a, nullptr); break;
+    case 2: e = launch_direct<2>(a, nullptr); break;
+    case 3: e = launch_direct<3>(a, nullptr); break;
+    case 4: e = launch_direct<4>(a, nullptr); break;
+    case 5: e = launch_direct<5>(a, nullptr); break;
+    case 6: e = launch_direct<6>(a, nullptr); break;
+    case 7: e = launch_direct<7>(a, nullptr); break;
+    default: e = launch_direct<8>(a, nullptr); break;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return hip_fail(e, "direct filter");
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Internal host-side helpers of libbfvec (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bfvec {
+
+// Thread-local error message, reported through bf_last_error().
+void set_error(const std::string& msg);
+void clear_error();
+
+// Returns a status code after recording msg.
+int fail(int code, const std::string& msg);
+
+// Window radius R = ceil(3 sigma_s) (square window of the paper's Section 1).
+int window_radius(double sigma_s);
+
+// One-dimensional factor of the spatial Gaussian, omega_1(u) for u = -R..R.
+std::vector<double> spatial_taps(double sigma_s);
+
+// Whitening per eq. (COB); see bf_whiten in bfvec.h.  Returns a status.
+int whiten(int d, const double* C, double* W);
+
+// Philox4x32-10 block function (Salmon et al., SC'11).
+void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+// X[t][m] ~ B(N, 1/2) from the Philox stream of (seed, t, m).
+int binomial_draw(uint64_t seed, int t, int m, int N);
+
+// Order rule; see bf_choose_N.
+int choose_order(int d, const double* W, const float* lo, const float* hi, int* N);
+
+// Argument validation shared by the entry points.
+int check_common(const void* f, int H, int W, int d, double sigma_s, const void* out);
+
+}  // namespace bfvec

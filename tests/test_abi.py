@@ -1,0 +1,148 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+and its host-side logic (whitening, draws, order rule, validation) agrees with
+the oracle.  No device work is started here."""
+
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import paper_1605_02164_amd as P
+from paper_1605_02164_amd import bfvec as B
+from oracle import mcsf as O
+from synth import random_spd
+from tests.helpers import header_functions
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    declared = header_functions()
+    assert set(declared) == set(P.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert P.version() >= 10000
+
+
+def test_opts_struct_layout(tmp_path):
+    # the ctypes mirror of bf_opts must match the C layout of include/bfvec.h
+    import subprocess
+    from tests.helpers import ROOT
+    fields = [name for name, _ in B.bf_opts._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "bfvec.h"\n'
+                   "int main(void){printf(\"%zu\", sizeof(bf_opts));" +
+                   "".join(f'printf(" %zu", offsetof(bf_opts, {n}));' for n in fields) +
+                   "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", f"{ROOT}/include", str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(B.bf_opts)
+    assert got[1:] == [getattr(B.bf_opts, n).offset for n in fields]
+    o = B.bf_opts()
+    B.lib().bf_opts_init(ctypes.byref(o))
+    assert (o.N, o.precision, o.center, o.tile_h) == (0, 0, 1, 0)
+
+
+@pytest.mark.parametrize("d,seed", [(1, 1), (3, 2), (6, 3), (8, 4)])
+def test_whitening_matches_oracle(d, seed):
+    C = random_spd(d, -3, -1, seed)
+    W = P.bf_whiten(C)
+    assert np.max(np.abs(W - O.whiten(C))) <= 1e-13 * np.max(np.abs(W))
+    Ci = np.linalg.inv(C)
+    assert np.max(np.abs(W.T @ W - Ci)) <= 1e-12 * np.max(np.abs(Ci))
+
+
+def test_whitening_block_and_diagonal():
+    C = np.array([[100.0, 0, 0], [0, 25, 12.5], [0, 12.5, 25]])
+    assert np.max(np.abs(P.bf_whiten(C) - O.whiten(C))) < 1e-16
+    Cd = np.diag([0.0064, 0.0064, 0.0064])
+    assert np.array_equal(P.bf_whiten(Cd), O.whiten(Cd))
+
+
+@pytest.mark.parametrize("d,N,K,seed", [(3, 33, 256, 2003), (3, 309, 128, 2002),
+                                        (6, 40, 64, 2004), (1, 1, 50, 0),
+                                        (2, 65, 17, 2**63 + 12345)])
+def test_draws_match_oracle(d, N, K, seed):
+    C = random_spd(d, -3, -1, d + 10) if d > 1 else np.array([[0.04]])
+    Y, w = P.bf_sample_terms(C, N, K, seed)
+    Yo, wo = O.sample_terms(C, N, K, seed)
+    assert np.array_equal(Y, Yo)
+    assert np.max(np.abs(w - wo)) <= 1e-13 * max(1.0, np.max(np.abs(wo)))
+
+
+def test_order_rule_matches_oracle():
+    rng = np.random.default_rng(5)
+    for d in (1, 3, 6):
+        C = random_spd(d, -3, -1, d) if d > 1 else np.array([[0.01]])
+        W = O.whiten(C)
+        f = rng.uniform(-0.3, 1.2, size=(5, 7, d)).astype(np.float32)
+        lo, hi = f.reshape(-1, d).min(0), f.reshape(-1, d).max(0)
+        assert P.bf_choose_N(W, lo, hi) == O.choose_order(f, W)
+
+
+def test_order_rule_limit():
+    W = np.eye(1) / 1e-3
+    with pytest.raises(P.BfError) as e:
+        P.bf_choose_N(W, [0.0], [1.0])
+    assert e.value.code == B.BF_EUNSUPPORTED
+
+
+def _call_vec(f=0x1000, H=8, W=8, d=3, sigma=1.0, C=None, K=4, out=0x100000):
+    C = np.eye(d) * 0.01 if C is None else C
+    Ch = np.ascontiguousarray(C, dtype=np.float64)
+    rc = B.lib().bf_vec(f, H, W, d, sigma, Ch.ctypes.data_as(ctypes.c_void_p) if C is not False else None,
+                        K, 1, out)
+    return rc, B.lib().bf_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(H=0), B.BF_EINVAL), (dict(W=-1), B.BF_EINVAL), (dict(d=0), B.BF_EINVAL),
+    (dict(d=9, C=np.eye(9)), B.BF_EINVAL), (dict(K=0), B.BF_EINVAL),
+    (dict(sigma=-1.0), B.BF_EINVAL), (dict(sigma=float("nan")), B.BF_EINVAL),
+    (dict(sigma=40.0), B.BF_EINVAL), (dict(f=0), B.BF_EINVAL), (dict(out=0), B.BF_EINVAL),
+    (dict(out=0x1000 + 16), B.BF_EINVAL),                # out overlaps f
+    (dict(C=np.array([[1.0, 0.5, 0], [0.4, 1, 0], [0, 0, 1]])), B.BF_ENOTSPD),
+    (dict(C=np.array([[1.0, 2, 0], [2, 1, 0], [0, 0, 1]])), B.BF_ENOTSPD),
+    (dict(C=np.diag([1.0, 0.0, 1.0])), B.BF_ENOTSPD),
+    (dict(sigma=14.0), B.BF_EUNSUPPORTED),               # R = 42 > 40
+])
+def test_argument_errors_before_device_work(kw, code):
+    rc, msg = _call_vec(**kw)
+    assert rc == code, msg
+    assert msg
+
+
+def test_invalid_options_rejected():
+    o = B.make_opts()
+    o.precision = 7
+    Ch = np.eye(3) * 0.01
+    rc = B.lib().bf_vec_ex(0x1000, 8, 8, 3, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                           0x100000, ctypes.byref(o))
+    assert rc == B.BF_EINVAL
+    o = B.make_opts()
+    o.N = -2
+    rc = B.lib().bf_vec_ex(0x1000, 8, 8, 3, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                           0x100000, ctypes.byref(o))
+    assert rc == B.BF_EINVAL
+
+
+def test_term_table_validation():
+    w = np.array([[1.0, float("inf"), 0.0]])
+    rc = B.lib().bf_vec_terms(0x1000, 4, 4, 3, 1.0, w.ctypes.data_as(ctypes.c_void_p), None, 1,
+                              0x100000, None)
+    assert rc == B.BF_EINVAL
+    w = np.ones((2, 3))
+    wt = np.array([1.0, -1.0])
+    rc = B.lib().bf_vec_terms(0x1000, 4, 4, 3, 1.0, w.ctypes.data_as(ctypes.c_void_p),
+                              wt.ctypes.data_as(ctypes.c_void_p), 2, 0x100000, None)
+    assert rc == B.BF_EINVAL
+
+
+def test_product_path_has_no_fallback(monkeypatch, tmp_path):
+    # a missing library is an error, never a silent CPU path
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        B.lib()
