@@ -122,32 +122,37 @@ int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStr
 }
 
 // ---------------------------------------------------------------------------
-// Strip height: as tall as LDS allows, split evenly over the image height,
-// lowered while there are fewer strips than compute units.
+// Strip height.  Each workgroup streams one strip per term and recomputes 2R
+// halo rows per strip, so tall strips waste less; but all compute units
+// should be busy (two workgroups fit on a CU).  Choose the number of strips
+// down the image that minimises (waves of workgroups) x (rows per strip incl.
+// halo).
 // ---------------------------------------------------------------------------
 
 int choose_strip_height(int d, int R, int H, int W, int requested, int* TH) {
-  const int Hr = (H + kB - 1) / kB * kB;
-  int maxTH = 0;
-  for (int th = kB; th <= Hr; th += kB)
-    if (fused_lds_bytes(d, R, th) <= kLdsLimit) maxTH = th;
-  if (maxTH == 0)
+  if (fused_lds_bytes(d, R) > kLdsLimit)
     return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
   if (requested > 0) {
-    const int th = (requested + kB - 1) / kB * kB;
-    if (th > maxTH) return fail(BF_EUNSUPPORTED, "requested tile_h exceeds the LDS budget");
-    *TH = th;
+    *TH = (requested + kB - 1) / kB * kB;
     return BF_OK;
   }
   const int nsx = (W + kTW - 1) / kTW;
-  int n = (H + maxTH - 1) / maxTH;
-  int th = ((H + n - 1) / n + kB - 1) / kB * kB;
-  const int floor_th = std::max(kB, (2 * R + kB - 1) / kB * kB);
-  while ((long)nsx * ((H + th - 1) / th) < 256 && th > floor_th) {
-    ++n;
-    th = std::max(floor_th, ((H + n - 1) / n + kB - 1) / kB * kB);
+  const int slots = 2 * 256;                 // resident workgroups on the GPU
+  const int halo = lag_steps(R) * kB;
+  long best = -1;
+  int best_th = kB;
+  for (int nsy = 1; nsy <= (H + kB - 1) / kB; ++nsy) {
+    const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
+    const long nwg = (long)nsx * ((H + th - 1) / th);
+    const long waves = (nwg + slots - 1) / slots;
+    const long cost = waves * (th + halo);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_th = th;
+    }
+    if (nwg > 16L * slots) break;
   }
-  *TH = th;
+  *TH = best_th;
   return BF_OK;
 }
 
@@ -175,60 +180,68 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
               const float* hi, int TH) {
   hipStream_t st = (hipStream_t)o->stream;
   const int R = window_radius(sigma_s);
-
   const int NP = d + 1;
-  const int ntp = ntaps_padded(R);
-  const int taps_al = (ntp + 3) / 4 * 4;
+  const int ntaps = 2 * R + 1;
   const double two_pi = 6.283185307179586476925286766559;
   // host staging: terms | weights | taps
   const size_t n_terms = (size_t)K * NP, n_w = weights ? (size_t)K : 0;
-  std::vector<float> hbuf(n_terms + n_w + taps_al, 0.0f);
+  std::vector<float> hbuf(n_terms + n_w + (size_t)ntaps, 0.0f);
   for (int t = 0; t < K; ++t)
     for (int m = 0; m < d; ++m) hbuf[(size_t)t * NP + m] = (float)(w[(size_t)t * d + m] / two_pi);
   if (weights)
     for (int t = 0; t < K; ++t) hbuf[n_terms + t] = (float)weights[t];
   const std::vector<double> taps = spatial_taps(sigma_s);
-  for (int u = 0; u < 2 * R + 1; ++u) hbuf[n_terms + n_w + u] = (float)taps[u];
+  for (int u = 0; u < ntaps; ++u) hbuf[n_terms + n_w + u] = (float)taps[u];
 
   FusedArgs a{};
   a.f = f;
-  a.out = out;
-  a.num_out = o->num_out;
-  a.z_out = o->z_out;
   for (int m = 0; m < 8; ++m)
     a.cen[m] = (o->center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
   a.H = H;
   a.W = W;
   a.K = K;
   a.R = R;
-  a.ntp = ntp;
-  a.taps_al = taps_al;
   a.TH = TH;
   a.nsx = (W + kTW - 1) / kTW;
   a.nsy = (H + TH - 1) / TH;
   a.SW = stage_width(R);
-  a.lag = (2 * R + kB - 1) / kB;
+  a.lag = lag_steps(R);
   a.RSB = a.lag + 1;
   a.CRB = a.lag + 2;
   a.steps = a.lag + TH / kB;
 
+  // one stream-ordered allocation: accumulators | terms | weights | taps
+  const size_t n_acc = (size_t)NP * H * W;
   float* dbuf = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&dbuf, hbuf.size() * sizeof(float), st), "hipMallocAsync(terms)");
-  hipError_t e = hipMemcpyAsync(dbuf, hbuf.data(), hbuf.size() * sizeof(float),
+  HIP_TRY(hipMallocAsync((void**)&dbuf, (n_acc + hbuf.size()) * sizeof(float), st),
+          "hipMallocAsync(accumulators)");
+  a.acc = dbuf;
+  float* dterms = dbuf + n_acc;
+  hipError_t e = hipMemcpyAsync(dterms, hbuf.data(), hbuf.size() * sizeof(float),
                                 hipMemcpyHostToDevice, st);
-  a.terms = dbuf;
-  a.weights = weights ? dbuf + n_terms : nullptr;
-  a.taps = dbuf + n_terms + n_w;
+  const float* dweights = weights ? dterms + n_terms : nullptr;
+  a.taps = dterms + n_terms + n_w;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (e == hipSuccess && o->time_kernel) {
     e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     if (e == hipSuccess) e = hipEventRecord(ev0, st);
   }
-  if (e == hipSuccess) e = launch_fused_fp32(d, a, st);
+  if (e == hipSuccess) e = launch_fused_fp32(d, a, dterms, dweights, st);
+  if (e == hipSuccess && o->time_kernel) e = hipEventRecord(ev1, st);
+  if (e == hipSuccess) {
+    FinalizeArgs fa{};
+    fa.acc = a.acc;
+    fa.out = out;
+    fa.num_out = o->num_out;
+    fa.z_out = o->z_out;
+    for (int m = 0; m < 8; ++m) fa.cen[m] = a.cen[m];
+    fa.H = H;
+    fa.W = W;
+    e = launch_finalize(d, fa, st);
+  }
   if (e == hipSuccess && o->time_kernel) {
-    e = hipEventRecord(ev1, st);
-    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    e = hipEventSynchronize(ev1);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
     o->kernel_ms = ms;

@@ -9,25 +9,28 @@ namespace bfvec {
 
 // Tile geometry of the fused kernels.
 constexpr int kTW = 16;   // output columns per workgroup strip
-constexpr int kB = 16;    // input rows per pipeline step
-constexpr int kP1 = 8;    // horizontal-pass outputs per item (register block)
+constexpr int kB = 8;     // input rows per pipeline step
+constexpr int kP1 = 4;    // horizontal-pass outputs per item (register block)
 constexpr int kP2 = 4;    // vertical-pass outputs per item (register block)
 constexpr int kRMax = 40; // largest window radius handled by the fused kernels
-// taps padded to a multiple of 8 (zero taps), staging row width, and its bound
-inline constexpr int ntaps_padded(int R) { return ((2 * R + 1 + 7) / 8) * 8; }
-inline constexpr int stage_width(int R) { return kTW + ntaps_padded(R) + 4; }
+
+// Staging row width for radius R: at least TW + 2R + 4 floats (the
+// horizontal window of a 4-output block plus one spare block), and equal to
+// 8 modulo 16 so that the 128-bit window loads of the 16 lanes that share an
+// LDS cycle fall in distinct bank groups.
+inline constexpr int stage_width(int R) {
+  return 16 * ((kTW + 2 * R + 4 - 8 + 15) / 16) + 8;
+}
 constexpr int kSWMax = stage_width(kRMax);
+// 2R rows of look-ahead, in steps of kB rows
+inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
 
 struct FusedArgs {
   const float* f;        // H*W*d input (device)
-  float* out;            // H*W*d output (device)
-  float* num_out;        // optional H*W*d numerator (device) or null
-  float* z_out;          // optional H*W normaliser (device) or null
-  const float* terms;    // K*(d+1): w_t / (2 pi) (revolutions per unit), pad
-  const float* weights;  // K term weights or null
-  const float* taps;     // ntp spatial taps, zero padded
+  float* acc;            // (d+1)*H*W accumulators, planar [m][y][x] (device)
+  const float* taps;     // 2R+1 spatial taps (device), zero padded to a multiple of 4
   float cen[8];          // per-channel centre subtracted before the phase
-  int H, W, K, R, ntp, taps_al;
+  int H, W, K, R;
   int TH;                // strip height (multiple of kB)
   int nsx, nsy;          // strips across and down
   int SW;                // staging row width (floats)
@@ -35,7 +38,18 @@ struct FusedArgs {
   int steps, lag;        // steps per term, and 2R look-ahead in steps
 };
 
-size_t fused_lds_bytes(int d, int R, int TH);
-hipError_t launch_fused_fp32(int d, const FusedArgs& a, hipStream_t st);
+struct FinalizeArgs {
+  const float* acc;      // (d+1)*H*W planar accumulators
+  float* out;            // H*W*d
+  float* num_out;        // optional H*W*d numerator (uncentred) or null
+  float* z_out;          // optional H*W normaliser or null
+  float cen[8];
+  int H, W;
+};
+
+size_t fused_lds_bytes(int d, int R);
+hipError_t launch_fused_fp32(int d, const FusedArgs& a, const float* terms,
+                             const float* weights, hipStream_t st);
+hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t st);
 
 }  // namespace bfvec

@@ -1,24 +1,27 @@
 // Fused MCSF kernel for gfx950 (CDNA4), FP32 channels.
 //
-// One workgroup owns a strip of TW output columns and TH output rows and keeps
-// the numerator and normaliser of every strip pixel in LDS for the whole run
-// (Algorithm 1, accumulators P and Z).  For each of the K terms it streams
-// down the strip in steps of B input rows; a step
+// One workgroup owns a strip of TW output columns and TH output rows (TH is
+// normally a large fraction of the image height).  For each of the K terms
+// it streams down the strip in steps of B input rows; a step
 //   1. modulates B haloed rows: theta = <w_t, f - c>, H = cos + i sin
 //      (eq. (Ht)), writing the 2(d+1) real channels
 //      {cos f_m, sin f_m (m < d), cos, sin} to a staging buffer (zero outside
 //      the image: out-of-domain pixels contribute nothing);
-//   2. runs the horizontal pass of the separable truncated Gaussian omega on
-//      those rows, writing into a ring of the last RS rows;
-//   3. once 2R rows of look-ahead are in the ring, runs the vertical pass for B
-//      output rows and demodulates into the accumulators:
-//      P_m += cos * (omega*cos f_m) + sin * (omega*sin f_m),
-//      Z   += cos * (omega*cos)     + sin * (omega*sin)   (eqs. (numerator), (denom)).
-// After the last term out = P / Z is written (Algorithm 1, last step).
+//   2. runs the horizontal pass of the truncated separable Gaussian omega
+//      over those rows into a ring holding the last RS rows;
+//   3. once 2R rows of look-ahead are in the ring, runs the vertical pass for
+//      B output rows and demodulates:
+//      P_m += cos (omega * cos f_m) + sin (omega * sin f_m),
+//      Z   += cos (omega * cos)     + sin (omega * sin)    (eqs. (numerator), (denom)),
+//      adding into planar accumulators in device memory (Algorithm 1, P and Z).
+// A separate finalize kernel divides (Algorithm 1, last step).
 //
-// Work per output pixel and term: 2(d+1)(2R+1) FMAs per pass.  Both passes are
-// register-blocked sliding windows reading LDS with 128-bit loads; taps are
-// read from LDS as wave-uniform broadcasts.  No MFMA: the passes are stencils.
+// Work per output pixel and term: 2(d+1)(2R+1) FMAs per pass.  Both passes
+// are register-blocked sliding windows over LDS (4 outputs per item).  With
+// R fixed at compile time the window loops unroll completely and the taps
+// live in registers; a runtime-R variant serves every other radius.  No
+// MFMA: the passes are stencils.  LDS stays near 70 KB so two workgroups
+// share a compute unit.
 
 #include <hip/hip_runtime.h>
 
@@ -30,106 +33,183 @@ namespace {
 
 template <int D>
 struct Geo {
-  static constexpr int NP = D + 1;        // channel pairs (d numerators + Z)
-  static constexpr int NC = 2 * NP;       // real channels
-  static constexpr int NT = 64 * NP;      // threads per workgroup
-  // modulation slots per thread (B x SW pixels, SW <= SW_MAX)
-  static constexpr int MI = (kB * kSWMax + NT - 1) / NT;
+  static constexpr int NP = D + 1;   // channel pairs (d numerators + Z)
+  static constexpr int NC = 2 * NP;  // real channels
+  static constexpr int NT = 64 * NP; // threads per workgroup
+  static constexpr int MI = (kB * kSWMax + NT - 1) / NT;  // modulation slots
 };
 
 __device__ __forceinline__ int wrap(int r, int n) { return r >= n ? r - n : r; }
 
-__device__ __forceinline__ void ld8(float (&v)[8], const float* p) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  const float4 b = *reinterpret_cast<const float4*>(p + 4);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-
-__device__ __forceinline__ void ld4(float (&v)[8], const float* p) {
+__device__ __forceinline__ void ld4(float* v, const float* p) {
   const float4 a = *reinterpret_cast<const float4*>(p);
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
-// Sliding-window FMAs of a P-output register block.  The window is two
-// P-blocks (lo | hi); output p takes taps t[i] against window[p + i].
-// fma_lo applies the terms that fall in the lo block, fma_hi the rest.
-template <int P, int N>
-__device__ __forceinline__ void fma_lo(float (&acc)[P], const float* t, const float (&lo)[N]) {
+// Sliding-window FMAs of a 4-output register block against taps t[0..3]:
+// output p takes t[i] * window[p + i]; the window is two 4-blocks (lo | hi).
+__device__ __forceinline__ void fma_lo(float (&acc)[4], const float* t, const float* lo) {
 #pragma unroll
-  for (int i = 0; i < P; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int p = 0; p + i < P; ++p) acc[p] = fmaf(t[i], lo[p + i], acc[p]);
+    for (int p = 0; p + i < 4; ++p) acc[p] = fmaf(t[i], lo[p + i], acc[p]);
+}
+__device__ __forceinline__ void fma_hi(float (&acc)[4], const float* t, const float* hi) {
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+#pragma unroll
+    for (int p = 4 - i; p < 4; ++p) acc[p] = fmaf(t[i], hi[p + i - 4], acc[p]);
 }
 
-template <int P, int N>
-__device__ __forceinline__ void fma_hi(float (&acc)[P], const float* t, const float (&hi)[N]) {
+// Horizontal pass of one item: 4 consecutive outputs of one channel of one
+// row; src points at the staging column of the first output's window start.
+template <int RC>
+__device__ __forceinline__ void hpass(const float* src, const float* tapr, const float* s_taps,
+                                      int ntap4, float (&acc)[4]) {
+  if constexpr (RC >= 0) {
+    constexpr int NW = 2 * RC + 4, NB = (NW + 3) / 4;
+    float x[NB * 4];
 #pragma unroll
-  for (int i = 1; i < P; ++i)
+    for (int b = 0; b < NB; ++b) ld4(x + 4 * b, src + 4 * b);
 #pragma unroll
-    for (int p = P - i; p < P; ++p) acc[p] = fmaf(t[i], hi[p + i - P], acc[p]);
+    for (int u = 0; u <= 2 * RC; ++u)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u], x[p + u], acc[p]);
+  } else {
+    const int nblk = ntap4 / 4;
+    float ra[4], rb[4], t[8];
+    ld4(ra, src);
+    ld4(rb, src + 4);
+    int b = 0;
+    for (; b + 2 <= nblk; b += 2) {
+      ld4(t, s_taps + 4 * b);
+      ld4(t + 4, s_taps + 4 * b + 4);
+      fma_lo(acc, t, ra);
+      ld4(ra, src + 4 * b + 8);                       // b + 2 <= nblk here
+      fma_hi(acc, t, rb);
+      fma_lo(acc, t + 4, rb);
+      ld4(rb, src + 4 * min(b + 3, nblk));            // clamped: no branch
+      fma_hi(acc, t + 4, ra);
+    }
+    if (b < nblk) {
+      ld4(t, s_taps + 4 * b);
+      fma_lo(acc, t, ra);
+      fma_hi(acc, t, rb);
+    }
+  }
+}
+
+// Vertical pass of one item: 4 consecutive output rows of one channel of one
+// column.  col points at the channel column in ring row 0; rb is the ring row
+// of the first window row; ring rows wrap at RS (window blocks of 4 rows are
+// aligned, so a block never straddles the wrap).
+template <int RC, int RST>
+__device__ __forceinline__ void vpass(const float* col, int rb, int RS, const float* tapr,
+                                      const float* s_taps, int ntap4, float (&acc)[4]) {
+  if constexpr (RC >= 0) {
+    constexpr int NW = 2 * RC + 4, NB = (NW + 3) / 4;
+    float x[NB * 4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const float* r = col + wrap(rb + 4 * b, RS) * RST;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[4 * b + i] = r[i * RST];
+    }
+#pragma unroll
+    for (int u = 0; u <= 2 * RC; ++u)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u], x[p + u], acc[p]);
+  } else {
+    const int nblk = ntap4 / 4;
+    auto ldb = [&](float* v, int blk) {
+      const float* r = col + wrap(rb + 4 * blk, RS) * RST;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = r[i * RST];
+    };
+    float ra[4], rbv[4], t[8];
+    ldb(ra, 0);
+    ldb(rbv, 1);
+    int b = 0;
+    for (; b + 2 <= nblk; b += 2) {
+      ld4(t, s_taps + 4 * b);
+      ld4(t + 4, s_taps + 4 * b + 4);
+      fma_lo(acc, t, ra);
+      ldb(ra, b + 2);
+      fma_hi(acc, t, rbv);
+      fma_lo(acc, t + 4, rbv);
+      ldb(rbv, min(b + 3, nblk));
+      fma_hi(acc, t + 4, ra);
+    }
+    if (b < nblk) {
+      ld4(t, s_taps + 4 * b);
+      fma_lo(acc, t, ra);
+      fma_hi(acc, t, rbv);
+    }
+  }
 }
 
 }  // namespace
 
-template <int D>
+// RC: window radius fixed at compile time, or -1 for a runtime radius.
+template <int D, int RC>
 __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
                                                                 const float* __restrict__ terms,
                                                                 const float* __restrict__ weights) {
   using G = Geo<D>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
-  constexpr int TW = kTW, B = kB, P1 = kP1, P2 = kP2;
-  constexpr int RST = 2 * NP * TW;         // ring row stride [k][m][x]
-  constexpr int CST = 2 * TW;              // cos/sin ring row stride [k][x]
-  constexpr int AST = NP * TW;             // accumulator row stride [m][x]
+  constexpr int TW = kTW, B = kB;
+  constexpr int RST = NC * TW;       // ring row stride: [ch][x]
+  constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
+  constexpr int NTAPR = RC >= 0 ? 2 * RC + 1 : 1;
 
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
-  const int SW = a.SW, R = a.R, ntp = a.ntp, TH = a.TH;
+  const int R = RC >= 0 ? RC : a.R;
+  const int SW = RC >= 0 ? stage_width(RC) : a.SW;
+  const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
+  const int taps_al = (ntap4 + 7) / 8 * 8;
   const int RS = a.RSB * B, CRS = a.CRB * B;
   float* s_taps = lds;
-  float* s_stage = s_taps + a.taps_al;
+  float* s_stage = s_taps + taps_al;
   float* s_ring = s_stage + B * NC * SW;
   float* s_cs = s_ring + RS * RST;
-  float* s_acc = s_cs + CRS * CST;
 
   const int tid = threadIdx.x;
-  // XCD-aware tile order: consecutive dispatch ids go round-robin over the 8
-  // XCDs; give each XCD a contiguous run of strips so that neighbouring strips
-  // (which share their halo of f) meet in the same L2.
+  // XCD-aware strip order: dispatch ids go round-robin over the 8 XCDs; give
+  // each XCD a contiguous run of strips so neighbours (which share their halo
+  // of f) meet in the same L2.
   const int nt = a.nsx * a.nsy;
   int bid = blockIdx.x;
-  {
-    const int per = (nt + 7) / 8;
-    const int xcd = bid % 8, loc = bid / 8;
-    const int remapped = xcd * per + loc;
-    bid = (nt % 8 == 0) ? remapped : bid;
-  }
+  if (nt % 8 == 0) bid = (bid % 8) * (nt / 8) + bid / 8;
   const int sx = bid % a.nsx, sy = bid / a.nsx;
-  const int x0 = sx * TW, y0 = sy * TH;
-
-  for (int i = tid; i < a.taps_al; i += NT) s_taps[i] = i < ntp ? a.taps[i] : 0.0f;
-  for (int i = tid; i < RS * RST; i += NT) s_ring[i] = 0.0f;
-  for (int i = tid; i < TH * AST; i += NT) s_acc[i] = 0.0f;
-
-  // ---- per-thread fixed roles --------------------------------------------
-  // modulation: pixel slots tid + i*NT of the B x SW step tile
-  // pass 1 item: channel ch, row rr, column block xb (P1 outputs)
-  const int p1_ch = tid % NC;
-  const int p1_rr = ((tid / NC) % 2) + 2 * (tid / (4 * NC));
-  const int p1_xb = (tid / (2 * NC)) % 2;
-  const int p1_k = p1_ch % 2, p1_m = p1_ch / 2;
-  // pass 2 item: column x, pair m, row group g (P2 outputs)
-  const int p2_x = tid % TW;
-  const int p2_m = (tid / TW) % NP;
-  int p2_g = tid / (TW * NP);
-  if constexpr (TW * NP == 64) p2_g = __builtin_amdgcn_readfirstlane(p2_g);
-
-  const int nmod = B * SW;
+  const int x0 = sx * TW, y0 = sy * a.TH;
   const int Wd = a.W, Hd = a.H;
 
-  // Modulation slots: pixel tid + i*NT of the B x SW step tile.  Their row,
-  // column and column validity do not change between steps: precompute them.
+  for (int i = tid; i < taps_al; i += NT) s_taps[i] = i < 2 * R + 1 ? a.taps[i] : 0.0f;
+  for (int i = tid; i < RS * RST; i += NT) s_ring[i] = 0.0f;
+  __syncthreads();
+  float tapr[NTAPR];
+#pragma unroll
+  for (int u = 0; u < NTAPR; ++u) tapr[u] = s_taps[u];
+
+  // ---- per-thread fixed roles -------------------------------------------------
+  // pass 1 item: channel ch, 4-column block xq, row rr of the step
+  const int p1_ch = tid % NC;
+  const int p1_xq = (tid / NC) % 4;
+  const int p1_rr = tid / (4 * NC);
+  // pass 2 item: column x, cos/sin half k, pair m, 4-row group g
+  const int p2_x = tid & 15;
+  const int p2_k = (tid >> 4) & 1;
+  const int p2_m = (tid >> 5) % NP;
+  int p2_g = (tid >> 5) / NP;
+  if constexpr (NP % 2 == 0) p2_g = __builtin_amdgcn_readfirstlane(p2_g);
+  const int p2_ch = 2 * p2_m + p2_k;
+  const bool p2_xin = x0 + p2_x < Wd;
+  const size_t plane = (size_t)Hd * Wd;
+  float* accm = a.acc + (size_t)p2_m * plane + min(x0 + p2_x, Wd - 1);  // lane's column of plane m
+
+  // modulation slots: pixel tid + i*NT of the B x SW step tile
+  const int nmod = B * SW;
   int m_rr[MI], m_off[MI], m_x[MI];
   bool m_xin[MI];
 #pragma unroll
@@ -142,33 +222,39 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
     m_xin[i] = tid + i * NT < nmod && j < TW + 2 * R && m_x[i] >= 0 && m_x[i] < Wd;
   }
   const int ybase = y0 - R;
-  const float* fcol = a.f;
 
-  // Prefetch registers: raw f of each slot for the next step.  Loads are
-  // unconditional from a clamped (in-image) address so they stay in flight
-  // across the passes; masking happens at use.
+  // f prefetch: raw values of each slot for the next step, loaded from a
+  // clamped in-image address so the loads stay in flight across the passes
   float fcur[MI][D];
-  auto load_step = [&](int s, float (&dst)[MI][D]) {
+  auto load_f = [&](int s) {
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
-      if (i * NT < nmod) {  // wave-uniform: skip slots beyond the step tile
+      if (i * NT < nmod) {
         const int y = min(max(ybase + s * B + m_rr[i], 0), Hd - 1);
         const int x = min(max(m_x[i], 0), Wd - 1);
-        const float* src = fcol + ((size_t)y * Wd + x) * D;
+        const float* src = a.f + ((size_t)y * Wd + x) * D;
 #pragma unroll
-        for (int m = 0; m < D; ++m) dst[i][m] = src[m];
+        for (int m = 0; m < D; ++m) fcur[i][m] = src[m];
       }
     }
   };
-  load_step(0, fcur);
-  __syncthreads();
+  // accumulator prefetch for the output rows of step s of term t
+  float accp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  auto load_acc = [&](int t, int s) {
+    if (t > 0 && t < a.K && s >= a.lag && p2_k == 0 && p2_xin) {
+      const int yb = y0 + (s - a.lag) * B + p2_g * 4;
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        if (yb + p < Hd) accp[p] = accm[(size_t)(yb + p) * Wd];
+    }
+  };
+  load_f(0);
 
   const int steps = a.steps, lag = a.lag;
-  const float* termp = terms;
-  for (int t = 0; t < a.K; ++t, termp += NP) {
+  for (int t = 0; t < a.K; ++t) {
     float wr[D];
 #pragma unroll
-    for (int m = 0; m < D; ++m) wr[m] = termp[m];
+    for (int m = 0; m < D; ++m) wr[m] = terms[t * NP + m];
     const float tw = weights ? weights[t] : 1.0f;
 
     for (int s = 0; s < steps; ++s) {
@@ -176,7 +262,7 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
       const int rslot = (gs % a.RSB) * B;
       const int cslot = (gs % a.CRB) * B;
 
-      // ---- 1. modulation ---------------------------------------------------
+      // ---- 1. modulation -------------------------------------------------------
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
         if (i * NT < nmod && tid + i * NT < nmod) {
@@ -184,7 +270,7 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
           const bool in = m_xin[i] && y >= 0 && y < Hd;
           float fv[D];
 #pragma unroll
-          for (int m = 0; m < D; ++m) fv[m] = in ? fcur[i][m] - a.cen[m] : 0.0f;
+          for (int m = 0; m < D; ++m) fv[m] = fcur[i][m] - a.cen[m];
           float rho = 0.0f;
 #pragma unroll
           for (int m = 0; m < D; ++m) rho = fmaf(wr[m], fv[m], rho);
@@ -207,166 +293,138 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
           }
         }
       }
-      // prefetch f for the next step (wrapping into the next term)
+      load_f(s + 1 == steps ? 0 : s + 1);
+      __syncthreads();
+
+      // ---- 2. horizontal pass ----------------------------------------------------
       {
-        const int ns = (s + 1 == steps) ? 0 : s + 1;
-        load_step(ns, fcur);
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        hpass<RC>(s_stage + (p1_rr * NC + p1_ch) * SW + p1_xq * 4, tapr, s_taps, ntap4, acc);
+        *reinterpret_cast<float4*>(s_ring + (rslot + p1_rr) * RST + p1_ch * TW + p1_xq * 4) =
+            make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
       __syncthreads();
 
-      // ---- 2. horizontal pass ------------------------------------------------
-      // Sliding window of two 8-float blocks (ra | rb); each block is reloaded
-      // right after its last use so the LDS latency hides behind 32+ FMAs.
-      {
-        const float* src = s_stage + (p1_rr * NC + p1_ch) * SW + p1_xb * P1;
-        const int nblk = ntp / P1;                 // tap blocks; window needs nblk+1
-        float acc[P1];
-#pragma unroll
-        for (int p = 0; p < P1; ++p) acc[p] = 0.0f;
-        float ra[8], rb[8], ta[8], tb[8];
-        ld8(ra, src);
-        ld8(rb, src + 8);
-        int b = 0;
-        for (; b + 2 <= nblk; b += 2) {
-          ld8(ta, s_taps + b * 8);
-          ld8(tb, s_taps + b * 8 + 8);
-          fma_lo<P1>(acc, ta, ra);
-          ld8(ra, src + b * 8 + 16);                         // b + 2 <= nblk here
-          fma_hi<P1>(acc, ta, rb);
-          fma_lo<P1>(acc, tb, rb);
-          ld8(rb, src + min(b + 3, nblk) * 8);               // clamped: no branch
-          fma_hi<P1>(acc, tb, ra);
-        }
-        if (b < nblk) {
-          ld8(ta, s_taps + b * 8);
-          fma_lo<P1>(acc, ta, ra);
-          fma_hi<P1>(acc, ta, rb);
-        }
-        float* dst = s_ring + (rslot + p1_rr) * RST + (p1_k * NP + p1_m) * TW + p1_xb * P1;
-        *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        *reinterpret_cast<float4*>(dst + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
-      }
-      __syncthreads();
-
-      // ---- 3. vertical pass + demodulation -----------------------------------
+      // ---- 3. vertical pass, demodulation, accumulation -----------------------------
       if (s >= lag) {
-        const int ob = s - lag;                      // output block in the strip
-        const int base = ((gs - lag) % a.RSB) * B + p2_g * P2;
-        float a0[P2], a1[P2];
+        const int ob = s - lag;
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int rb = ((gs - lag) % a.RSB) * B + p2_g * 4;
+        vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rb, RS, tapr, s_taps, ntap4, acc);
+        const int cb = ((gs - lag) % a.CRB) * B + p2_g * 4 + R;
+        float tot[4];
 #pragma unroll
-        for (int p = 0; p < P2; ++p) a0[p] = a1[p] = 0.0f;
-        // column of this item in plane k = 0; plane k = 1 sits NP*TW further
-        const float* col = s_ring + p2_m * TW + p2_x;
-        const int nblk = ntp / P2;
-        // ping-pong 4-row blocks (xa | xb), both planes
-        float xa0[4], xa1[4], xb0[4], xb1[4], tq[8];
-        auto ldblk = [&](float (&v0)[4], float (&v1)[4], int blk) {
-          const float* r = col + wrap(base + blk * P2, RS) * RST;  // aligned block: no wrap inside
-#pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            v0[p] = r[p * RST];
-            v1[p] = r[p * RST + NP * TW];
-          }
-        };
-        ldblk(xa0, xa1, 0);
-        ldblk(xb0, xb1, 1);
-        int b = 0;
-        for (; b + 2 <= nblk; b += 2) {
-          ld8(tq, s_taps + b * 4);
-          fma_lo<P2>(a0, tq, xa0);
-          fma_lo<P2>(a1, tq, xa1);
-          ldblk(xa0, xa1, b + 2);                            // b + 2 <= nblk here
-          fma_hi<P2>(a0, tq, xb0);
-          fma_hi<P2>(a1, tq, xb1);
-          fma_lo<P2>(a0, tq + 4, xb0);
-          fma_lo<P2>(a1, tq + 4, xb1);
-          ldblk(xb0, xb1, min(b + 3, nblk));                 // clamped: no branch
-          fma_hi<P2>(a0, tq + 4, xa0);
-          fma_hi<P2>(a1, tq + 4, xa1);
+        for (int p = 0; p < 4; ++p) {
+          const float cs = s_cs[wrap(cb + p, CRS) * CST + p2_k * TW + p2_x];
+          const float q = cs * acc[p];
+          tot[p] = q + __shfl_xor(q, 16);
         }
-        if (b < nblk) {
-          ld4(tq, s_taps + b * 4);
-          fma_lo<P2>(a0, tq, xa0);
-          fma_lo<P2>(a1, tq, xa1);
-          fma_hi<P2>(a0, tq, xb0);
-          fma_hi<P2>(a1, tq, xb1);
-        }
-        // demodulate with cos/sin at the output pixels (input row yo + R)
-        const int cbase = ((gs - lag) % a.CRB) * B;
+        if (p2_k == 0 && p2_xin) {
+          const int yb = y0 + ob * B + p2_g * 4;
 #pragma unroll
-        for (int p = 0; p < P2; ++p) {
-          const int yo = ob * B + p2_g * P2 + p;       // output row within strip
-          const int crow = wrap(cbase + p2_g * P2 + p + R, CRS);
-          const float c = s_cs[crow * CST + p2_x];
-          const float sn = s_cs[crow * CST + TW + p2_x];
-          float* ac = s_acc + yo * AST + p2_m * TW + p2_x;
-          *ac = fmaf(tw * sn, a1[p], fmaf(tw * c, a0[p], *ac));
+          for (int p = 0; p < 4; ++p)
+            if (yb + p < Hd) accm[(size_t)(yb + p) * Wd] = fmaf(tw, tot[p], t > 0 ? accp[p] : 0.0f);
         }
       }
-    }
-  }
-  __syncthreads();
-
-  // ---- final division and store ---------------------------------------------
-  for (int i = tid; i < TH * TW; i += NT) {
-    const int yl = i / TW, xl = i - yl * TW;
-    const int y = y0 + yl, x = x0 + xl;
-    if (y < Hd && x < Wd) {
-      const float* ac = s_acc + yl * AST + xl;
-      const float Z = ac[D * TW];
-      float* o = a.out + ((size_t)y * Wd + x) * D;
-#pragma unroll
-      for (int m = 0; m < D; ++m) o[m] = ac[m * TW] / Z + a.cen[m];
-      if (a.num_out) {
-        float* nn = a.num_out + ((size_t)y * Wd + x) * D;
-#pragma unroll
-        for (int m = 0; m < D; ++m) nn[m] = fmaf(a.cen[m], Z, ac[m * TW]);
+      {
+        const bool last = s + 1 == steps;
+        load_acc(last ? t + 1 : t, last ? 0 : s + 1);
       }
-      if (a.z_out) a.z_out[(size_t)y * Wd + x] = Z;
     }
   }
 }
 
+// out = num / Z + c ; optional uncentred numerator and normaliser
+template <int D>
+__global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
+  const size_t plane = (size_t)a.H * a.W;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= plane) return;
+  const float Z = a.acc[(size_t)D * plane + i];
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    const float num = a.acc[(size_t)m * plane + i];
+    a.out[i * D + m] = num / Z + a.cen[m];
+    if (a.num_out) a.num_out[i * D + m] = fmaf(a.cen[m], Z, num);
+  }
+  if (a.z_out) a.z_out[i] = Z;
+}
+
 // ---------------------------------------------------------------------------
-// Host-side launch helpers for the fused kernel
+// Host-side launch helpers
 // ---------------------------------------------------------------------------
 
-size_t fused_lds_bytes(int d, int R, int TH) {
+size_t fused_lds_bytes(int d, int R) {
   const int NP = d + 1, NC = 2 * NP;
-  const int ntp = ntaps_padded(R);
-  const int SW = kTW + ntp + 4;
-  const int lag = (2 * R + kB - 1) / kB;
+  const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
+  const int taps_al = (ntap4 + 7) / 8 * 8;
+  const int lag = lag_steps(R);
   const int RS = (lag + 1) * kB, CRS = (lag + 2) * kB;
-  const size_t fl = (size_t)((ntp + 3) / 4 * 4) + (size_t)kB * NC * SW +
-                    (size_t)RS * 2 * NP * kTW + (size_t)CRS * 2 * kTW +
-                    (size_t)TH * NP * kTW;
+  const size_t fl = (size_t)taps_al + (size_t)kB * NC * stage_width(R) +
+                    (size_t)RS * NC * kTW + (size_t)CRS * 2 * kTW;
   return fl * sizeof(float);
 }
 
-template <int D>
-static hipError_t launch_d(const FusedArgs& a, int nblocks, size_t lds, hipStream_t st) {
-  auto kern = mcsf_fused_fp32<D>;
+template <int D, int RC>
+static hipError_t launch_dr(const FusedArgs& a, const float* terms, const float* weights,
+                            hipStream_t st) {
+  const size_t lds = fused_lds_bytes(D, a.R);
+  auto kern = mcsf_fused_fp32<D, RC>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(64 * (D + 1)), lds, st, a, a.terms, a.weights);
+  hipLaunchKernelGGL(kern, dim3(a.nsx * a.nsy), dim3(64 * (D + 1)), lds, st, a, terms, weights);
   return hipGetLastError();
 }
 
-hipError_t launch_fused_fp32(int d, const FusedArgs& a, hipStream_t st) {
-  const size_t lds = fused_lds_bytes(d, a.R, a.TH);
-  const int nblocks = a.nsx * a.nsy;
+// Radii with a fully unrolled specialisation (the workload radii and the
+// serving range); every other radius takes the runtime-R variant.
+template <int D>
+static hipError_t launch_d(const FusedArgs& a, const float* terms, const float* weights,
+                           hipStream_t st) {
+  switch (a.R) {
+    case 6: return launch_dr<D, 6>(a, terms, weights, st);
+    case 9: return launch_dr<D, 9>(a, terms, weights, st);
+    case 12: return launch_dr<D, 12>(a, terms, weights, st);
+    case 15: return launch_dr<D, 15>(a, terms, weights, st);
+    case 18: return launch_dr<D, 18>(a, terms, weights, st);
+    case 21: return launch_dr<D, 21>(a, terms, weights, st);
+    case 24: return launch_dr<D, 24>(a, terms, weights, st);
+    case 30: return launch_dr<D, 30>(a, terms, weights, st);
+    default: return launch_dr<D, -1>(a, terms, weights, st);
+  }
+}
+
+hipError_t launch_fused_fp32(int d, const FusedArgs& a, const float* terms, const float* weights,
+                             hipStream_t st) {
   switch (d) {
-    case 1: return launch_d<1>(a, nblocks, lds, st);
-    case 2: return launch_d<2>(a, nblocks, lds, st);
-    case 3: return launch_d<3>(a, nblocks, lds, st);
-    case 4: return launch_d<4>(a, nblocks, lds, st);
-    case 5: return launch_d<5>(a, nblocks, lds, st);
-    case 6: return launch_d<6>(a, nblocks, lds, st);
-    case 7: return launch_d<7>(a, nblocks, lds, st);
-    case 8: return launch_d<8>(a, nblocks, lds, st);
+    case 1: return launch_dr<1, -1>(a, terms, weights, st);
+    case 2: return launch_dr<2, -1>(a, terms, weights, st);
+    case 3: return launch_d<3>(a, terms, weights, st);
+    case 4: return launch_dr<4, -1>(a, terms, weights, st);
+    case 5: return launch_dr<5, -1>(a, terms, weights, st);
+    case 6: return launch_d<6>(a, terms, weights, st);
+    case 7: return launch_dr<7, -1>(a, terms, weights, st);
+    case 8: return launch_dr<8, -1>(a, terms, weights, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t st) {
+  const size_t plane = (size_t)a.H * a.W;
+  const dim3 grid((unsigned)((plane + 255) / 256));
+  switch (d) {
+    case 1: hipLaunchKernelGGL(mcsf_finalize<1>, grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(mcsf_finalize<2>, grid, dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(mcsf_finalize<3>, grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(mcsf_finalize<4>, grid, dim3(256), 0, st, a); break;
+    case 5: hipLaunchKernelGGL(mcsf_finalize<5>, grid, dim3(256), 0, st, a); break;
+    case 6: hipLaunchKernelGGL(mcsf_finalize<6>, grid, dim3(256), 0, st, a); break;
+    case 7: hipLaunchKernelGGL(mcsf_finalize<7>, grid, dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(mcsf_finalize<8>, grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace bfvec
