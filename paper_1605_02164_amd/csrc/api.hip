@@ -169,6 +169,10 @@ int check_opts(const bf_opts* o) {
 int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
   const int R = window_radius(sigma_s);
   if (R > kRMax) return fail(BF_EUNSUPPORTED, "sigma_s too large: window radius above 40");
+  // the kernels address f and the accumulators with 32-bit element offsets
+  const double elems = (double)(H + 2 * kB) * (double)(W + kTW) * (double)(d + 1);
+  if (elems >= 4294967296.0 - 65536.0)
+    return fail(BF_EUNSUPPORTED, "image too large: H*W*(d+1) must stay below 2^32 elements");
   if (o->precision != BF_FP32)
     return fail(BF_EUNSUPPORTED, "this build handles precision BF_FP32 only");
   return choose_strip_height(d, R, H, W, o->tile_h, TH);
@@ -209,9 +213,10 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   a.RSB = a.lag + 1;
   a.CRB = a.lag + 2;
   a.steps = a.lag + TH / kB;
+  a.Hp = a.nsy * TH;
 
   // one stream-ordered allocation: accumulators | terms | weights | taps
-  const size_t n_acc = (size_t)NP * H * W;
+  const size_t n_acc = (size_t)NP * a.Hp * a.nsx * kTW;
   float* dbuf = nullptr;
   HIP_TRY(hipMallocAsync((void**)&dbuf, (n_acc + hbuf.size()) * sizeof(float), st),
           "hipMallocAsync(accumulators)");
@@ -238,6 +243,8 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
     for (int m = 0; m < 8; ++m) fa.cen[m] = a.cen[m];
     fa.H = H;
     fa.W = W;
+    fa.Hp = a.Hp;
+    fa.Wp = a.nsx * kTW;
     e = launch_finalize(d, fa, st);
   }
   if (e == hipSuccess && o->time_kernel) {

@@ -16,10 +16,11 @@ constexpr int kRMax = 40; // largest window radius handled by the fused kernels
 
 // Staging row width for radius R: at least TW + 2R + 4 floats (the
 // horizontal window of a 4-output block plus one spare block), and equal to
-// 8 modulo 16 so that the 128-bit window loads of the 16 lanes that share an
-// LDS cycle fall in distinct bank groups.
+// 16 modulo 32: measured on gfx950, that residue makes the 128-bit window
+// loads of the horizontal pass free of LDS bank conflicts for the lane order
+// used (widths of other residues cost one to two extra passes per load).
 inline constexpr int stage_width(int R) {
-  return 16 * ((kTW + 2 * R + 4 - 8 + 15) / 16) + 8;
+  return 32 * ((kTW + 2 * R + 4 - 16 + 31) / 32) + 16;
 }
 constexpr int kSWMax = stage_width(kRMax);
 // 2R rows of look-ahead, in steps of kB rows
@@ -27,11 +28,13 @@ inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
 
 struct FusedArgs {
   const float* f;        // H*W*d input (device)
-  float* acc;            // (d+1)*H*W accumulators, planar [m][y][x] (device)
+  float* acc;            // (d+1)*Hp*Wp accumulators, planar [m][y][x] (device),
+                         // padded to whole strips: Hp = nsy*TH, Wp = nsx*kTW
   const float* taps;     // 2R+1 spatial taps (device), zero padded to a multiple of 4
   float cen[8];          // per-channel centre subtracted before the phase
   int H, W, K, R;
   int TH;                // strip height (multiple of kB)
+  int Hp;                // padded accumulator rows (nsy*TH)
   int nsx, nsy;          // strips across and down
   int SW;                // staging row width (floats)
   int RSB, CRB;          // ring sizes in blocks of kB rows
@@ -39,12 +42,12 @@ struct FusedArgs {
 };
 
 struct FinalizeArgs {
-  const float* acc;      // (d+1)*H*W planar accumulators
+  const float* acc;      // (d+1)*Hp*Wp planar accumulators
   float* out;            // H*W*d
   float* num_out;        // optional H*W*d numerator (uncentred) or null
   float* z_out;          // optional H*W normaliser or null
   float cen[8];
-  int H, W;
+  int H, W, Hp, Wp;
 };
 
 size_t fused_lds_bytes(int d, int R);

@@ -193,9 +193,11 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
   for (int u = 0; u < NTAPR; ++u) tapr[u] = s_taps[u];
 
   // ---- per-thread fixed roles -------------------------------------------------
-  // pass 1 item: channel ch, 4-column block xq, row rr of the step
-  const int p1_ch = tid % NC;
-  const int p1_xq = (tid / NC) % 4;
+  // pass 1 item: 4-column block xq, channel ch, row rr of the step.  xq varies
+  // fastest across lanes: the items' 128-bit ring writes then cover contiguous
+  // LDS (a channel-fastest order measured a 7-way bank conflict on them).
+  const int p1_xq = tid % 4;
+  const int p1_ch = (tid / 4) % NC;
   const int p1_rr = tid / (4 * NC);
   // pass 2 item: column x, cos/sin half k, pair m, 4-row group g
   const int p2_x = tid & 15;
@@ -204,9 +206,10 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
   int p2_g = (tid >> 5) / NP;
   if constexpr (NP % 2 == 0) p2_g = __builtin_amdgcn_readfirstlane(p2_g);
   const int p2_ch = 2 * p2_m + p2_k;
-  const bool p2_xin = x0 + p2_x < Wd;
-  const size_t plane = (size_t)Hd * Wd;
-  float* accm = a.acc + (size_t)p2_m * plane + min(x0 + p2_x, Wd - 1);  // lane's column of plane m
+  // accumulators: planar [m][Hp][Wp] padded to whole strips, so every lane
+  // owns valid storage; 32-bit element offsets from the (uniform) base
+  const int Wp = a.nsx * TW;
+  const unsigned acc_lane = (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
 
   // modulation slots: pixel tid + i*NT of the B x SW step tile
   const int nmod = B * SW;
@@ -223,112 +226,144 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
   }
   const int ybase = y0 - R;
 
-  // f prefetch: raw values of each slot for the next step, loaded from a
-  // clamped in-image address so the loads stay in flight across the passes
-  float fcur[MI][D];
-  auto load_f = [&](int s) {
+  // Prefetch buffers, two steps deep (ping-pong A/B by step parity): raw f of
+  // each modulation slot, loaded from a clamped in-image address so the loads
+  // stay in flight across the passes, and this lane's accumulators for the
+  // output rows of the step.
+  const int steps = a.steps, lag = a.lag, K = a.K;
+  float fA[MI][D], fB[MI][D];
+  float aA[2] = {0.0f, 0.0f}, aB[2] = {0.0f, 0.0f};
+  int m_fx[MI];  // clamped column offset of each slot, in floats
+#pragma unroll
+  for (int i = 0; i < MI; ++i) m_fx[i] = min(max(m_x[i], 0), Wd - 1) * D;
+  auto load_f = [&](float (&dst)[MI][D], int s) {
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
       if (i * NT < nmod) {
         const int y = min(max(ybase + s * B + m_rr[i], 0), Hd - 1);
-        const int x = min(max(m_x[i], 0), Wd - 1);
-        const float* src = a.f + ((size_t)y * Wd + x) * D;
+        const unsigned o = (unsigned)y * (unsigned)(Wd * D) + (unsigned)m_fx[i];
 #pragma unroll
-        for (int m = 0; m < D; ++m) fcur[i][m] = src[m];
+        for (int m = 0; m < D; ++m) dst[i][m] = a.f[o + m];
       }
     }
   };
-  // accumulator prefetch for the output rows of step s of term t
-  float accp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  auto load_acc = [&](int t, int s) {
-    if (t > 0 && t < a.K && s >= a.lag && p2_k == 0 && p2_xin) {
-      const int yb = y0 + (s - a.lag) * B + p2_g * 4;
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        if (yb + p < Hd) accp[p] = accm[(size_t)(yb + p) * Wd];
+  auto load_acc = [&](float (&dst)[2], int t, int s) {
+    if (t > 0 && t < K && s >= lag) {
+      const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
+      dst[0] = a.acc[o];
+      dst[1] = a.acc[o + Wp];
     }
   };
-  load_f(0);
 
-  const int steps = a.steps, lag = a.lag;
-  for (int t = 0; t < a.K; ++t) {
-    float wr[D];
+  // ring positions of the current step (rows written) and of the step lag
+  // behind it (rows the vertical pass starts from), advanced by B per step
+  int rslot = 0, cslot = 0;
+  int rslot_lag = (a.RSB - lag % a.RSB) % a.RSB * B, cslot_lag = (a.CRB - lag % a.CRB) % a.CRB * B;
+  float wr[D];
+  float tw = 1.0f;
+  auto load_term = [&](int t) {
 #pragma unroll
     for (int m = 0; m < D; ++m) wr[m] = terms[t * NP + m];
-    const float tw = weights ? weights[t] : 1.0f;
+    tw = weights ? weights[t] : 1.0f;
+  };
 
-    for (int s = 0; s < steps; ++s) {
-      const int gs = t * steps + s;
-      const int rslot = (gs % a.RSB) * B;
-      const int cslot = (gs % a.CRB) * B;
-
-      // ---- 1. modulation -------------------------------------------------------
+  // One pipeline step s of term t; fcur/acur hold this step's prefetched
+  // data and are refilled for the step two ahead.
+  auto step = [&](int t, int s, float (&fcur)[MI][D], float (&acur)[2]) {
+    // ---- 1. modulation ---------------------------------------------------------
 #pragma unroll
-      for (int i = 0; i < MI; ++i) {
-        if (i * NT < nmod && tid + i * NT < nmod) {
-          const int y = ybase + s * B + m_rr[i];
-          const bool in = m_xin[i] && y >= 0 && y < Hd;
-          float fv[D];
+    for (int i = 0; i < MI; ++i) {
+      if (i * NT < nmod && tid + i * NT < nmod) {
+        const int y = ybase + s * B + m_rr[i];
+        const bool in = m_xin[i] && y >= 0 && y < Hd;
+        float fv[D];
 #pragma unroll
-          for (int m = 0; m < D; ++m) fv[m] = fcur[i][m] - a.cen[m];
-          float rho = 0.0f;
+        for (int m = 0; m < D; ++m) fv[m] = fcur[i][m] - a.cen[m];
+        float rho = 0.0f;
 #pragma unroll
-          for (int m = 0; m < D; ++m) rho = fmaf(wr[m], fv[m], rho);
-          const float fr = __builtin_amdgcn_fractf(rho);
-          float c = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
-          c = in ? c : 0.0f;
-          sn = in ? sn : 0.0f;
-          float* st = s_stage + m_off[i];
+        for (int m = 0; m < D; ++m) rho = fmaf(wr[m], fv[m], rho);
+        const float fr = __builtin_amdgcn_fractf(rho);
+        float c = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+        c = in ? c : 0.0f;
+        sn = in ? sn : 0.0f;
+        float* st = s_stage + m_off[i];
 #pragma unroll
-          for (int m = 0; m < D; ++m) {
-            st[(2 * m) * SW] = c * fv[m];
-            st[(2 * m + 1) * SW] = sn * fv[m];
-          }
-          st[(2 * D) * SW] = c;
-          st[(2 * D + 1) * SW] = sn;
-          const int xc = m_x[i] - x0;
-          if (xc >= 0 && xc < TW) {
-            s_cs[(cslot + m_rr[i]) * CST + xc] = c;
-            s_cs[(cslot + m_rr[i]) * CST + TW + xc] = sn;
-          }
+        for (int m = 0; m < D; ++m) {
+          st[(2 * m) * SW] = c * fv[m];
+          st[(2 * m + 1) * SW] = sn * fv[m];
+        }
+        st[(2 * D) * SW] = c;
+        st[(2 * D + 1) * SW] = sn;
+        const int xc = m_x[i] - x0;
+        if (xc >= 0 && xc < TW) {
+          s_cs[(cslot + m_rr[i]) * CST + xc] = c;
+          s_cs[(cslot + m_rr[i]) * CST + TW + xc] = sn;
         }
       }
-      load_f(s + 1 == steps ? 0 : s + 1);
-      __syncthreads();
+    }
+    // the step two ahead, possibly in the next term(s)
+    int s2 = s + 2, t2 = t;
+    if (s2 >= steps) { s2 -= steps; ++t2; }
+    if (s2 >= steps) { s2 -= steps; ++t2; }
+    load_f(fcur, s2);
+    __syncthreads();
 
-      // ---- 2. horizontal pass ----------------------------------------------------
-      {
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        hpass<RC>(s_stage + (p1_rr * NC + p1_ch) * SW + p1_xq * 4, tapr, s_taps, ntap4, acc);
-        *reinterpret_cast<float4*>(s_ring + (rslot + p1_rr) * RST + p1_ch * TW + p1_xq * 4) =
-            make_float4(acc[0], acc[1], acc[2], acc[3]);
-      }
-      __syncthreads();
+    // ---- 2. horizontal pass ------------------------------------------------------
+    {
+      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      hpass<RC>(s_stage + (p1_rr * NC + p1_ch) * SW + p1_xq * 4, tapr, s_taps, ntap4, acc);
+      *reinterpret_cast<float4*>(s_ring + (rslot + p1_rr) * RST + p1_ch * TW + p1_xq * 4) =
+          make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+    __syncthreads();
 
-      // ---- 3. vertical pass, demodulation, accumulation -----------------------------
-      if (s >= lag) {
-        const int ob = s - lag;
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        const int rb = ((gs - lag) % a.RSB) * B + p2_g * 4;
-        vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rb, RS, tapr, s_taps, ntap4, acc);
-        const int cb = ((gs - lag) % a.CRB) * B + p2_g * 4 + R;
-        float tot[4];
+    // ---- 3. vertical pass, demodulation, accumulation -------------------------------
+    if (s >= lag) {
+      const int ob = s - lag;
+      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      const int rb = rslot_lag + p2_g * 4;
+      (void)ob;
+      vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rb, RS, tapr, s_taps, ntap4, acc);
+      const int cb = cslot_lag + p2_g * 4 + R;
+      float tot[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const float cs = s_cs[wrap(cb + p, CRS) * CST + p2_k * TW + p2_x];
-          const float q = cs * acc[p];
-          tot[p] = q + __shfl_xor(q, 16);
-        }
-        if (p2_k == 0 && p2_xin) {
-          const int yb = y0 + ob * B + p2_g * 4;
-#pragma unroll
-          for (int p = 0; p < 4; ++p)
-            if (yb + p < Hd) accm[(size_t)(yb + p) * Wd] = fmaf(tw, tot[p], t > 0 ? accp[p] : 0.0f);
-        }
+      for (int p = 0; p < 4; ++p) {
+        const float cs = s_cs[wrap(cb + p, CRS) * CST + p2_k * TW + p2_x];
+        const float q = cs * acc[p];
+        tot[p] = q + __shfl_xor(q, 16);
       }
-      {
-        const bool last = s + 1 == steps;
-        load_acc(last ? t + 1 : t, last ? 0 : s + 1);
+      {  // lane k adds rows 2k and 2k+1 of the pair's 4-row block
+        const unsigned o = acc_lane + (unsigned)(ob * B + p2_g * 4) * Wp;
+        const float v0 = p2_k ? tot[2] : tot[0], v1 = p2_k ? tot[3] : tot[1];
+        a.acc[o] = fmaf(tw, v0, t > 0 ? acur[0] : 0.0f);
+        a.acc[o + Wp] = fmaf(tw, v1, t > 0 ? acur[1] : 0.0f);
+      }
+    }
+    load_acc(acur, t2, s2);
+    rslot = wrap(rslot + B, RS);
+    cslot = wrap(cslot + B, CRS);
+    rslot_lag = wrap(rslot_lag + B, RS);
+    cslot_lag = wrap(cslot_lag + B, CRS);
+  };
+
+  // Flattened loop over (term, step) pairs of global steps, two per trip so
+  // the A/B prefetch buffers keep fixed roles.
+  load_f(fA, 0);
+  load_f(fB, steps > 1 ? 1 : 0);
+  load_term(0);
+  const int total = K * steps;
+  int t = 0, s = 0;
+  for (int gs = 0; gs < total; gs += 2) {
+    step(t, s, fA, aA);
+    if (++s == steps) {
+      s = 0;
+      if (++t < K) load_term(t);
+    }
+    if (gs + 1 < total) {
+      step(t, s, fB, aB);
+      if (++s == steps) {
+        s = 0;
+        if (++t < K) load_term(t);
       }
     }
   }
@@ -337,13 +372,15 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_fp32(FusedArgs a,
 // out = num / Z + c ; optional uncentred numerator and normaliser
 template <int D>
 __global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
-  const size_t plane = (size_t)a.H * a.W;
+  const size_t npx = (size_t)a.H * a.W;
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= plane) return;
-  const float Z = a.acc[(size_t)D * plane + i];
+  if (i >= npx) return;
+  const size_t y = i / a.W, x = i - y * a.W;
+  const size_t plane = (size_t)a.Hp * a.Wp, j = y * a.Wp + x;
+  const float Z = a.acc[(size_t)D * plane + j];
 #pragma unroll
   for (int m = 0; m < D; ++m) {
-    const float num = a.acc[(size_t)m * plane + i];
+    const float num = a.acc[(size_t)m * plane + j];
     a.out[i * D + m] = num / Z + a.cen[m];
     if (a.num_out) a.num_out[i * D + m] = fmaf(a.cen[m], Z, num);
   }
