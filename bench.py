@@ -33,7 +33,7 @@ def algorithmic_flops_per_pixel(d, R, K):
     return K * (4 * d + 8 * (d + 1) * (2 * R + 1) + 4 * (d + 1))
 
 
-def cpu_baseline(f, C, sigma_s, K, seed, N, crop=384, k_sample=32):
+def cpu_baseline(f, C, sigma_s, K, seed, N, crop=512, k_sample=64):
     """The oracle's separable MCSF (FP64 numpy, single thread) on a centred
     crop with the first k_sample of the same terms; rate scaled to K terms."""
     import numpy as np
