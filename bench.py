@@ -59,7 +59,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="voronoi4096_d3_s10_K256")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="precision of the headline value; the other modes are reported beside it")
+    ap.add_argument("--only", action="store_true", help="time only --precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the "
@@ -96,29 +98,51 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def step():
-        _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=out, precision=args.precision,
+    def step(prec, dst):
+        _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=dst, precision=prec,
                            stream=stream, time_kernel=True, return_opts=True)
         return o.N_used, o.kernel_ms
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        N, _ = step()
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    kms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        N, ms = step()
-        kms.append(ms)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = H * W * args.steps / dt / 1e6
-    kernel_ms = float(np.mean(kms))
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
-    achieved = flops / (kernel_ms * 1e-3) / 1e12
-    log(f"N={N} step {1e3 * dt / args.steps:.2f} ms, kernel {kernel_ms:.2f} ms, "
-        f"{achieved:.2f} TFLOP/s algorithmic")
+
+    def run(prec, dst):
+        for _ in range(args.warmup):
+            step(prec, dst)
+        torch.cuda.synchronize()
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            N, ms = step(prec, dst)
+            kms.append(ms)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kernel_ms = float(np.mean(kms))
+        rec = {"value": H * W * args.steps / dt / 1e6, "ms_per_step": 1e3 * dt / args.steps,
+               "kernel_ms": kernel_ms, "achieved_tflops": flops / (kernel_ms * 1e-3) / 1e12, "N": N}
+        log(f"{prec}: N={N} step {rec['ms_per_step']:.2f} ms, kernel {kernel_ms:.2f} ms, "
+            f"{rec['achieved_tflops']:.2f} TFLOP/s algorithmic, {rec['value']:.2f} Mpix/s")
+        return rec
+
+    precs = [args.precision] if args.only else [args.precision] + \
+        [q for q in ("fp32", "fp16", "bf16") if q != args.precision]
+    results, outs = {}, {}
+    for prec in precs:
+        outs[prec] = torch.empty_like(fg)
+        log(f"timing {prec}: {args.warmup} warmup + {args.steps} steps")
+        results[prec] = run(prec, outs[prec])
+    main_rec = results[args.precision]
+    N = main_rec["N"]
+    # deviation of the 16-bit modes from the FP32 output (fraction of each
+    # channel's range), from the same run's outputs
+    if "fp32" in outs:
+        span = (fg.reshape(-1, d).amax(0) - fg.reshape(-1, d).amin(0)).clamp_min(1e-30)
+        for prec in results:
+            if prec != "fp32":
+                diff = (outs[prec] - outs["fp32"]).abs().reshape(-1, d) / span
+                results[prec]["max_dev_vs_fp32"] = float(diff.max())
+                results[prec]["mean_dev_vs_fp32"] = float(diff.mean())
+    value, kernel_ms, achieved = main_rec["value"], main_rec["kernel_ms"], main_rec["achieved_tflops"]
+    dt = main_rec["ms_per_step"] * args.steps / 1e3
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -139,13 +163,14 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp16": "f16 storage, f32 accumulate",
                   "bf16": "bf16 storage, f32 accumulate"}[args.precision],
+        "modes": results,
         "data": "synthetic",
         "config": {"workload": args.workload, "H": H, "W": W, "d": d, "sigma_s": sigma_s,
                    "window": 2 * R + 1, "K": K, "N": N, "C": "0.08^2 I" if d == 3 else "SPD",
                    "precision": args.precision},
         "roofline": {
             "bound": "alu",
-            "kernel": f"mcsf_fused_fp32<{d}>",
+            "kernel": f"mcsf_fused<{d}, {R}, {args.precision}>",
             "achieved": achieved,
             "peak": PEAK_FP32_VALU,
             "unit": "TFLOP/s",

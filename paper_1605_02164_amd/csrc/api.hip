@@ -129,15 +129,19 @@ int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStr
 // halo).
 // ---------------------------------------------------------------------------
 
-int choose_strip_height(int d, int R, int H, int W, int requested, int* TH) {
-  if (fused_lds_bytes(d, R) > kLdsLimit)
+int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH) {
+  if (fused_lds_bytes(d, R, prec) > kLdsLimit)
     return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
   if (requested > 0) {
     *TH = (requested + kB - 1) / kB * kB;
     return BF_OK;
   }
   const int nsx = (W + kTW - 1) / kTW;
-  const int slots = 2 * 256;                 // resident workgroups on the GPU
+  // resident workgroups on the GPU
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int slots = fused_blocks_per_cu(d, R, prec) * std::max(ncu, 1);
   const int halo = lag_steps(R) * kB;
   long best = -1;
   int best_th = kB;
@@ -173,9 +177,7 @@ int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
   const double elems = (double)(H + 2 * kB) * (double)(W + kTW) * (double)(d + 1);
   if (elems >= 4294967296.0 - 65536.0)
     return fail(BF_EUNSUPPORTED, "image too large: H*W*(d+1) must stay below 2^32 elements");
-  if (o->precision != BF_FP32)
-    return fail(BF_EUNSUPPORTED, "this build handles precision BF_FP32 only");
-  return choose_strip_height(d, R, H, W, o->tile_h, TH);
+  return choose_strip_height(d, R, o->precision, H, W, o->tile_h, TH);
 }
 
 // Launch the fused filter for a host FP64 term table (radians per unit).
@@ -208,7 +210,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   a.TH = TH;
   a.nsx = (W + kTW - 1) / kTW;
   a.nsy = (H + TH - 1) / TH;
-  a.SW = stage_width(R);
+  a.SW = o->precision == BF_FP32 ? stage_width(R) : stage_width16(R);
   a.lag = lag_steps(R);
   a.RSB = a.lag + 1;
   a.CRB = a.lag + 2;
@@ -232,7 +234,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     if (e == hipSuccess) e = hipEventRecord(ev0, st);
   }
-  if (e == hipSuccess) e = launch_fused_fp32(d, a, dterms, dweights, st);
+  if (e == hipSuccess) e = launch_fused(d, o->precision, a, dterms, dweights, st);
   if (e == hipSuccess && o->time_kernel) e = hipEventRecord(ev1, st);
   if (e == hipSuccess) {
     FinalizeArgs fa{};

@@ -22,6 +22,13 @@ constexpr int kRMax = 40; // largest window radius handled by the fused kernels
 inline constexpr int stage_width(int R) {
   return 32 * ((kTW + 2 * R + 4 - 16 + 31) / 32) + 16;
 }
+// Same for 16-bit storage (elements, always even): at least TW + 2R + 4, with
+// the row width in dwords not a multiple of 16 -- measured on gfx950, 64-bit
+// window loads then conflict 2-way, against 4- to 8-way for multiples of 16.
+inline constexpr int stage_width16(int R) {
+  const int dw = (kTW + 2 * R + 4 + 3) / 4 * 2;   // dwords, even (64-bit aligned rows)
+  return 2 * (dw % 16 == 0 ? dw + 2 : dw);
+}
 constexpr int kSWMax = stage_width(kRMax);
 // 2R rows of look-ahead, in steps of kB rows
 inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
@@ -50,9 +57,12 @@ struct FinalizeArgs {
   int H, W, Hp, Wp;
 };
 
-size_t fused_lds_bytes(int d, int R);
-hipError_t launch_fused_fp32(int d, const FusedArgs& a, const float* terms,
-                             const float* weights, hipStream_t st);
+// prec: 0 = FP32 channels, 1 = FP16 storage, 2 = BF16 storage (FP32 accumulation)
+size_t fused_lds_bytes(int d, int R, int prec);
+// resident workgroups per compute unit for this kernel instance (device query)
+int fused_blocks_per_cu(int d, int R, int prec);
+hipError_t launch_fused(int d, int prec, const FusedArgs& a, const float* terms,
+                        const float* weights, hipStream_t st);
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t st);
 
 }  // namespace bfvec

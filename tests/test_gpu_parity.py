@@ -266,3 +266,67 @@ def test_direct_filter_matches_exact_oracle():
     out = host(P.bf_direct(cuda(f), 3.0, C))
     ref, _ = O.direct_exact(f.astype(np.float64), 3.0, C)
     assert np.all(rel_err_per_channel(out, ref, f) <= 1e-5)
+
+
+# --- 16-bit storage (FP16 / BF16 channels and ring rows, FP32 accumulation) ---------
+#
+# These modes are measured, not held to the FP32 bound: the tests print the
+# max and mean error against the FP64 oracle (fraction of each channel's range)
+# and gate at a sanity bound well above the observed error, which a wrong
+# index, tap or pair order would exceed by orders of magnitude.  As for FP32,
+# rounding is amplified by 1/z where the normaliser is small (z = Z / (K sum
+# omega)), so the gate applies to error * min(1, z / 0.1).
+
+LP_BOUND = {"fp16": 3e-3, "bf16": 3e-2}
+
+
+def lp_errors(got, ref, f, z):
+    ok = z >= ZMIN
+    f2 = np.asarray(f, np.float64).reshape(-1, f.shape[-1])
+    span = f2.max(0) - f2.min(0)
+    span[span == 0] = 1
+    d = np.abs(np.asarray(got, np.float64)[ok] - np.asarray(ref, np.float64)[ok]).reshape(-1, f.shape[-1]) / span
+    scaled = d * np.minimum(1.0, z[ok] / 0.1)[:, None]
+    return d.max(), d.mean(), scaled.max()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_low_precision_voronoi128_full_image(prec):
+    say(f"case {prec} voronoi128_d3_s2_K64 full image")
+    f, C, p = workload("voronoi128_d3_s2_K64")
+    got, N = P.bf_vec_ex(cuda(f), p["sigma_s"], C, p["K"], p["term_seed"], precision=prec)
+    _, w = oracle_terms(f.astype(np.float64), C, p["K"], p["term_seed"])
+    ref, _, Z = O.mcsf_separable(f.astype(np.float64), p["sigma_s"], w)
+    mx, mean, sc = lp_errors(host(got), ref, f, Z / (p["K"] * O.spatial_taps(p["sigma_s"]).sum() ** 2))
+    say(f"  {prec}: max err {mx:.3e} mean err {mean:.3e} (fraction of range)")
+    assert sc <= LP_BOUND[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_low_precision_voronoi4096_sampled(prec):
+    say(f"case {prec} voronoi4096_d3_s10_K256 full size, sampled pixels")
+    f, C, p = workload("voronoi4096_d3_s10_K256")
+    pix = sample_pixels(p["H"], p["W"], 32, 5, R=O.window_radius(p["sigma_s"]))
+    got, N = P.bf_vec_ex(cuda(f), p["sigma_s"], C, p["K"], p["term_seed"], precision=prec)
+    f64 = f.astype(np.float64)
+    _, w = oracle_terms(f64, C, p["K"], p["term_seed"])
+    ref, Z = O.direct_sampled(f64, p["sigma_s"], w, pixels=pix)
+    g = host(got)[pix[:, 0], pix[:, 1]]
+    mx, mean, sc = lp_errors(g, ref, f, Z / O.spatial_taps(p["sigma_s"]).sum() ** 2)
+    say(f"  {prec}: max err {mx:.3e} mean err {mean:.3e} (fraction of range)")
+    assert sc <= LP_BOUND[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("H,W,d,sigma,K", [(37, 29, 3, 1.5, 6), (20, 45, 6, 4.0, 5),
+                                           (33, 17, 2, 0.0, 3), (64, 48, 3, 13.0, 2)])
+def test_low_precision_edge_shapes(prec, H, W, d, sigma, K):
+    say(f"case {prec} edge H={H} W={W} d={d} sigma_s={sigma} K={K}")
+    f = voronoi_image(H, W, d, 3, 0.0, 1.0, 0.02, 17 + H + W + d)
+    C = np.eye(d) * 0.15 ** 2 if d % 2 else random_spd(d, -2.0, -1.0, d)
+    got, N = P.bf_vec_ex(cuda(f), sigma, C, K, 7, precision=prec)
+    _, w = oracle_terms(f.astype(np.float64), C, K, 7)
+    ref, _, Z = O.mcsf_separable(f.astype(np.float64), sigma, w)
+    mx, mean, sc = lp_errors(host(got), ref, f, Z / (K * O.spatial_taps(sigma).sum() ** 2))
+    say(f"  {prec}: max err {mx:.3e} mean err {mean:.3e} conditioning-scaled {sc:.3e}")
+    assert sc <= LP_BOUND[prec]
