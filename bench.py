@@ -5,7 +5,10 @@ A step is one whole call of the filter (bf_vec_ex: min/max reduction, order
 rule, whitening, term draws, term upload, fused kernel) over the
 4096x4096x3 sigma_s=10 K=256 workload, input resident in HBM.  Prints one
 JSON line with Mpix/s, the fused kernel's roofline position (HIP events around
-each launch) and the FP64 oracle's rate on the host as a CPU baseline.
+each launch), the FP64 oracle's rate on the host as a CPU baseline, and the
+serving run: a stream of mixed requests through the continuous-batching
+server, first all at once (sustained capacity), then as Poisson arrivals at a
+fraction of that capacity (p50/p99 latency).
 """
 
 import argparse
@@ -53,6 +56,114 @@ def cpu_baseline(f, C, sigma_s, K, seed, N, crop=512, k_sample=64):
                       f"(rate scaled to {K} terms), separable FP64 oracle, {dt:.1f} s"}
 
 
+def serving_run(args, P, torch, log_fn):
+    """Serving workload: requests with square sides log-uniform in
+    [256, 2048], d in {3, 6}, sigma_s in {2..8}, C = sigma_r^2 I with sigma_r
+    ~ U[0.05, 0.2], K in {64, 128, 256}, FP16 storage.  Images are crops (at
+    request-seeded offsets, row pitch 2048) of two resident 2048^2 images:
+    Voronoi colour (d = 3) and colour plus correlated channels (d = 6)."""
+    import numpy as np
+    from synth import serving_requests, voronoi_image, feature_image
+    dev = torch.device("cuda:0")
+    n = args.serve_requests
+    log_fn("serving: generating the 2048^2 image pools")
+    pool = {3: torch.from_numpy(voronoi_image(2048, 2048, 3, 64, 0.0, 1.0, 0.02, seed=3003)).to(dev),
+            6: torch.from_numpy(feature_image(2048, 2048, 64, seed=3004, smooth_sigma=32.0)).to(dev)}
+    reqs = serving_requests(n, seed=5, rate_hz=1.0)
+    crops, total_px, outs = [], 0, []
+    for q in reqs:
+        rng = np.random.Generator(np.random.PCG64(q["image_seed"]))
+        s = q["H"]
+        oy, ox = (int(v) for v in rng.integers(0, 2048 - s + 1, size=2))
+        crops.append(pool[q["d"]][oy:oy + s, ox:ox + s])
+        total_px += s * s
+    flat = torch.empty(sum(q["H"] * q["W"] * q["d"] for q in reqs), dtype=torch.float32, device=dev)
+    o = 0
+    for q in reqs:
+        m = q["H"] * q["W"] * q["d"]
+        outs.append(flat[o:o + m].view(q["H"], q["W"], q["d"]))
+        o += m
+    torch.cuda.synchronize()
+    srv = P.Server(arena_bytes=args.serve_arena_gib << 30, max_active=args.serve_max_active,
+                   quantum_us=args.serve_quantum_us)
+
+    def submit_all(arrivals):
+        ts = []
+        for q, f, out, a in zip(reqs, crops, outs, arrivals):
+            C = (q["sigma_r"] ** 2) * np.eye(q["d"])
+            t, _ = srv.submit(f, q["sigma_s"], C, q["K"], seed=q["term_seed"], out=out,
+                              precision="fp16", arrival=a)
+            ts.append(t)
+        return ts
+
+    def collect(ts):
+        sts = [srv.poll(t) for t in ts]
+        bad = [s for s in sts if s["state"] != "done"]
+        if bad:
+            raise RuntimeError(f"serving: {len(bad)} requests did not finish: {bad[0]}")
+        for t in ts:
+            srv.forget(t)
+        return sts
+
+    # warm-up: one small request of every kernel instance in the stream
+    seen = {}
+    for i, q in enumerate(reqs):
+        seen.setdefault((q["d"], q["sigma_s"]), i)
+    warm = []
+    for (d, sig), i in seen.items():
+        C = (reqs[i]["sigma_r"] ** 2) * np.eye(d)
+        t, _ = srv.submit(pool[d][:96, :96], sig, C, 8, seed=1)
+        warm.append(t)
+    srv.drain(600.0)
+    collect(warm)
+
+    # 1. capacity: everything arrives at once
+    log_fn(f"serving: {n} requests at once")
+    t0 = srv.clock() + 0.5
+    ts = submit_all([t0] * n)
+    srv.drain(1200.0)
+    sts = collect(ts)
+    makespan = max(s["done"] for s in sts) - t0
+    capacity = n / makespan
+    sat = {"makespan_s": makespan, "capacity_rps": capacity, "mpix_s": total_px / makespan / 1e6,
+           "p50_ms": 1e3 * float(np.percentile([s["done"] - s["arrival"] for s in sts], 50))}
+    log_fn(f"serving: capacity {capacity:.1f} req/s, {sat['mpix_s']:.1f} Mpix/s")
+
+    # 2. latency: Poisson arrivals at args.serve_load x capacity
+    rate = args.serve_load * capacity
+    arr = [q["arrival"] / rate for q in reqs]   # the generator's unit-rate arrival times
+    log_fn(f"serving: {n} Poisson arrivals at {rate:.1f} req/s")
+    t0 = srv.clock() + 0.5
+    ts = submit_all([t0 + a for a in arr])
+    srv.drain(1200.0)
+    sts = collect(ts)
+    lat = np.array([s["done"] - s["arrival"] for s in sts]) * 1e3
+    span = max(s["done"] for s in sts) - t0
+    stats = srv.stats()
+    srv.close()
+    # spot check: a few requests equal the same filter run alone, bit for bit
+    same = True
+    for i in (0, n // 2, n - 1):
+        q = reqs[i]
+        ref, _ = P.bf_vec_ex(crops[i].contiguous(), q["sigma_s"], (q["sigma_r"] ** 2) * np.eye(q["d"]),
+                             q["K"], seed=q["term_seed"], precision="fp16")
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(ref, outs[i]))
+    rec = {
+        "requests": n, "precision": "fp16", "load": args.serve_load, "rate_rps": rate,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
+        "mpix_s": total_px / span / 1e6, "total_mpix": total_px / 1e6,
+        "saturated": sat, "quantum_us": args.serve_quantum_us,
+        "max_active": args.serve_max_active, "rounds": stats["rounds"],
+        "launches": stats["launches"], "arena_peak_gib": stats["arena_peak"] / 2**30,
+        "spot_check_bitwise_equal_alone": same,
+    }
+    log_fn(f"serving: p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms, "
+           f"{rec['mpix_s']:.1f} Mpix/s")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +174,13 @@ def main():
                     help="precision of the headline value; the other modes are reported beside it")
     ap.add_argument("--only", action="store_true", help="time only --precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the measured capacity")
+    ap.add_argument("--serve-quantum-us", type=float, default=2000.0)
+    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-arena-gib", type=int, default=16)
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters against known traffic) and exit")
@@ -144,6 +262,10 @@ def main():
     value, kernel_ms, achieved = main_rec["value"], main_rec["kernel_ms"], main_rec["achieved_tflops"]
     dt = main_rec["ms_per_step"] * args.steps / 1e3
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_run(args, P, torch, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
@@ -181,6 +303,7 @@ def main():
             "kernel_ms": kernel_ms,
         },
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

@@ -28,8 +28,10 @@
  *     return BF_EDEVICE.
  *   - The library allocates only small per-call device buffers (term table,
  *     taps, reduction partials) in stream order; the caller owns images.
- *   - Limits: 1 <= H, W <= 65536; 1 <= d <= 8; 0 <= sigma_s <= 32 (R <= 96);
- *     1 <= K <= 65536; 1 <= N <= 65536.
+ *   - Limits: 1 <= H, W <= 65536; 1 <= d <= 8; 1 <= K <= 65536;
+ *     1 <= N <= 65536; the fused filter takes window radii R <= 40
+ *     (sigma_s <= 13.33) and images with H*W*(d+1) below 2^32 elements
+ *     (BF_EUNSUPPORTED otherwise); bf_direct takes R <= 96.
  */
 #ifndef BFVEC_H
 #define BFVEC_H
@@ -47,7 +49,8 @@ enum {
   BF_ENOMEM = 3,        /* device or host allocation failed                */
   BF_EDEVICE = 4,       /* HIP runtime error                               */
   BF_EUNSUPPORTED = 5,  /* option not supported for these sizes            */
-  BF_EBUSY = 6          /* serving queue full                              */
+  BF_EBUSY = 6,         /* serving queue full                              */
+  BF_ETIMEDOUT = 7      /* a wait ended before the request finished        */
 };
 
 /* Storage type of the modulated channels and of the horizontal-pass
@@ -134,6 +137,133 @@ int bf_minmax(const float* f, int H, int W, int d, float* lo, float* hi,
  * Same layout, window and boundary rules as bf_vec.  Synchronous. */
 int bf_direct(const float* f, int H, int W, int d, double sigma_s,
               const double* C, float* out);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many filter requests on one GPU.
+ *
+ * A server owns a device arena (accumulators, term tables, reduction
+ * partials), a few HIP streams of default priority and one scheduler thread.
+ * Requests are admitted in arrival order while their device footprint fits
+ * the arena and fewer than max_active are admitted.  Each scheduling round
+ * gives every admitted request the next chunk of its terms -- about
+ * quantum_us of modelled device time, so a request smaller than that
+ * finishes in its first round while a large one advances a quantum per round
+ * -- and packs the chunks of requests that share a kernel instance (d, window
+ * radius, precision) into one launch of the batched kernel.  Instances map to
+ * streams, so different instances run concurrently.  Rounds are queued at
+ * most `depth` ahead of the device.  A result is bit-identical to bf_vec_ex
+ * with the same arguments: chunking only splits Algorithm 1's term loop,
+ * whose accumulators sit in device memory between terms in both paths.
+ *
+ * Threading: every bf_server_* call is thread-safe; the scheduler runs on its
+ * own thread.  The server binds to the HIP device current at creation.
+ * ---------------------------------------------------------------------- */
+typedef struct bf_server bf_server;   /* opaque */
+
+typedef struct bf_server_config {
+  uint64_t arena_bytes; /* device arena; 0 = 8 GiB                                */
+  int max_active;       /* admitted requests at once; 0 = 64                       */
+  int max_queued;       /* submitted, not yet admitted; 0 = unlimited, else submit
+                           returns BF_EBUSY beyond it                              */
+  int streams;          /* HIP streams for the rounds, 1..16; 0 = 4               */
+  int depth;            /* rounds queued on the device at once, >= 1; 0 = 2        */
+  double quantum_us;    /* modelled device time per request per round; 0 = 2000   */
+  int reserved[8];
+} bf_server_config;
+
+typedef struct bf_request {
+  const float* f;       /* DEVICE image, H x W x d floats; pixel (y, x) starts at
+                           f + (y*pitch + x)*d.  Must hold its final contents at
+                           submit and stay unchanged until the request ends.      */
+  float* out;           /* DEVICE output, H x W x d contiguous; written when the
+                           request ends; must not overlap f                        */
+  int H, W, d;
+  int pitch;            /* pixels per row of f, >= W; 0 = W                       */
+  double sigma_s;
+  const double* C;      /* HOST d x d covariance, copied at submit                */
+  int K;                /* Monte Carlo terms                                      */
+  int N;                /* raised-cosine order; 0 = automatic rule                */
+  uint64_t seed;        /* term draws, as in bf_vec_ex                            */
+  int precision;        /* BF_FP32, BF_FP16, BF_BF16                              */
+  int center;           /* as bf_opts.center                                      */
+  double arrival;       /* server clock (s, see bf_server_clock) at which the
+                           request arrives; <= 0: at submit.  Latency is measured
+                           from it; a request is not admitted before it.          */
+  int reserved[4];
+} bf_request;
+
+enum {
+  BF_REQ_QUEUED = 0,    /* submitted, not admitted                               */
+  BF_REQ_PREPARING = 1, /* admitted: min/max reduction and term table in flight  */
+  BF_REQ_RUNNING = 2,   /* in the rounds                                          */
+  BF_REQ_DONE = 3,      /* out is complete                                        */
+  BF_REQ_FAILED = 4,    /* see error / message                                    */
+  BF_REQ_CANCELLED = 5  /* never admitted: server destroyed first                 */
+};
+
+typedef struct bf_request_status {
+  int state;            /* BF_REQ_*                                               */
+  int error;            /* BF_* code when failed                                  */
+  int N_used;           /* order used (once the term table is built)              */
+  int chunks;           /* rounds that advanced this request                      */
+  double arrival;       /* server clock, s                                        */
+  double admitted;      /* 0 until admitted                                       */
+  double started;       /* first chunk queued; 0 before                           */
+  double done;          /* completion observed by the scheduler; 0 before         */
+  char message[128];    /* failure message, "" otherwise                          */
+} bf_request_status;
+
+typedef struct bf_server_stats {
+  uint64_t submitted, completed, failed;
+  uint64_t rounds;      /* scheduling rounds queued                               */
+  uint64_t launches;    /* batched kernel launches                                */
+  uint64_t workgroups;  /* workgroups over all launches                           */
+  uint64_t arena_bytes, arena_peak;
+  int admitted;         /* requests admitted now                                  */
+  int queued;           /* requests waiting for admission now                     */
+  int reserved[6];
+} bf_server_stats;
+
+/* Fill *cfg with the defaults (all zero fields mean "default"). */
+void bf_server_config_init(bf_server_config* cfg);
+/* Fill *req with defaults: pitch 0, N 0 (auto), BF_FP16, centring on,
+ * arrival 0 (at submit); pointers null. */
+void bf_request_init(bf_request* req);
+
+/* Create a server on the current device (cfg may be NULL for defaults).
+ * Allocates the arena and starts the scheduler thread.  BF_ENOMEM if the
+ * arena cannot be allocated. */
+int bf_server_create(const bf_server_config* cfg, bf_server** srv);
+
+/* Queue a request.  Arguments are validated as in bf_vec_ex before anything
+ * is queued (BF_EINVAL, BF_ENOTSPD, BF_EUNSUPPORTED); BF_ENOMEM if its
+ * footprint exceeds the whole arena, BF_EBUSY past max_queued.  *ticket names
+ * it in later calls. */
+int bf_server_submit(bf_server* srv, const bf_request* req, uint64_t* ticket);
+
+/* Current status of a request (BF_EINVAL for an unknown ticket). */
+int bf_server_poll(bf_server* srv, uint64_t ticket, bf_request_status* st);
+
+/* Wait until the request is done, failed or cancelled, at most timeout_s
+ * seconds (< 0: no limit).  BF_ETIMEDOUT if still in flight; st (optional)
+ * receives the status either way. */
+int bf_server_wait(bf_server* srv, uint64_t ticket, double timeout_s, bf_request_status* st);
+
+/* Wait until every submitted request has ended (timeout as bf_server_wait). */
+int bf_server_drain(bf_server* srv, double timeout_s);
+
+/* Drop the record of an ended request (BF_EBUSY if it has not ended). */
+int bf_server_forget(bf_server* srv, uint64_t ticket);
+
+/* Counters since creation. */
+int bf_server_get_stats(bf_server* srv, bf_server_stats* s);
+
+/* Seconds since the server was created (steady clock). */
+double bf_server_clock(const bf_server* srv);
+
+/* Cancel requests not yet admitted, let admitted ones finish, stop the
+ * scheduler and free the server's device and host memory. */
+int bf_server_destroy(bf_server* srv);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* bf_last_error(void);

@@ -14,7 +14,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbfvec.so")
 
-BF_OK, BF_EINVAL, BF_ENOTSPD, BF_ENOMEM, BF_EDEVICE, BF_EUNSUPPORTED, BF_EBUSY = range(7)
+BF_OK, BF_EINVAL, BF_ENOTSPD, BF_ENOMEM, BF_EDEVICE, BF_EUNSUPPORTED, BF_EBUSY, \
+    BF_ETIMEDOUT = range(8)
+(BF_REQ_QUEUED, BF_REQ_PREPARING, BF_REQ_RUNNING, BF_REQ_DONE, BF_REQ_FAILED,
+ BF_REQ_CANCELLED) = range(6)
+REQ_STATES = {BF_REQ_QUEUED: "queued", BF_REQ_PREPARING: "preparing", BF_REQ_RUNNING: "running",
+              BF_REQ_DONE: "done", BF_REQ_FAILED: "failed", BF_REQ_CANCELLED: "cancelled"}
 BF_FP32, BF_FP16, BF_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
 
@@ -23,6 +28,9 @@ EXPORTS = [
     "bf_opts_init", "bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten",
     "bf_sample_terms", "bf_choose_N", "bf_minmax", "bf_direct",
     "bf_last_error", "bf_version",
+    "bf_server_config_init", "bf_request_init", "bf_server_create", "bf_server_submit",
+    "bf_server_poll", "bf_server_wait", "bf_server_drain", "bf_server_forget",
+    "bf_server_get_stats", "bf_server_clock", "bf_server_destroy",
 ]
 
 
@@ -47,6 +55,68 @@ class bf_opts(ctypes.Structure):
         ("time_kernel", ctypes.c_int),
         ("kernel_ms", ctypes.c_float),
         ("reserved", ctypes.c_int * 5),
+    ]
+
+
+class bf_server_config(ctypes.Structure):
+    _fields_ = [
+        ("arena_bytes", ctypes.c_uint64),
+        ("max_active", ctypes.c_int),
+        ("max_queued", ctypes.c_int),
+        ("streams", ctypes.c_int),
+        ("depth", ctypes.c_int),
+        ("quantum_us", ctypes.c_double),
+        ("reserved", ctypes.c_int * 8),
+    ]
+
+
+class bf_request(ctypes.Structure):
+    _fields_ = [
+        ("f", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("H", ctypes.c_int),
+        ("W", ctypes.c_int),
+        ("d", ctypes.c_int),
+        ("pitch", ctypes.c_int),
+        ("sigma_s", ctypes.c_double),
+        ("C", ctypes.c_void_p),
+        ("K", ctypes.c_int),
+        ("N", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int),
+        ("center", ctypes.c_int),
+        ("arrival", ctypes.c_double),
+        ("reserved", ctypes.c_int * 4),
+    ]
+
+
+class bf_request_status(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int),
+        ("error", ctypes.c_int),
+        ("N_used", ctypes.c_int),
+        ("chunks", ctypes.c_int),
+        ("arrival", ctypes.c_double),
+        ("admitted", ctypes.c_double),
+        ("started", ctypes.c_double),
+        ("done", ctypes.c_double),
+        ("message", ctypes.c_char * 128),
+    ]
+
+
+class bf_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64),
+        ("rounds", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64),
+        ("workgroups", ctypes.c_uint64),
+        ("arena_bytes", ctypes.c_uint64),
+        ("arena_peak", ctypes.c_uint64),
+        ("admitted", ctypes.c_int),
+        ("queued", ctypes.c_int),
+        ("reserved", ctypes.c_int * 6),
     ]
 
 
@@ -76,8 +146,24 @@ def lib():
     L.bf_last_error.argtypes = []
     L.bf_last_error.restype = ctypes.c_char_p
     L.bf_version.argtypes = []
+    L.bf_server_config_init.argtypes = [ctypes.POINTER(bf_server_config)]
+    L.bf_server_config_init.restype = None
+    L.bf_request_init.argtypes = [ctypes.POINTER(bf_request)]
+    L.bf_request_init.restype = None
+    L.bf_server_create.argtypes = [ctypes.POINTER(bf_server_config), ctypes.POINTER(P)]
+    L.bf_server_submit.argtypes = [P, ctypes.POINTER(bf_request), ctypes.POINTER(U64)]
+    L.bf_server_poll.argtypes = [P, U64, ctypes.POINTER(bf_request_status)]
+    L.bf_server_wait.argtypes = [P, U64, D, ctypes.POINTER(bf_request_status)]
+    L.bf_server_drain.argtypes = [P, D]
+    L.bf_server_forget.argtypes = [P, U64]
+    L.bf_server_get_stats.argtypes = [P, ctypes.POINTER(bf_server_stats)]
+    L.bf_server_clock.argtypes = [P]
+    L.bf_server_clock.restype = D
+    L.bf_server_destroy.argtypes = [P]
     for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_sample_terms",
-                 "bf_choose_N", "bf_minmax", "bf_direct", "bf_version"):
+                 "bf_choose_N", "bf_minmax", "bf_direct", "bf_version", "bf_server_create",
+                 "bf_server_submit", "bf_server_poll", "bf_server_wait", "bf_server_drain",
+                 "bf_server_forget", "bf_server_get_stats", "bf_server_destroy"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -231,3 +317,118 @@ def bf_direct(f, sigma_s, C, out=None):
 
 def version():
     return lib().bf_version()
+
+
+def _status_dict(st):
+    return {"state": REQ_STATES.get(st.state, st.state), "error": st.error, "N_used": st.N_used,
+            "chunks": st.chunks, "arrival": st.arrival, "admitted": st.admitted,
+            "started": st.started, "done": st.done, "message": st.message.decode()}
+
+
+def _image_view(f):
+    """(pointer, H, W, d, pitch) of an (H, W, d) float32 CUDA tensor whose
+    rows may be strided (e.g. a crop of a larger image)."""
+    import torch
+    if not (f.is_cuda and f.dtype == torch.float32 and f.dim() == 3):
+        raise ValueError("f must be an (H, W, d) float32 CUDA tensor")
+    H, W, d = f.shape
+    s0, s1, s2 = f.stride()
+    if not ((s2 == 1 or d == 1) and (s1 == d or W == 1) and s0 % d == 0 and s0 // d >= W):
+        raise ValueError("f must have contiguous pixels and a row pitch that is a multiple of d")
+    return f.data_ptr(), H, W, d, s0 // d
+
+
+class Server:
+    """Continuous-batching server on the current device (bf_server_* of the
+    C ABI).  ``submit`` queues one request and returns its ticket; the
+    tensors it was given are kept alive here until the request is forgotten
+    or the server closed."""
+
+    def __init__(self, arena_bytes=0, max_active=0, max_queued=0, streams=0, depth=0,
+                 quantum_us=0.0):
+        cfg = bf_server_config()
+        lib().bf_server_config_init(ctypes.byref(cfg))
+        cfg.arena_bytes = int(arena_bytes)
+        cfg.max_active = int(max_active)
+        cfg.max_queued = int(max_queued)
+        cfg.streams = int(streams)
+        cfg.depth = int(depth)
+        cfg.quantum_us = float(quantum_us)
+        h = ctypes.c_void_p()
+        _check(lib().bf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._refs = {}
+
+    def submit(self, f, sigma_s, C, K, seed, out=None, N=0, precision="fp16", center=True,
+               arrival=0.0):
+        """Queue the filter of ``f`` (see bf_vec_ex for the arguments);
+        ``arrival`` is the server-clock time the request arrives (0: now).
+        Returns (ticket, out)."""
+        import torch
+        ptr, H, W, d, pitch = _image_view(f)
+        if out is None:
+            out = torch.empty((H, W, d), dtype=torch.float32, device=f.device)
+        elif not (out.is_cuda and out.dtype == torch.float32 and tuple(out.shape) == (H, W, d)
+                  and out.is_contiguous()):
+            raise ValueError("out must be a contiguous (H, W, d) float32 CUDA tensor")
+        Ch = _host_f64(C, (d, d))
+        r = bf_request()
+        lib().bf_request_init(ctypes.byref(r))
+        r.f, r.out = ptr, out.data_ptr()
+        r.H, r.W, r.d, r.pitch = H, W, d, pitch
+        r.sigma_s = float(sigma_s)
+        r.C = Ch.ctypes.data
+        r.K, r.N = int(K), int(N)
+        r.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        r.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        r.center = 1 if center else 0
+        r.arrival = float(arrival)
+        t = ctypes.c_uint64()
+        _check(lib().bf_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._refs[t.value] = (f, out)
+        return t.value, out
+
+    def poll(self, ticket):
+        st = bf_request_status()
+        _check(lib().bf_server_poll(self._h, ticket, ctypes.byref(st)))
+        return _status_dict(st)
+
+    def wait(self, ticket, timeout=-1.0):
+        """Block until the request ends; returns its status dict (raises
+        BfError on timeout)."""
+        st = bf_request_status()
+        _check(lib().bf_server_wait(self._h, ticket, float(timeout), ctypes.byref(st)))
+        return _status_dict(st)
+
+    def drain(self, timeout=-1.0):
+        _check(lib().bf_server_drain(self._h, float(timeout)))
+
+    def forget(self, ticket):
+        _check(lib().bf_server_forget(self._h, ticket))
+        self._refs.pop(ticket, None)
+
+    def stats(self):
+        s = bf_server_stats()
+        _check(lib().bf_server_get_stats(self._h, ctypes.byref(s)))
+        return {n: getattr(s, n) for n, _ in bf_server_stats._fields_ if n != "reserved"}
+
+    def clock(self):
+        return lib().bf_server_clock(self._h)
+
+    def close(self):
+        if self._h:
+            _check(lib().bf_server_destroy(self._h))
+            self._h = None
+            self._refs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -35,8 +35,8 @@ int hip_fail(hipError_t e, const char* what) {
 
 constexpr int kMMThreads = 256;
 
-__global__ __launch_bounds__(kMMThreads) void minmax_partial(const float* f, size_t npx, int d,
-                                                             float* part) {
+__global__ __launch_bounds__(kMMThreads) void minmax_partial(const float* f, size_t npx, int W,
+                                                             int pitch, int d, float* part) {
   __shared__ float s_lo[8][kMMThreads], s_hi[8][kMMThreads];
   __shared__ int s_bad[kMMThreads];
   float lo[8], hi[8];
@@ -47,8 +47,9 @@ __global__ __launch_bounds__(kMMThreads) void minmax_partial(const float* f, siz
   int bad = 0;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
+    const size_t y = p / (size_t)W, q = (y * (size_t)pitch + (p - y * (size_t)W)) * (size_t)d;
     for (int m = 0; m < d; ++m) {
-      const float v = f[p * d + m];
+      const float v = f[q + m];
       bad |= !isfinite(v);
       lo[m] = fminf(lo[m], v);
       hi[m] = fmaxf(hi[m], v);
@@ -94,19 +95,32 @@ __global__ __launch_bounds__(64) void minmax_final(const float* part, int nparts
   }
 }
 
-int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStream_t st) {
+}  // namespace
+
+int minmax_parts(size_t npx) {
+  return (int)std::min<size_t>(1024, (npx + kMMThreads - 1) / kMMThreads);
+}
+
+hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* part, int nparts,
+                         float* res, hipStream_t st) {
   const size_t npx = (size_t)H * W;
-  const int nparts = (int)std::min<size_t>(1024, (npx + kMMThreads - 1) / kMMThreads);
+  hipLaunchKernelGGL(minmax_partial, dim3(nparts), dim3(kMMThreads), 0, st, f, npx, W, pitch, d,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(minmax_final, dim3(1), dim3(64), 0, st, part, nparts, res);
+  return hipGetLastError();
+}
+
+namespace {
+
+int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStream_t st) {
+  const int nparts = minmax_parts((size_t)H * W);
   float* dbuf = nullptr;
   HIP_TRY(hipMallocAsync((void**)&dbuf, ((size_t)nparts * 17 + 17) * sizeof(float), st),
           "hipMallocAsync(minmax)");
   float* res = dbuf + (size_t)nparts * 17;
-  hipLaunchKernelGGL(minmax_partial, dim3(nparts), dim3(kMMThreads), 0, st, f, npx, d, dbuf);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(minmax_final, dim3(1), dim3(64), 0, st, dbuf, nparts, res);
-    e = hipGetLastError();
-  }
+  hipError_t e = launch_minmax(f, H, W, W, d, dbuf, nparts, res, st);
   float h[17];
   if (e == hipSuccess) e = hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipFreeAsync(dbuf, st);
@@ -120,6 +134,8 @@ int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStr
   }
   return BF_OK;
 }
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // Strip height.  Each workgroup streams one strip per term and recomputes 2R
@@ -160,6 +176,8 @@ int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int
   return BF_OK;
 }
 
+namespace {
+
 int check_opts(const bf_opts* o) {
   if (o->N < 0 || o->N > 65536) return fail(BF_EINVAL, "opts.N must be 0 (auto) or in [1, 65536]");
   if (o->precision != BF_FP32 && o->precision != BF_FP16 && o->precision != BF_BF16)
@@ -169,14 +187,75 @@ int check_opts(const bf_opts* o) {
   return BF_OK;
 }
 
-// Checks that need no device work: window size, precision, strip height.
-int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
-  const int R = window_radius(sigma_s);
+}  // namespace
+
+int check_fused_size(int H, int W, int pitch, int d, int R) {
   if (R > kRMax) return fail(BF_EUNSUPPORTED, "sigma_s too large: window radius above 40");
   // the kernels address f and the accumulators with 32-bit element offsets
   const double elems = (double)(H + 2 * kB) * (double)(W + kTW) * (double)(d + 1);
-  if (elems >= 4294967296.0 - 65536.0)
+  const double felems = (double)H * (double)pitch * (double)d;
+  if (elems >= 4294967296.0 - 65536.0 || felems >= 4294967296.0 - 65536.0)
     return fail(BF_EUNSUPPORTED, "image too large: H*W*(d+1) must stay below 2^32 elements");
+  return BF_OK;
+}
+
+void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH) {
+  a.H = H;
+  a.W = W;
+  a.R = R;
+  a.TH = TH;
+  a.nsx = (W + kTW - 1) / kTW;
+  a.nsy = (H + TH - 1) / TH;
+  a.SW = prec == BF_FP32 ? stage_width(R) : stage_width16(R);
+  a.lag = lag_steps(R);
+  a.RSB = a.lag + 1;
+  a.CRB = a.lag + 2;
+  a.steps = a.lag + TH / kB;
+  a.Hp = a.nsy * TH;
+}
+
+size_t fused_acc_floats(const FusedArgs& a, int d) {
+  return (size_t)(d + 1) * a.Hp * a.nsx * kTW;
+}
+
+std::vector<float> term_table(int d, int K, const double* w, const double* weights,
+                              double sigma_s, size_t* off_weights, size_t* off_taps) {
+  const int NP = d + 1;
+  const int ntaps = 2 * window_radius(sigma_s) + 1;
+  const double two_pi = 6.283185307179586476925286766559;
+  const size_t n_terms = (size_t)K * NP, n_w = weights ? (size_t)K : 0;
+  std::vector<float> h(n_terms + n_w + (size_t)ntaps, 0.0f);
+  for (int t = 0; t < K; ++t)
+    for (int m = 0; m < d; ++m) h[(size_t)t * NP + m] = (float)(w[(size_t)t * d + m] / two_pi);
+  if (weights)
+    for (int t = 0; t < K; ++t) h[n_terms + t] = (float)weights[t];
+  const std::vector<double> taps = spatial_taps(sigma_s);
+  for (int u = 0; u < ntaps; ++u) h[n_terms + n_w + u] = (float)taps[u];
+  *off_weights = weights ? n_terms : (size_t)-1;
+  *off_taps = n_terms + n_w;
+  return h;
+}
+
+void frequency_table(int d, const double* Wm, int N, int K, uint64_t seed, double* w) {
+  const double sqn = std::sqrt((double)N);
+  for (int t = 0; t < K; ++t) {
+    int Y[8];
+    for (int m = 0; m < d; ++m) Y[m] = N - 2 * binomial_draw(seed, t, m, N);
+    for (int j = 0; j < d; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += (double)Y[k] * Wm[k * d + j];
+      w[(size_t)t * d + j] = s / sqn;
+    }
+  }
+}
+
+namespace {
+
+// Checks that need no device work: window size, precision, strip height.
+int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
+  const int R = window_radius(sigma_s);
+  const int rc = check_fused_size(H, W, W, d, R);
+  if (rc) return rc;
   return choose_strip_height(d, R, o->precision, H, W, o->tile_h, TH);
 }
 
@@ -186,39 +265,20 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
               const float* hi, int TH) {
   hipStream_t st = (hipStream_t)o->stream;
   const int R = window_radius(sigma_s);
-  const int NP = d + 1;
-  const int ntaps = 2 * R + 1;
-  const double two_pi = 6.283185307179586476925286766559;
-  // host staging: terms | weights | taps
-  const size_t n_terms = (size_t)K * NP, n_w = weights ? (size_t)K : 0;
-  std::vector<float> hbuf(n_terms + n_w + (size_t)ntaps, 0.0f);
-  for (int t = 0; t < K; ++t)
-    for (int m = 0; m < d; ++m) hbuf[(size_t)t * NP + m] = (float)(w[(size_t)t * d + m] / two_pi);
-  if (weights)
-    for (int t = 0; t < K; ++t) hbuf[n_terms + t] = (float)weights[t];
-  const std::vector<double> taps = spatial_taps(sigma_s);
-  for (int u = 0; u < ntaps; ++u) hbuf[n_terms + n_w + u] = (float)taps[u];
+  size_t off_w = 0, off_taps = 0;
+  const std::vector<float> hbuf = term_table(d, K, w, weights, sigma_s, &off_w, &off_taps);
 
   FusedArgs a{};
   a.f = f;
   for (int m = 0; m < 8; ++m)
     a.cen[m] = (o->center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
-  a.H = H;
-  a.W = W;
-  a.K = K;
-  a.R = R;
-  a.TH = TH;
-  a.nsx = (W + kTW - 1) / kTW;
-  a.nsy = (H + TH - 1) / TH;
-  a.SW = o->precision == BF_FP32 ? stage_width(R) : stage_width16(R);
-  a.lag = lag_steps(R);
-  a.RSB = a.lag + 1;
-  a.CRB = a.lag + 2;
-  a.steps = a.lag + TH / kB;
-  a.Hp = a.nsy * TH;
+  fused_geometry(a, H, W, R, o->precision, TH);
+  a.fpitch = W;
+  a.t0 = 0;
+  a.t1 = K;
 
   // one stream-ordered allocation: accumulators | terms | weights | taps
-  const size_t n_acc = (size_t)NP * a.Hp * a.nsx * kTW;
+  const size_t n_acc = fused_acc_floats(a, d);
   float* dbuf = nullptr;
   HIP_TRY(hipMallocAsync((void**)&dbuf, (n_acc + hbuf.size()) * sizeof(float), st),
           "hipMallocAsync(accumulators)");
@@ -226,15 +286,16 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   float* dterms = dbuf + n_acc;
   hipError_t e = hipMemcpyAsync(dterms, hbuf.data(), hbuf.size() * sizeof(float),
                                 hipMemcpyHostToDevice, st);
-  const float* dweights = weights ? dterms + n_terms : nullptr;
-  a.taps = dterms + n_terms + n_w;
+  a.terms = dterms;
+  a.weights = weights ? dterms + off_w : nullptr;
+  a.taps = dterms + off_taps;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (e == hipSuccess && o->time_kernel) {
     e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     if (e == hipSuccess) e = hipEventRecord(ev0, st);
   }
-  if (e == hipSuccess) e = launch_fused(d, o->precision, a, dterms, dweights, st);
+  if (e == hipSuccess) e = launch_fused(d, o->precision, a, st);
   if (e == hipSuccess && o->time_kernel) e = hipEventRecord(ev1, st);
   if (e == hipSuccess) {
     FinalizeArgs fa{};
@@ -352,16 +413,7 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   if (N == 0 && (rc = choose_order(d, Wm, lo, hi, &N))) return rc;
   o->N_used = N;
   std::vector<double> w((size_t)K * d);
-  const double sqn = std::sqrt((double)N);
-  for (int t = 0; t < K; ++t) {
-    int Y[8];
-    for (int m = 0; m < d; ++m) Y[m] = N - 2 * binomial_draw(seed, t, m, N);
-    for (int j = 0; j < d; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < d; ++k) s += (double)Y[k] * Wm[k * d + j];
-      w[(size_t)t * d + j] = s / sqn;
-    }
-  }
+  frequency_table(d, Wm, N, K, seed, w.data());
   return run_terms(f, H, W, d, sigma_s, w.data(), nullptr, K, out, o, lo, hi, TH);
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
+#include <vector>
 
 namespace bfvec {
 
@@ -34,18 +36,31 @@ constexpr int kSWMax = stage_width(kRMax);
 inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
 
 struct FusedArgs {
-  const float* f;        // H*W*d input (device)
+  const float* f;        // input (device), row y at f + y*fpitch*d
   float* acc;            // (d+1)*Hp*Wp accumulators, planar [m][y][x] (device),
                          // padded to whole strips: Hp = nsy*TH, Wp = nsx*kTW
   const float* taps;     // 2R+1 spatial taps (device), zero padded to a multiple of 4
+  const float* terms;    // term table (device): row t holds w_t / 2pi in its first d of d+1 floats
+  const float* weights;  // K term weights (device), or null for equal weights
   float cen[8];          // per-channel centre subtracted before the phase
-  int H, W, K, R;
+  int H, W, R;
+  int fpitch;            // pixels between vertically adjacent pixels of f (>= W)
+  int t0, t1;            // term range of this launch; the accumulators start at zero at term 0
   int TH;                // strip height (multiple of kB)
   int Hp;                // padded accumulator rows (nsy*TH)
   int nsx, nsy;          // strips across and down
   int SW;                // staging row width (floats)
   int RSB, CRB;          // ring sizes in blocks of kB rows
   int steps, lag;        // steps per term, and 2R look-ahead in steps
+};
+
+// Several requests of one kernel instance (same d, R, precision) in one
+// launch: workgroups first[i] .. first[i+1]-1 take the strips of req[i].
+constexpr int kMaxBatch = 16;
+struct BatchArgs {
+  int n;
+  int first[kMaxBatch + 1];
+  FusedArgs req[kMaxBatch];
 };
 
 struct FinalizeArgs {
@@ -61,8 +76,34 @@ struct FinalizeArgs {
 size_t fused_lds_bytes(int d, int R, int prec);
 // resident workgroups per compute unit for this kernel instance (device query)
 int fused_blocks_per_cu(int d, int R, int prec);
-hipError_t launch_fused(int d, int prec, const FusedArgs& a, const float* terms,
-                        const float* weights, hipStream_t st);
+hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st);
+// All requests of b share d, R and prec (and hence LDS size and staging width).
+hipError_t launch_fused_batch(int d, int R, int prec, const BatchArgs& b, hipStream_t st);
 hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t st);
+
+// Per-channel extrema of an image with row pitch `pitch` pixels, in two
+// kernels: nparts partial blocks into part (nparts*17 floats), then the
+// final reduction into res (17 floats: d minima at 0.., d maxima at 8..,
+// a non-finite flag at 16).
+int minmax_parts(size_t npx);
+hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* part, int nparts,
+                         float* res, hipStream_t st);
+
+// ---- host planning shared by the entry points and the serving scheduler ----
+// BF_EUNSUPPORTED (with the message set) if the fused kernels cannot take
+// this image: radius above kRMax, or sizes past 32-bit element offsets.
+int check_fused_size(int H, int W, int pitch, int d, int R);
+// Strip height for an image alone on the device (requested > 0 forces it).
+int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH);
+// Strip geometry, staging width and ring sizes of a FusedArgs.
+void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH);
+// Accumulator floats of a planned FusedArgs: (d+1) planes of Hp x Wp.
+size_t fused_acc_floats(const FusedArgs& a, int d);
+// Host term table: K rows of w_t/2pi (stride d+1) | K weights (if any) | 2R+1
+// taps.  Offsets of the weights and taps are returned in floats.
+std::vector<float> term_table(int d, int K, const double* w, const double* weights,
+                              double sigma_s, size_t* off_weights, size_t* off_taps);
+// Frequencies w_t = W^T Y_t / sqrt(N) of K terms drawn from seed (K x d, radians).
+void frequency_table(int d, const double* Wm, int N, int K, uint64_t seed, double* w);
 
 }  // namespace bfvec

@@ -1,584 +1,9 @@
-// Fused MCSF kernel for gfx950 (CDNA4), FP32 channels.
-//
-// One workgroup owns a strip of TW output columns and TH output rows (TH is
-// normally a large fraction of the image height).  For each of the K terms
-// it streams down the strip in steps of B input rows; a step
-//   1. modulates B haloed rows: theta = <w_t, f - c>, H = cos + i sin
-//      (eq. (Ht)), writing the 2(d+1) real channels
-//      {cos f_m, sin f_m (m < d), cos, sin} to a staging buffer (zero outside
-//      the image: out-of-domain pixels contribute nothing);
-//   2. runs the horizontal pass of the truncated separable Gaussian omega
-//      over those rows into a ring holding the last RS rows;
-//   3. once 2R rows of look-ahead are in the ring, runs the vertical pass for
-//      B output rows and demodulates:
-//      P_m += cos (omega * cos f_m) + sin (omega * sin f_m),
-//      Z   += cos (omega * cos)     + sin (omega * sin)    (eqs. (numerator), (denom)),
-//      adding into planar accumulators in device memory (Algorithm 1, P and Z).
-// A separate finalize kernel divides (Algorithm 1, last step).
-//
-// Work per output pixel and term: 2(d+1)(2R+1) FMAs per pass.  Both passes
-// are register-blocked sliding windows over LDS (4 outputs per item).  With
-// R fixed at compile time the window loops unroll completely and the taps
-// live in registers; a runtime-R variant serves every other radius.  No
-// MFMA: the passes are stencils.  LDS stays near 70 KB so two workgroups
-// share a compute unit.
-//
-// Low-precision variants (PREC 1 = FP16, 2 = BF16) store the modulated
-// channels and the horizontal-pass rows as 16-bit pairs and run both passes
-// with v_dot2_f32_{f16,bf16}: two taps times two adjacent samples added into
-// an FP32 accumulator.  With the taps split by parity, output 2q takes
-// (w[2i], w[2i+1]) against samples (2q+2i, 2q+2i+1) and output 2q+1 takes
-// (w[2i-1], w[2i]) against the same aligned pair, so every window read is an
-// aligned 32-bit pair and each output costs R+1 dot2 instead of 2R+1 FMAs.
-// Demodulation, accumulation and the division stay FP32.
+// Single-request launches of the fused MCSF kernel, the finalize kernel,
+// and the occupancy and LDS sizing used to plan strips.
 
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-
-#include "mcsf_common.h"
+#include "mcsf_fused_dev.h"
 
 namespace bfvec {
-
-namespace {
-
-template <int D>
-struct Geo {
-  static constexpr int NP = D + 1;   // channel pairs (d numerators + Z)
-  static constexpr int NC = 2 * NP;  // real channels
-  static constexpr int NT = 64 * NP; // threads per workgroup
-  static constexpr int MI = (kB * kSWMax + NT - 1) / NT;  // modulation slots
-};
-
-__device__ __forceinline__ int wrap(int r, int n) { return r >= n ? r - n : r; }
-
-__device__ __forceinline__ void ld4(float* v, const float* p) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-}
-
-// Sliding-window FMAs of a 4-output register block against taps t[0..3]:
-// output p takes t[i] * window[p + i]; the window is two 4-blocks (lo | hi).
-__device__ __forceinline__ void fma_lo(float (&acc)[4], const float* t, const float* lo) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int p = 0; p + i < 4; ++p) acc[p] = fmaf(t[i], lo[p + i], acc[p]);
-}
-__device__ __forceinline__ void fma_hi(float (&acc)[4], const float* t, const float* hi) {
-#pragma unroll
-  for (int i = 1; i < 4; ++i)
-#pragma unroll
-    for (int p = 4 - i; p < 4; ++p) acc[p] = fmaf(t[i], hi[p + i - 4], acc[p]);
-}
-
-// ---- 16-bit storage helpers --------------------------------------------------
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-typedef short short2_t __attribute__((ext_vector_type(2)));
-
-template <int PREC>
-__device__ __forceinline__ unsigned short to16(float x) {
-  if constexpr (PREC == 1) return __builtin_bit_cast(unsigned short, (_Float16)x);
-  else return __builtin_bit_cast(unsigned short, (__bf16)x);
-}
-
-// a.lo*b.lo + a.hi*b.hi + c, products and sum in FP32
-template <int PREC>
-__device__ __forceinline__ float dot2(unsigned a, unsigned b, float c) {
-  if constexpr (PREC == 1)
-    return __builtin_amdgcn_fdot2(__builtin_bit_cast(half2_t, a), __builtin_bit_cast(half2_t, b), c,
-                                  false);
-  else
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(short2_t, a),
-                                           __builtin_bit_cast(short2_t, b), c, false);
-}
-
-__device__ __forceinline__ unsigned pack16(unsigned short lo, unsigned short hi) {
-  return (unsigned)lo | ((unsigned)hi << 16);
-}
-
-// Swap lanes 32..63 of a with lanes 0..31 of b (v_permlane32_swap_b32).
-// Written as a register-only instruction with both operands read and written:
-// the compiler builtin's second result was dropped in generated code.  The
-// s_nop pairs cover the VALU-write/permlane-read hazard windows.
-__device__ __forceinline__ void swap_halves(unsigned& a, unsigned& b) {
-  asm volatile("s_nop 4\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 4" : "+v"(a), "+v"(b));
-}
-
-// two FP32 values to one packed 16-bit pair (single v_cvt_pk_* instruction)
-typedef float float2_t __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-template <int PREC>
-__device__ __forceinline__ unsigned pack2(float lo, float hi) {
-  const float2_t v = {lo, hi};
-  if constexpr (PREC == 1) return __builtin_bit_cast(unsigned, __builtin_convertvector(v, half2_t));
-  else return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
-}
-
-// Four outputs (p = 0..3, starting at an even sample) of a 2R+1-tap window
-// over aligned sample pairs x2[j] = (x[2j], x[2j+1]):
-//   out[2q]   = sum_i te[i] . x2[q+i],   te[i] = (w[2i],   w[2i+1])
-//   out[2q+1] = sum_i to[i] . x2[q+i],   to[i] = (w[2i-1], w[2i])
-template <int PREC, int R>
-__device__ __forceinline__ void window4_lp(const unsigned* x2, const unsigned* te,
-                                           const unsigned* to, float (&acc)[4]) {
-#pragma unroll
-  for (int i = 0; i <= R; ++i) {
-    acc[0] = dot2<PREC>(te[i], x2[i], acc[0]);
-    acc[1] = dot2<PREC>(to[i], x2[i], acc[1]);
-    acc[2] = dot2<PREC>(te[i], x2[i + 1], acc[2]);
-    acc[3] = dot2<PREC>(to[i], x2[i + 1], acc[3]);
-  }
-}
-
-// Horizontal pass, 16-bit storage: src points at the dword holding samples
-// (first output, first output + 1) of the window start.
-template <int PREC, int RC>
-__device__ __forceinline__ void hpass_lp(const unsigned* src, const unsigned* te, const unsigned* to,
-                                         const unsigned* s_te, const unsigned* s_to, int R,
-                                         float (&acc)[4]) {
-  if constexpr (RC >= 0) {
-    constexpr int NWD = RC + 2, NL = (NWD + 1) / 2;
-    unsigned x2[2 * NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-      const uint2 v = *reinterpret_cast<const uint2*>(src + 2 * j);
-      x2[2 * j] = v.x;
-      x2[2 * j + 1] = v.y;
-    }
-    window4_lp<PREC, RC>(x2, te, to, acc);
-  } else {
-    unsigned cur = src[0];
-    for (int i = 0; i <= R; ++i) {
-      const unsigned nxt = src[i + 1];
-      const unsigned ei = s_te[i], oi = s_to[i];
-      acc[0] = dot2<PREC>(ei, cur, acc[0]);
-      acc[1] = dot2<PREC>(oi, cur, acc[1]);
-      acc[2] = dot2<PREC>(ei, nxt, acc[2]);
-      acc[3] = dot2<PREC>(oi, nxt, acc[3]);
-      cur = nxt;
-    }
-  }
-}
-
-// Vertical pass, 16-bit storage: the ring holds row pairs (even row in the
-// low half); col points at this item's channel column in pair-row 0, pb is
-// the pair-row of the first window row; pair-rows wrap at RSP (blocks of two
-// pair-rows are aligned and never straddle the wrap).
-template <int PREC, int RC, int RSTD>
-__device__ __forceinline__ void vpass_lp(const unsigned* col, int pb, int RSP, const unsigned* te,
-                                         const unsigned* to, const unsigned* s_te,
-                                         const unsigned* s_to, int R, float (&acc)[4]) {
-  if constexpr (RC >= 0) {
-    constexpr int NWD = RC + 2, NB = (NWD + 1) / 2;
-    unsigned y2[2 * NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const unsigned* r = col + wrap(pb + 2 * b, RSP) * RSTD;
-      y2[2 * b] = r[0];
-      y2[2 * b + 1] = r[RSTD];
-    }
-    window4_lp<PREC, RC>(y2, te, to, acc);
-  } else {
-    unsigned cur = col[wrap(pb, RSP) * RSTD];
-    for (int i = 0; i <= R; ++i) {
-      const unsigned nxt = col[wrap(pb + i + 1, RSP) * RSTD];
-      const unsigned ei = s_te[i], oi = s_to[i];
-      acc[0] = dot2<PREC>(ei, cur, acc[0]);
-      acc[1] = dot2<PREC>(oi, cur, acc[1]);
-      acc[2] = dot2<PREC>(ei, nxt, acc[2]);
-      acc[3] = dot2<PREC>(oi, nxt, acc[3]);
-      cur = nxt;
-    }
-  }
-}
-
-// Horizontal pass of one item: 4 consecutive outputs of one channel of one
-// row; src points at the staging column of the first output's window start.
-template <int RC>
-__device__ __forceinline__ void hpass(const float* src, const float* tapr, const float* s_taps,
-                                      int ntap4, float (&acc)[4]) {
-  if constexpr (RC >= 0) {
-    constexpr int NW = 2 * RC + 4, NB = (NW + 3) / 4;
-    float x[NB * 4];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) ld4(x + 4 * b, src + 4 * b);
-#pragma unroll
-    for (int u = 0; u <= 2 * RC; ++u)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u], x[p + u], acc[p]);
-  } else {
-    const int nblk = ntap4 / 4;
-    float ra[4], rb[4], t[8];
-    ld4(ra, src);
-    ld4(rb, src + 4);
-    int b = 0;
-    for (; b + 2 <= nblk; b += 2) {
-      ld4(t, s_taps + 4 * b);
-      ld4(t + 4, s_taps + 4 * b + 4);
-      fma_lo(acc, t, ra);
-      ld4(ra, src + 4 * b + 8);                       // b + 2 <= nblk here
-      fma_hi(acc, t, rb);
-      fma_lo(acc, t + 4, rb);
-      ld4(rb, src + 4 * min(b + 3, nblk));            // clamped: no branch
-      fma_hi(acc, t + 4, ra);
-    }
-    if (b < nblk) {
-      ld4(t, s_taps + 4 * b);
-      fma_lo(acc, t, ra);
-      fma_hi(acc, t, rb);
-    }
-  }
-}
-
-// Vertical pass of one item: 4 consecutive output rows of one channel of one
-// column.  col points at the channel column in ring row 0; rb is the ring row
-// of the first window row; ring rows wrap at RS (window blocks of 4 rows are
-// aligned, so a block never straddles the wrap).
-template <int RC, int RST>
-__device__ __forceinline__ void vpass(const float* col, int rb, int RS, const float* tapr,
-                                      const float* s_taps, int ntap4, float (&acc)[4]) {
-  if constexpr (RC >= 0) {
-    constexpr int NW = 2 * RC + 4, NB = (NW + 3) / 4;
-    float x[NB * 4];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float* r = col + wrap(rb + 4 * b, RS) * RST;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) x[4 * b + i] = r[i * RST];
-    }
-#pragma unroll
-    for (int u = 0; u <= 2 * RC; ++u)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u], x[p + u], acc[p]);
-  } else {
-    const int nblk = ntap4 / 4;
-    auto ldb = [&](float* v, int blk) {
-      const float* r = col + wrap(rb + 4 * blk, RS) * RST;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = r[i * RST];
-    };
-    float ra[4], rbv[4], t[8];
-    ldb(ra, 0);
-    ldb(rbv, 1);
-    int b = 0;
-    for (; b + 2 <= nblk; b += 2) {
-      ld4(t, s_taps + 4 * b);
-      ld4(t + 4, s_taps + 4 * b + 4);
-      fma_lo(acc, t, ra);
-      ldb(ra, b + 2);
-      fma_hi(acc, t, rbv);
-      fma_lo(acc, t + 4, rbv);
-      ldb(rbv, min(b + 3, nblk));
-      fma_hi(acc, t + 4, ra);
-    }
-    if (b < nblk) {
-      ld4(t, s_taps + 4 * b);
-      fma_lo(acc, t, ra);
-      fma_hi(acc, t, rbv);
-    }
-  }
-}
-
-}  // namespace
-
-// RC: window radius fixed at compile time, or -1 for a runtime radius.
-// PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
-template <int D, int RC, int PREC>
-__global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused(FusedArgs a,
-                                                           const float* __restrict__ terms,
-                                                           const float* __restrict__ weights) {
-  using G = Geo<D>;
-  constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
-  constexpr int TW = kTW, B = kB;
-  constexpr int RST = NC * TW;       // ring row stride: [ch][x]
-  constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
-  constexpr bool LP = PREC != 0;
-  constexpr int NTAPR = (RC >= 0 && !LP) ? 2 * RC + 1 : 1;
-  constexpr int NTAPP = (RC >= 0 && LP) ? RC + 1 : 1;   // packed tap pairs
-
-  extern __shared__ float4 lds4[];
-  float* lds = reinterpret_cast<float*>(lds4);
-  const int R = RC >= 0 ? RC : a.R;
-  const int SW = RC >= 0 ? (LP ? stage_width16(RC) : stage_width(RC)) : a.SW;
-  const int MW = RC >= 0 ? kTW + 2 * RC : SW;   // modulated columns per staging row
-  const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
-  const int taps_al = (ntap4 + 7) / 8 * 8;
-  const int tapp_al = (R + 1 + 3) / 4 * 4;
-  const int RS = a.RSB * B, CRS = a.CRB * B;
-  // LDS carve-up: FP32 taps | packed tap pairs (16-bit modes) | staging |
-  // ring | cos/sin ring.  16-bit modes store the ring as row pairs.
-  float* s_taps = lds;
-  unsigned* s_te = reinterpret_cast<unsigned*>(s_taps + taps_al);
-  unsigned* s_to = s_te + (LP ? tapp_al : 0);
-  float* s_stage = reinterpret_cast<float*>(s_to + (LP ? tapp_al : 0));
-  unsigned short* s_stage16 = reinterpret_cast<unsigned short*>(s_stage);
-  float* s_ring = s_stage + (LP ? B * NC * SW / 2 : B * NC * SW);
-  unsigned* s_ring32 = reinterpret_cast<unsigned*>(s_ring);
-  unsigned short* s_ring16 = reinterpret_cast<unsigned short*>(s_ring);
-  float* s_cs = s_ring + (LP ? RS / 2 : RS) * RST;
-
-  const int tid = threadIdx.x;
-  // XCD-aware strip order: dispatch ids go round-robin over the 8 XCDs; give
-  // each XCD a contiguous run of strips so neighbours (which share their halo
-  // of f) meet in the same L2.
-  const int nt = a.nsx * a.nsy;
-  int bid = blockIdx.x;
-  if (nt % 8 == 0) bid = (bid % 8) * (nt / 8) + bid / 8;
-  const int sx = bid % a.nsx, sy = bid / a.nsx;
-  const int x0 = sx * TW, y0 = sy * a.TH;
-  const int Wd = a.W, Hd = a.H;
-
-  for (int i = tid; i < taps_al; i += NT) s_taps[i] = i < 2 * R + 1 ? a.taps[i] : 0.0f;
-  for (int i = tid; i < (LP ? RS / 2 : RS) * RST; i += NT) s_ring[i] = 0.0f;
-  for (int i = tid; i < B * NC * (SW - MW); i += NT) {   // staging padding columns
-    const int row = i / (SW - MW), col = MW + i % (SW - MW);
-    if constexpr (LP) s_stage16[row * SW + col] = 0;
-    else s_stage[row * SW + col] = 0.0f;
-  }
-  __syncthreads();
-  if constexpr (LP) {
-    // tap pairs by parity: te[i] = (w[2i], w[2i+1]), to[i] = (w[2i-1], w[2i]),
-    // with w[-1] = w[2R+1] = 0
-    for (int i = tid; i < tapp_al; i += NT) {
-      const float w0 = 2 * i <= 2 * R ? s_taps[2 * i] : 0.0f;
-      const float w1 = 2 * i + 1 <= 2 * R ? s_taps[2 * i + 1] : 0.0f;
-      const float wm = i > 0 && 2 * i - 1 <= 2 * R ? s_taps[2 * i - 1] : 0.0f;
-      s_te[i] = pack16(to16<PREC>(w0), to16<PREC>(w1));
-      s_to[i] = pack16(to16<PREC>(wm), to16<PREC>(w0));
-    }
-    __syncthreads();
-  }
-  float tapr[NTAPR];
-#pragma unroll
-  for (int u = 0; u < NTAPR; ++u) tapr[u] = s_taps[u];
-  unsigned tpe[NTAPP], tpo[NTAPP];
-#pragma unroll
-  for (int i = 0; i < NTAPP; ++i) {
-    tpe[i] = LP ? s_te[i] : 0u;
-    tpo[i] = LP ? s_to[i] : 0u;
-  }
-
-  // ---- per-thread fixed roles -------------------------------------------------
-  // pass 1 item: 4-column block xq, channel ch, row rr of the step.  xq varies
-  // fastest across lanes: the items' 128-bit ring writes then cover contiguous
-  // LDS (a channel-fastest order measured a 7-way bank conflict on them).
-  const int p1_xq = tid % 4;
-  const int p1_ch = (tid / 4) % NC;
-  const int p1_rr = tid / (4 * NC);
-  // pass 2 item: column x, cos/sin half k, pair m, 4-row group g
-  const int p2_x = tid & 15;
-  const int p2_k = (tid >> 4) & 1;
-  const int p2_m = (tid >> 5) % NP;
-  int p2_g = (tid >> 5) / NP;
-  if constexpr (NP % 2 == 0) p2_g = __builtin_amdgcn_readfirstlane(p2_g);
-  const int p2_ch = 2 * p2_m + p2_k;
-  // accumulators: planar [m][Hp][Wp] padded to whole strips, so every lane
-  // owns valid storage; 32-bit element offsets from the (uniform) base
-  const int Wp = a.nsx * TW;
-  const unsigned acc_lane = (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
-
-  // Modulation slots: pixel tid + i*NT of the B x MW step tile.  With R fixed
-  // the passes read only the TW + 2R window columns; the runtime-R loops also
-  // read zero-tap padding, so they modulate the whole row.  Columns beyond MW
-  // are zeroed once below and never written again.
-  const int nmod = B * MW;
-  int m_rr[MI], m_off[MI], m_x[MI];
-  bool m_xin[MI];
-#pragma unroll
-  for (int i = 0; i < MI; ++i) {
-    const int pi = min(tid + i * NT, nmod - 1);
-    m_rr[i] = pi / MW;
-    const int j = pi - m_rr[i] * MW;
-    m_off[i] = m_rr[i] * NC * SW + j;
-    m_x[i] = x0 - R + j;
-    m_xin[i] = tid + i * NT < nmod && j < TW + 2 * R && m_x[i] >= 0 && m_x[i] < Wd;
-  }
-  const int ybase = y0 - R;
-
-  // Prefetch buffers, two steps deep (ping-pong A/B by step parity): raw f of
-  // each modulation slot, loaded from a clamped in-image address so the loads
-  // stay in flight across the passes, and this lane's accumulators for the
-  // output rows of the step.
-  const int steps = a.steps, lag = a.lag, K = a.K;
-  float fA[MI][D], fB[MI][D];
-  float aA[2] = {0.0f, 0.0f}, aB[2] = {0.0f, 0.0f};
-  int m_fx[MI];  // clamped column offset of each slot, in floats
-#pragma unroll
-  for (int i = 0; i < MI; ++i) m_fx[i] = min(max(m_x[i], 0), Wd - 1) * D;
-  auto load_f = [&](float (&dst)[MI][D], int s) {
-#pragma unroll
-    for (int i = 0; i < MI; ++i) {
-      if (i * NT < nmod) {
-        const int y = min(max(ybase + s * B + m_rr[i], 0), Hd - 1);
-        const unsigned o = (unsigned)y * (unsigned)(Wd * D) + (unsigned)m_fx[i];
-#pragma unroll
-        for (int m = 0; m < D; ++m) dst[i][m] = a.f[o + m];
-      }
-    }
-  };
-  auto load_acc = [&](float (&dst)[2], int t, int s) {
-    if (t > 0 && t < K && s >= lag) {
-      const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
-      dst[0] = a.acc[o];
-      dst[1] = a.acc[o + Wp];
-    }
-  };
-
-  // ring positions of the current step (rows written) and of the step lag
-  // behind it (rows the vertical pass starts from), advanced by B per step
-  int rslot = 0, cslot = 0;
-  int rslot_lag = (a.RSB - lag % a.RSB) % a.RSB * B, cslot_lag = (a.CRB - lag % a.CRB) % a.CRB * B;
-  float wr[D];
-  float tw = 1.0f;
-  auto load_term = [&](int t) {
-#pragma unroll
-    for (int m = 0; m < D; ++m) wr[m] = terms[t * NP + m];
-    tw = weights ? weights[t] : 1.0f;
-  };
-
-  // One pipeline step s of term t; fcur/acur hold this step's prefetched
-  // data and are refilled for the step two ahead.
-  auto step = [&](int t, int s, float (&fcur)[MI][D], float (&acur)[2]) {
-    // ---- 1. modulation ---------------------------------------------------------
-#pragma unroll
-    for (int i = 0; i < MI; ++i) {
-      if (i * NT < nmod && tid + i * NT < nmod) {
-        const int y = ybase + s * B + m_rr[i];
-        const bool in = m_xin[i] && y >= 0 && y < Hd;
-        float fv[D];
-#pragma unroll
-        for (int m = 0; m < D; ++m) fv[m] = fcur[i][m] - a.cen[m];
-        float rho = 0.0f;
-#pragma unroll
-        for (int m = 0; m < D; ++m) rho = fmaf(wr[m], fv[m], rho);
-        const float fr = __builtin_amdgcn_fractf(rho);
-        float c = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
-        c = in ? c : 0.0f;
-        sn = in ? sn : 0.0f;
-        if constexpr (LP) {
-          unsigned short* st = s_stage16 + m_off[i];
-#pragma unroll
-          for (int m = 0; m < D; ++m) {
-            st[(2 * m) * SW] = to16<PREC>(c * fv[m]);
-            st[(2 * m + 1) * SW] = to16<PREC>(sn * fv[m]);
-          }
-          st[(2 * D) * SW] = to16<PREC>(c);
-          st[(2 * D + 1) * SW] = to16<PREC>(sn);
-        } else {
-          float* st = s_stage + m_off[i];
-#pragma unroll
-          for (int m = 0; m < D; ++m) {
-            st[(2 * m) * SW] = c * fv[m];
-            st[(2 * m + 1) * SW] = sn * fv[m];
-          }
-          st[(2 * D) * SW] = c;
-          st[(2 * D + 1) * SW] = sn;
-        }
-        const int xc = m_x[i] - x0;
-        if (xc >= 0 && xc < TW) {
-          s_cs[(cslot + m_rr[i]) * CST + xc] = c;
-          s_cs[(cslot + m_rr[i]) * CST + TW + xc] = sn;
-        }
-      }
-    }
-    // the step two ahead, possibly in the next term(s)
-    int s2 = s + 2, t2 = t;
-    if (s2 >= steps) { s2 -= steps; ++t2; }
-    if (s2 >= steps) { s2 -= steps; ++t2; }
-    load_f(fcur, s2);
-    __syncthreads();
-
-    // ---- 2. horizontal pass ------------------------------------------------------
-    {
-      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      if constexpr (LP) {
-        const unsigned* src =
-            reinterpret_cast<const unsigned*>(s_stage16 + (p1_rr * NC + p1_ch) * SW) + p1_xq * 2;
-        hpass_lp<PREC, RC>(src, tpe, tpo, s_te, s_to, R, acc);
-        // row r goes to the low (even r) or high (odd r) half of pair-row r/2
-        const int r = rslot + p1_rr;
-        if constexpr (4 * NC == 32) {
-          // rows 2w and 2w+1 of this item sit in lanes l and l+32: swap halves so
-          // the lower lanes hold both rows of columns 2,3 and the upper lanes
-          // both rows of columns 0,1, then write one packed 64-bit chunk each
-          unsigned a2 = __builtin_bit_cast(unsigned, acc[2]), a0 = __builtin_bit_cast(unsigned, acc[0]);
-          unsigned a3 = __builtin_bit_cast(unsigned, acc[3]), a1 = __builtin_bit_cast(unsigned, acc[1]);
-          swap_halves(a2, a0);   // lower lanes: (e2, o2); upper lanes: (e0, o0)
-          swap_halves(a3, a1);   // lower lanes: (e3, o3); upper lanes: (e1, o1)
-          const unsigned da = pack2<PREC>(__builtin_bit_cast(float, a2), __builtin_bit_cast(float, a0));
-          const unsigned db = pack2<PREC>(__builtin_bit_cast(float, a3), __builtin_bit_cast(float, a1));
-          const int upper = (tid >> 5) & 1;   // odd row of the pair
-          *reinterpret_cast<uint2*>(s_ring32 + (r >> 1) * RST + p1_ch * TW + p1_xq * 4 +
-                                    (upper ? 0 : 2)) = make_uint2(da, db);
-        } else {
-          unsigned short* dst = s_ring16 + 2 * ((r >> 1) * RST + p1_ch * TW + p1_xq * 4) + (r & 1);
-#pragma unroll
-          for (int p = 0; p < 4; ++p) dst[2 * p] = to16<PREC>(acc[p]);
-        }
-      } else {
-        hpass<RC>(s_stage + (p1_rr * NC + p1_ch) * SW + p1_xq * 4, tapr, s_taps, ntap4, acc);
-        *reinterpret_cast<float4*>(s_ring + (rslot + p1_rr) * RST + p1_ch * TW + p1_xq * 4) =
-            make_float4(acc[0], acc[1], acc[2], acc[3]);
-      }
-    }
-    __syncthreads();
-
-    // ---- 3. vertical pass, demodulation, accumulation -------------------------------
-    if (s >= lag) {
-      const int ob = s - lag;
-      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      const int rb = rslot_lag + p2_g * 4;
-      (void)ob;
-      if constexpr (LP)
-        vpass_lp<PREC, RC, RST>(s_ring32 + p2_ch * TW + p2_x, rb >> 1, RS / 2, tpe, tpo, s_te, s_to,
-                                R, acc);
-      else
-        vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rb, RS, tapr, s_taps, ntap4, acc);
-      const int cb = cslot_lag + p2_g * 4 + R;
-      float tot[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const float cs = s_cs[wrap(cb + p, CRS) * CST + p2_k * TW + p2_x];
-        const float q = cs * acc[p];
-        tot[p] = q + __shfl_xor(q, 16);
-      }
-      {  // lane k adds rows 2k and 2k+1 of the pair's 4-row block
-        const unsigned o = acc_lane + (unsigned)(ob * B + p2_g * 4) * Wp;
-        const float v0 = p2_k ? tot[2] : tot[0], v1 = p2_k ? tot[3] : tot[1];
-        a.acc[o] = fmaf(tw, v0, t > 0 ? acur[0] : 0.0f);
-        a.acc[o + Wp] = fmaf(tw, v1, t > 0 ? acur[1] : 0.0f);
-      }
-    }
-    load_acc(acur, t2, s2);
-    rslot = wrap(rslot + B, RS);
-    cslot = wrap(cslot + B, CRS);
-    rslot_lag = wrap(rslot_lag + B, RS);
-    cslot_lag = wrap(cslot_lag + B, CRS);
-  };
-
-  // Flattened loop over (term, step) pairs of global steps, two per trip so
-  // the A/B prefetch buffers keep fixed roles.
-  load_f(fA, 0);
-  load_f(fB, steps > 1 ? 1 : 0);
-  load_term(0);
-  const int total = K * steps;
-  int t = 0, s = 0;
-  for (int gs = 0; gs < total; gs += 2) {
-    step(t, s, fA, aA);
-    if (++s == steps) {
-      s = 0;
-      if (++t < K) load_term(t);
-    }
-    if (gs + 1 < total) {
-      step(t, s, fB, aB);
-      if (++s == steps) {
-        s = 0;
-        if (++t < K) load_term(t);
-      }
-    }
-  }
-}
 
 // out = num / Z + c ; optional uncentred numerator and normaliser
 template <int D>
@@ -635,52 +60,6 @@ static int blocks_per_cu_drp(int R) {
   return std::max(1, std::min(by_vgpr, by_lds));
 }
 
-template <int D, int RC, int PREC>
-static hipError_t launch_drp(const FusedArgs& a, const float* terms, const float* weights,
-                             hipStream_t st) {
-  const size_t lds = fused_lds_bytes(D, a.R, PREC);
-  auto kern = mcsf_fused<D, RC, PREC>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.nsx * a.nsy), dim3(64 * (D + 1)), lds, st, a, terms, weights);
-  return hipGetLastError();
-}
-
-// Radii with a fully unrolled specialisation (the workload radii and the
-// serving range); every other radius takes the runtime-R variant.
-template <int D, int PREC>
-static hipError_t launch_dp(const FusedArgs& a, const float* terms, const float* weights,
-                            hipStream_t st) {
-  switch (a.R) {
-    case 6: return launch_drp<D, 6, PREC>(a, terms, weights, st);
-    case 9: return launch_drp<D, 9, PREC>(a, terms, weights, st);
-    case 12: return launch_drp<D, 12, PREC>(a, terms, weights, st);
-    case 15: return launch_drp<D, 15, PREC>(a, terms, weights, st);
-    case 18: return launch_drp<D, 18, PREC>(a, terms, weights, st);
-    case 21: return launch_drp<D, 21, PREC>(a, terms, weights, st);
-    case 24: return launch_drp<D, 24, PREC>(a, terms, weights, st);
-    case 30: return launch_drp<D, 30, PREC>(a, terms, weights, st);
-    default: return launch_drp<D, -1, PREC>(a, terms, weights, st);
-  }
-}
-
-template <int PREC>
-static hipError_t launch_p(int d, const FusedArgs& a, const float* terms, const float* weights,
-                           hipStream_t st) {
-  switch (d) {
-    case 1: return launch_drp<1, -1, PREC>(a, terms, weights, st);
-    case 2: return launch_drp<2, -1, PREC>(a, terms, weights, st);
-    case 3: return launch_dp<3, PREC>(a, terms, weights, st);
-    case 4: return launch_drp<4, -1, PREC>(a, terms, weights, st);
-    case 5: return launch_drp<5, -1, PREC>(a, terms, weights, st);
-    case 6: return launch_dp<6, PREC>(a, terms, weights, st);
-    case 7: return launch_drp<7, -1, PREC>(a, terms, weights, st);
-    case 8: return launch_drp<8, -1, PREC>(a, terms, weights, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 template <int D, int PREC>
 static int bpc_dp(int R) {
   switch (R) {
@@ -714,12 +93,11 @@ int fused_blocks_per_cu(int d, int R, int prec) {
   return prec == 0 ? bpc_p<0>(d, R) : prec == 1 ? bpc_p<1>(d, R) : bpc_p<2>(d, R);
 }
 
-hipError_t launch_fused(int d, int prec, const FusedArgs& a, const float* terms,
-                        const float* weights, hipStream_t st) {
+hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st) {
   switch (prec) {
-    case 0: return launch_p<0>(d, a, terms, weights, st);
-    case 1: return launch_p<1>(d, a, terms, weights, st);
-    case 2: return launch_p<2>(d, a, terms, weights, st);
+    case 0: return launch_p<0>(d, a, a.R, st);
+    case 1: return launch_p<1>(d, a, a.R, st);
+    case 2: return launch_p<2>(d, a, a.R, st);
     default: return hipErrorInvalidValue;
   }
 }

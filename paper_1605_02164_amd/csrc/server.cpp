@@ -1,0 +1,766 @@
+// Continuous-batching server of the MCSF filter: the bf_server_* entry points.
+//
+// One scheduler thread per server drives the device:
+//   admission  -- requests whose arrival time has passed are admitted in
+//                 arrival order while their footprint (accumulators, term
+//                 table, reduction partials) fits the device arena and fewer
+//                 than max_active are admitted;
+//   preparation-- per-channel min/max on an auxiliary stream when the order
+//                 rule or centring needs it, then the host draws the K terms
+//                 (Proposition 2, as bf_vec_ex does) and uploads the table;
+//   rounds     -- every admitted request gets its next chunk of terms (a
+//                 quantum of modelled device time) and chunks of one kernel
+//                 instance go into one batched launch; at most `depth` rounds
+//                 are queued ahead of the device;
+//   completion -- after its last chunk a request's finalize kernel (the
+//                 division of Algorithm 1) and a completion event follow on
+//                 the same stream; the scheduler frees its arena block when
+//                 the event has passed.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "bfvec.h"
+#include "host.h"
+#include "mcsf_common.h"
+#include "scheduler.h"
+
+namespace bfvec {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr size_t kAlign = 256;
+constexpr int kMMFloats = 17;  // min/max result block: 8 minima, 8 maxima, flag
+
+// Modelled device cost of one term of a planned request, in microseconds:
+// executed flops of all its workgroup steps (modulation of the haloed rows,
+// both passes; the 16-bit passes do two taps per instruction) at a nominal
+// rate.  Only ratios between requests matter for the chunking.
+double model_term_us(const FusedArgs& a, int d, int prec) {
+  const double NC = 2.0 * (d + 1), taps = 2.0 * a.R + 1.0;
+  const double mod = (double)kB * (kTW + 2 * a.R) * (4.0 * d + 2.0);
+  const double pass = 2.0 * kB * NC * kTW * taps * 2.0 * (prec == BF_FP32 ? 1.0 : 0.5);
+  const double per_step = mod + pass;
+  const double flops = per_step * a.steps * (double)a.nsx * a.nsy;
+  return flops / 50e12 * 1e6;
+}
+
+struct Req {
+  uint64_t ticket = 0;
+  bf_request in{};
+  double Cm[64] = {0};
+  double Wm[64] = {0};
+  int R = 0, variant = 0, stream = 0;
+  FusedArgs a{};
+  size_t n_acc = 0, n_tab = 0, off_w = 0, off_taps = 0;
+  int nparts = 0;
+  size_t dev_bytes = 0, pin_bytes = 0, dev_off = 0, pin_off = 0;
+  bool has_dev = false, has_pin = false, need_minmax = false;
+  float* part = nullptr;  // device reduction partials (nparts*17) then result (17)
+  float* pin = nullptr;   // pinned: min/max result (17, padded to 32) then term table
+  double cost_term = 0.0;
+  int next_t = 0;
+  hipEvent_t ev_mm = nullptr, ev_done = nullptr;
+  // shared with callers (guarded by the server mutex)
+  int state = BF_REQ_QUEUED, error = 0, N_used = 0, chunks = 0;
+  std::string msg;
+  double t_arrival = 0, t_admit = 0, t_start = 0, t_done = 0;
+};
+
+struct Round {
+  std::vector<hipEvent_t> evs;
+};
+
+}  // namespace
+
+struct Server {
+  bf_server_config cfg{};
+  int device = 0;
+  Clock::time_point epoch;
+  char* dev_base = nullptr;
+  char* pin_base = nullptr;
+  Arena dev_arena, pin_arena;
+  std::vector<hipStream_t> streams;
+  hipStream_t aux = nullptr;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
+  std::deque<Req*> incoming;
+  std::map<std::tuple<int, int, int>, int> variants;  // (d, R, precision) -> id
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int queued = 0, admitted = 0;
+  bf_server_stats stats{};
+
+  // scheduler-thread state
+  std::multimap<std::pair<double, uint64_t>, Req*> pending;
+  std::vector<Req*> preparing, active, finishing;
+  std::deque<Round> rounds;
+  std::vector<hipEvent_t> event_pool;
+  int fatal = 0;
+  std::string fatal_msg;
+  std::thread worker;
+
+  double now() const {
+    return std::chrono::duration<double>(Clock::now() - epoch).count();
+  }
+
+  hipEvent_t take_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
+  void give_event(hipEvent_t& e) {
+    if (e) event_pool.push_back(e);
+    e = nullptr;
+  }
+
+  void release(Req* r) {
+    if (r->has_dev) dev_arena.release(r->dev_off);
+    if (r->has_pin) pin_arena.release(r->pin_off);
+    r->has_dev = r->has_pin = false;
+    give_event(r->ev_mm);
+    give_event(r->ev_done);
+  }
+
+  // Record the end of a request (caller holds no lock).
+  void finish(Req* r, int state, int error, const std::string& msg) {
+    release(r);
+    std::lock_guard<std::mutex> lk(mu);
+    r->state = state;
+    r->error = error;
+    r->msg = msg;
+    r->t_done = now();
+    --admitted;
+    if (state == BF_REQ_DONE) ++stats.completed;
+    else ++stats.failed;
+    cv_done.notify_all();
+  }
+
+  // First device error: the server fails every request from then on.  Only
+  // the scheduler thread writes these; submit reads them under the mutex.
+  void set_fatal(hipError_t e, const char* what) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (fatal) return;
+    fatal = BF_EDEVICE;
+    fatal_msg = std::string(what) + ": " + hipGetErrorString(e);
+  }
+
+  // ---- preparation ----------------------------------------------------------
+  bool prepare_terms(Req* r, const float* lo, const float* hi) {
+    const int d = r->in.d;
+    int N = r->in.N;
+    if (N == 0 && choose_order(d, r->Wm, lo, hi, &N) != BF_OK) {
+      finish(r, BF_REQ_FAILED, BF_EUNSUPPORTED, bf_last_error());
+      return false;
+    }
+    std::vector<double> w((size_t)r->in.K * d);
+    frequency_table(d, r->Wm, N, r->in.K, r->in.seed, w.data());
+    size_t off_w = 0, off_taps = 0;
+    const std::vector<float> tab =
+        term_table(d, r->in.K, w.data(), nullptr, r->in.sigma_s, &off_w, &off_taps);
+    float* ptab = r->pin + 32;
+    std::memcpy(ptab, tab.data(), tab.size() * sizeof(float));
+    float* dtab = reinterpret_cast<float*>(dev_base + r->dev_off) + r->n_acc;
+    hipError_t e = hipMemcpyAsync(dtab, ptab, tab.size() * sizeof(float), hipMemcpyHostToDevice,
+                                  streams[r->stream]);
+    if (e != hipSuccess) {
+      set_fatal(e, "term table upload");
+      finish(r, BF_REQ_FAILED, BF_EDEVICE, fatal_msg);
+      return false;
+    }
+    r->a.terms = dtab;
+    r->a.weights = nullptr;
+    r->a.taps = dtab + off_taps;
+    for (int m = 0; m < 8; ++m)
+      r->a.cen[m] = (r->in.center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
+    std::lock_guard<std::mutex> lk(mu);
+    r->N_used = N;
+    r->state = BF_REQ_RUNNING;
+    active.push_back(r);
+    return true;
+  }
+
+  bool admit() {
+    bool progress = false;
+    const double t = now();
+    while (!pending.empty() && !fatal) {
+      Req* r = pending.begin()->second;
+      if (r->t_arrival > t || admitted >= cfg.max_active) break;
+      size_t doff = 0, poff = 0;
+      if (!dev_arena.alloc(r->dev_bytes, &doff)) break;  // arrival order: no overtaking
+      if (!pin_arena.alloc(r->pin_bytes, &poff)) {
+        dev_arena.release(doff);
+        break;
+      }
+      pending.erase(pending.begin());
+      r->dev_off = doff;
+      r->pin_off = poff;
+      r->has_dev = r->has_pin = true;
+      float* dev = reinterpret_cast<float*>(dev_base + doff);
+      r->a.acc = dev;
+      r->part = dev + r->n_acc + r->n_tab;
+      r->pin = reinterpret_cast<float*>(pin_base + poff);
+      r->ev_done = take_event();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        --queued;
+        ++admitted;
+        r->state = BF_REQ_PREPARING;
+        r->t_admit = t;
+      }
+      progress = true;
+      if (!r->ev_done) {
+        finish(r, BF_REQ_FAILED, BF_EDEVICE, "hipEventCreate failed");
+        continue;
+      }
+      if (r->need_minmax) {
+        r->ev_mm = take_event();
+        float* res = r->part + (size_t)r->nparts * kMMFloats;
+        hipError_t e = r->ev_mm ? hipSuccess : hipErrorOutOfMemory;
+        if (e == hipSuccess)
+          e = launch_minmax(r->in.f, r->in.H, r->in.W, r->in.pitch, r->in.d, r->part, r->nparts,
+                            res, aux);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(r->pin, res, kMMFloats * sizeof(float), hipMemcpyDeviceToHost, aux);
+        if (e == hipSuccess) e = hipEventRecord(r->ev_mm, aux);
+        if (e != hipSuccess) {
+          set_fatal(e, "min/max reduction");
+          finish(r, BF_REQ_FAILED, BF_EDEVICE, fatal_msg);
+          continue;
+        }
+        preparing.push_back(r);
+      } else {
+        const float zero[8] = {0};
+        prepare_terms(r, zero, zero);
+      }
+    }
+    return progress;
+  }
+
+  bool finish_preparing() {
+    bool progress = false;
+    for (size_t i = 0; i < preparing.size();) {
+      Req* r = preparing[i];
+      const hipError_t q = hipEventQuery(r->ev_mm);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      preparing.erase(preparing.begin() + i);
+      progress = true;
+      if (q != hipSuccess) {
+        set_fatal(q, "min/max reduction");
+        finish(r, BF_REQ_FAILED, BF_EDEVICE, fatal_msg);
+        continue;
+      }
+      const float* h = r->pin;
+      if (h[16] != 0.0f) {
+        finish(r, BF_REQ_FAILED, BF_EINVAL, "f contains NaN or infinity");
+        continue;
+      }
+      prepare_terms(r, h, h + 8);
+    }
+    return progress;
+  }
+
+  // ---- rounds ---------------------------------------------------------------
+  bool enqueue_round() {
+    if (active.empty() || (int)rounds.size() >= cfg.depth || fatal) return false;
+    std::vector<PlanJob> jobs;
+    jobs.reserve(active.size());
+    for (size_t i = 0; i < active.size(); ++i)
+      jobs.push_back(PlanJob{(int)i, active[i]->variant, active[i]->next_t, active[i]->in.K,
+                             active[i]->cost_term});
+    const std::vector<PlanLaunch> plan = plan_round(jobs, cfg.quantum_us, kMaxBatch);
+    std::set<int> used;
+    std::vector<Req*> ended;
+    const double t = now();
+    uint64_t wgs = 0;
+    for (const PlanLaunch& L : plan) {
+      BatchArgs b{};
+      b.n = (int)L.items.size();
+      b.first[0] = 0;
+      Req* r0 = active[L.items[0].job];
+      for (int k = 0; k < b.n; ++k) {
+        Req* r = active[L.items[k].job];
+        b.req[k] = r->a;
+        b.req[k].t0 = L.items[k].t0;
+        b.req[k].t1 = L.items[k].t1;
+        b.first[k + 1] = b.first[k] + r->a.nsx * r->a.nsy;
+      }
+      hipStream_t st = streams[r0->stream];
+      hipError_t e = launch_fused_batch(r0->in.d, r0->R, r0->in.precision, b, st);
+      if (e != hipSuccess) {
+        set_fatal(e, "batched fused launch");
+        return true;
+      }
+      wgs += (uint64_t)b.first[b.n];
+      used.insert(r0->stream);
+      for (const PlanItem& it : L.items) {
+        Req* r = active[it.job];
+        r->next_t = it.t1;
+        if (r->next_t < r->in.K) continue;
+        FinalizeArgs fa{};
+        fa.acc = r->a.acc;
+        fa.out = r->in.out;
+        for (int m = 0; m < 8; ++m) fa.cen[m] = r->a.cen[m];
+        fa.H = r->in.H;
+        fa.W = r->in.W;
+        fa.Hp = r->a.Hp;
+        fa.Wp = r->a.nsx * kTW;
+        e = launch_finalize(r->in.d, fa, st);
+        if (e == hipSuccess) e = hipEventRecord(r->ev_done, st);
+        if (e != hipSuccess) {
+          set_fatal(e, "finalize launch");
+          return true;
+        }
+        ended.push_back(r);
+      }
+    }
+    Round rd;
+    for (int s : used) {
+      hipEvent_t ev = take_event();
+      if (!ev || hipEventRecord(ev, streams[s]) != hipSuccess) {
+        set_fatal(hipErrorUnknown, "round event");
+        give_event(ev);
+        break;
+      }
+      rd.evs.push_back(ev);
+    }
+    rounds.push_back(std::move(rd));
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (const PlanLaunch& L : plan)
+        for (const PlanItem& it : L.items) {
+          Req* r = active[it.job];
+          ++r->chunks;
+          if (r->t_start == 0.0) r->t_start = t;
+        }
+      ++stats.rounds;
+      stats.launches += plan.size();
+      stats.workgroups += wgs;
+    }
+    for (Req* r : ended) finishing.push_back(r);
+    std::vector<Req*> still;
+    still.reserve(active.size());
+    for (Req* r : active)
+      if (r->next_t < r->in.K) still.push_back(r);
+    active.swap(still);
+    return true;
+  }
+
+  bool reap_rounds() {
+    bool progress = false;
+    while (!rounds.empty()) {
+      Round& rd = rounds.front();
+      bool done = true;
+      for (hipEvent_t ev : rd.evs) {
+        const hipError_t q = hipEventQuery(ev);
+        if (q == hipErrorNotReady) {
+          done = false;
+          break;
+        }
+        if (q != hipSuccess) set_fatal(q, "round");
+      }
+      if (!done) break;
+      for (hipEvent_t& ev : rd.evs) give_event(ev);
+      rounds.pop_front();
+      progress = true;
+    }
+    return progress;
+  }
+
+  bool reap_done() {
+    bool progress = false;
+    for (size_t i = 0; i < finishing.size();) {
+      Req* r = finishing[i];
+      const hipError_t q = hipEventQuery(r->ev_done);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      finishing.erase(finishing.begin() + i);
+      progress = true;
+      if (q != hipSuccess) {
+        set_fatal(q, "request completion");
+        finish(r, BF_REQ_FAILED, BF_EDEVICE, fatal_msg);
+      } else {
+        finish(r, BF_REQ_DONE, BF_OK, "");
+      }
+    }
+    return progress;
+  }
+
+  // After a device error: wait for what was queued, then fail everything.
+  void fail_all() {
+    for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(aux);
+    for (Round& rd : rounds)
+      for (hipEvent_t& ev : rd.evs) give_event(ev);
+    rounds.clear();
+    std::vector<Req*> all;
+    for (auto* v : {&preparing, &active, &finishing}) {
+      all.insert(all.end(), v->begin(), v->end());
+      v->clear();
+    }
+    for (Req* r : all) finish(r, BF_REQ_FAILED, fatal, fatal_msg);
+    for (auto& kv : pending) {
+      std::lock_guard<std::mutex> lk(mu);
+      Req* r = kv.second;
+      r->state = BF_REQ_FAILED;
+      r->error = fatal;
+      r->msg = fatal_msg;
+      --queued;
+      ++stats.failed;
+    }
+    pending.clear();
+    std::lock_guard<std::mutex> lk(mu);
+    cv_done.notify_all();
+  }
+
+  void run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+      bool stopping;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        while (!incoming.empty()) {
+          Req* r = incoming.front();
+          incoming.pop_front();
+          pending.emplace(std::make_pair(r->t_arrival, r->ticket), r);
+        }
+        stopping = stop;
+      }
+      if (stopping && !pending.empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : pending) {
+          kv.second->state = BF_REQ_CANCELLED;
+          --queued;
+        }
+        pending.clear();
+        cv_done.notify_all();
+      }
+      if (fatal) fail_all();
+      const bool busy = !preparing.empty() || !active.empty() || !finishing.empty() ||
+                        !rounds.empty();
+      if (stopping && !busy) break;
+      bool progress = reap_done();
+      progress |= reap_rounds();
+      progress |= finish_preparing();
+      progress |= admit();
+      progress |= enqueue_round();
+      if (progress) continue;
+      if (busy) {
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        continue;
+      }
+      // idle: sleep until a submission, the next arrival, or stop
+      std::unique_lock<std::mutex> lk(mu);
+      if (!incoming.empty() || stop) continue;
+      if (pending.empty()) {
+        cv_work.wait(lk, [&] { return !incoming.empty() || stop; });
+      } else {
+        const double wait_s = pending.begin()->first.first - now();
+        if (wait_s > 0)
+          cv_work.wait_for(lk, std::chrono::duration<double>(std::min(wait_s, 1.0)));
+      }
+    }
+  }
+
+  void fill_status(const Req* r, bf_request_status* st) const {
+    std::memset(st, 0, sizeof(*st));
+    st->state = r->state;
+    st->error = r->error;
+    st->N_used = r->N_used;
+    st->chunks = r->chunks;
+    st->arrival = r->t_arrival;
+    st->admitted = r->t_admit;
+    st->started = r->t_start;
+    st->done = r->t_done;
+    std::strncpy(st->message, r->msg.c_str(), sizeof(st->message) - 1);
+  }
+};
+
+namespace {
+
+bool ended(int state) {
+  return state == BF_REQ_DONE || state == BF_REQ_FAILED || state == BF_REQ_CANCELLED;
+}
+
+int hip_err(hipError_t e, const char* what) {
+  return fail(BF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Validate a request and plan its launch geometry and footprint.
+int plan_request(Server* s, const bf_request* q, Req* r) {
+  if (!q) return fail(BF_EINVAL, "req must be non-null");
+  r->in = *q;
+  bf_request& in = r->in;
+  if (in.pitch == 0) in.pitch = in.W;
+  if (!in.f || !in.out) return fail(BF_EINVAL, "f and out must be non-null device pointers");
+  if (in.H < 1 || in.W < 1 || in.H > 65536 || in.W > 65536)
+    return fail(BF_EINVAL, "H and W must be in [1, 65536]");
+  if (in.d < 1 || in.d > 8) return fail(BF_EINVAL, "d must be in [1, 8]");
+  if (in.pitch < in.W) return fail(BF_EINVAL, "pitch must be 0 or >= W");
+  if (!std::isfinite(in.sigma_s) || in.sigma_s < 0.0 || in.sigma_s > 32.0)
+    return fail(BF_EINVAL, "sigma_s must be finite and in [0, 32]");
+  if (in.K < 1 || in.K > 65536) return fail(BF_EINVAL, "K must be in [1, 65536]");
+  if (in.N < 0 || in.N > 65536) return fail(BF_EINVAL, "N must be 0 (auto) or in [1, 65536]");
+  if (in.precision != BF_FP32 && in.precision != BF_FP16 && in.precision != BF_BF16)
+    return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
+  if (in.center != 0 && in.center != 1) return fail(BF_EINVAL, "center must be 0 or 1");
+  if (!in.C) return fail(BF_EINVAL, "C must be non-null");
+  if (!std::isfinite(in.arrival)) return fail(BF_EINVAL, "arrival must be finite");
+  {
+    const size_t fbytes = (((size_t)in.H - 1) * in.pitch + in.W) * in.d * sizeof(float);
+    const size_t obytes = (size_t)in.H * in.W * in.d * sizeof(float);
+    const char* a = (const char*)in.f;
+    const char* b = (const char*)in.out;
+    if (a < b + obytes && b < a + fbytes) return fail(BF_EINVAL, "out must not overlap f");
+  }
+  std::memcpy(r->Cm, in.C, sizeof(double) * in.d * in.d);
+  in.C = r->Cm;
+  int rc = whiten(in.d, r->Cm, r->Wm);
+  if (rc) return rc;
+  r->R = window_radius(in.sigma_s);
+  if ((rc = check_fused_size(in.H, in.W, in.pitch, in.d, r->R))) return rc;
+  int TH = 0;
+  {
+    // occupancy queries need the server's device current on this thread
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != s->device) e = hipSetDevice(s->device);
+    if (e != hipSuccess) return hip_err(e, "hipSetDevice");
+    rc = choose_strip_height(in.d, r->R, in.precision, in.H, in.W, 0, &TH);
+    if (cur != s->device) (void)hipSetDevice(cur);
+    if (rc) return rc;
+  }
+  fused_geometry(r->a, in.H, in.W, r->R, in.precision, TH);
+  r->a.f = in.f;
+  r->a.fpitch = in.pitch;
+  r->n_acc = fused_acc_floats(r->a, in.d);
+  r->n_tab = (size_t)in.K * (in.d + 1) + (size_t)(2 * r->R + 1);
+  r->need_minmax = in.N == 0 || in.center;
+  r->nparts = minmax_parts((size_t)in.H * in.W);
+  const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMFloats : 0;
+  r->dev_bytes = Arena::round_up((r->n_acc + r->n_tab) * sizeof(float), kAlign) +
+                 Arena::round_up(n_part * sizeof(float), kAlign);
+  r->pin_bytes = (32 + r->n_tab) * sizeof(float);
+  r->cost_term = model_term_us(r->a, in.d, in.precision);
+  if (!s->dev_arena.fits_ever(r->dev_bytes))
+    return fail(BF_ENOMEM, "request footprint exceeds the server's device arena");
+  if (!s->pin_arena.fits_ever(r->pin_bytes))
+    return fail(BF_ENOMEM, "request term table exceeds the server's host staging");
+  return BF_OK;
+}
+
+Req* find(Server* s, uint64_t ticket) {
+  auto it = s->reqs.find(ticket);
+  return it == s->reqs.end() ? nullptr : it->second.get();
+}
+
+}  // namespace
+}  // namespace bfvec
+
+struct bf_server : bfvec::Server {};
+
+using namespace bfvec;
+
+extern "C" {
+
+void bf_server_config_init(bf_server_config* cfg) {
+  if (cfg) std::memset(cfg, 0, sizeof(*cfg));
+}
+
+void bf_request_init(bf_request* req) {
+  if (!req) return;
+  std::memset(req, 0, sizeof(*req));
+  req->precision = BF_FP16;
+  req->center = 1;
+}
+
+int bf_server_create(const bf_server_config* cfg_in, bf_server** out) {
+  clear_error();
+  if (!out) return fail(BF_EINVAL, "srv must be non-null");
+  *out = nullptr;
+  bf_server_config cfg{};
+  if (cfg_in) cfg = *cfg_in;
+  if (cfg.arena_bytes == 0) cfg.arena_bytes = 8ull << 30;
+  if (cfg.max_active == 0) cfg.max_active = 64;
+  if (cfg.streams == 0) cfg.streams = 4;
+  if (cfg.depth == 0) cfg.depth = 2;
+  if (cfg.quantum_us == 0.0) cfg.quantum_us = 2000.0;
+  if (cfg.max_active < 1 || cfg.max_queued < 0 || cfg.streams < 1 || cfg.streams > 16 ||
+      cfg.depth < 1 || !(cfg.quantum_us > 0.0) || cfg.arena_bytes < (1u << 20))
+    return fail(BF_EINVAL, "bad server configuration");
+  auto s = std::make_unique<bf_server>();
+  s->cfg = cfg;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  // host staging: one term table per admitted request at most K = 65536, d = 8
+  const size_t pin_bytes = (size_t)cfg.max_active * 4096 * 10 * sizeof(float) + (64u << 20);
+  e = hipMalloc((void**)&s->dev_base, cfg.arena_bytes);
+  if (e != hipSuccess) return fail(BF_ENOMEM, "device arena allocation failed");
+  e = hipHostMalloc((void**)&s->pin_base, pin_bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipFree(s->dev_base);
+    return fail(BF_ENOMEM, "pinned staging allocation failed");
+  }
+  s->dev_arena.reset(cfg.arena_bytes, kAlign);
+  s->pin_arena.reset(pin_bytes, kAlign);
+  for (int i = 0; i <= cfg.streams && e == hipSuccess; ++i) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) (i < cfg.streams ? s->streams.push_back(st) : (void)(s->aux = st));
+  }
+  if (e != hipSuccess) {
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    (void)hipFree(s->dev_base);
+    (void)hipHostFree(s->pin_base);
+    return hip_err(e, "hipStreamCreate");
+  }
+  s->stats.arena_bytes = cfg.arena_bytes;
+  s->epoch = Clock::now();
+  Server* raw = s.get();
+  s->worker = std::thread([raw] { raw->run(); });
+  *out = s.release();
+  return BF_OK;
+}
+
+int bf_server_submit(bf_server* s, const bf_request* q, uint64_t* ticket) {
+  clear_error();
+  if (!s || !ticket) return fail(BF_EINVAL, "srv and ticket must be non-null");
+  auto r = std::make_unique<Req>();
+  int rc = plan_request(s, q, r.get());
+  if (rc) return rc;
+  const double t = s->now();
+  r->t_arrival = r->in.arrival > 0.0 ? r->in.arrival : t;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return fail(BF_EINVAL, "server is shutting down");
+  if (s->fatal) return fail(s->fatal, s->fatal_msg);
+  if (s->cfg.max_queued > 0 && s->queued >= s->cfg.max_queued)
+    return fail(BF_EBUSY, "serving queue full");
+  const auto key = std::make_tuple(r->in.d, r->R, r->in.precision);
+  auto it = s->variants.find(key);
+  if (it == s->variants.end()) it = s->variants.emplace(key, (int)s->variants.size()).first;
+  r->variant = it->second;
+  r->stream = r->variant % s->cfg.streams;
+  r->ticket = s->next_ticket++;
+  *ticket = r->ticket;
+  Req* raw = r.get();
+  s->reqs.emplace(r->ticket, std::move(r));
+  s->incoming.push_back(raw);
+  ++s->queued;
+  ++s->stats.submitted;
+  s->cv_work.notify_one();
+  return BF_OK;
+}
+
+int bf_server_poll(bf_server* s, uint64_t ticket, bf_request_status* st) {
+  clear_error();
+  if (!s || !st) return fail(BF_EINVAL, "srv and st must be non-null");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Req* r = find(s, ticket);
+  if (!r) return fail(BF_EINVAL, "unknown ticket");
+  s->fill_status(r, st);
+  return BF_OK;
+}
+
+int bf_server_wait(bf_server* s, uint64_t ticket, double timeout_s, bf_request_status* st) {
+  clear_error();
+  if (!s) return fail(BF_EINVAL, "srv must be non-null");
+  std::unique_lock<std::mutex> lk(s->mu);
+  Req* r = find(s, ticket);
+  if (!r) return fail(BF_EINVAL, "unknown ticket");
+  auto done = [&] { return ended(r->state); };
+  bool ok = true;
+  if (timeout_s < 0) s->cv_done.wait(lk, done);
+  else ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done);
+  if (st) s->fill_status(r, st);
+  if (!ok) return fail(BF_ETIMEDOUT, "request still in flight");
+  return BF_OK;
+}
+
+int bf_server_drain(bf_server* s, double timeout_s) {
+  clear_error();
+  if (!s) return fail(BF_EINVAL, "srv must be non-null");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto done = [&] {
+    for (auto& kv : s->reqs)
+      if (!ended(kv.second->state)) return false;
+    return true;
+  };
+  bool ok = true;
+  if (timeout_s < 0) s->cv_done.wait(lk, done);
+  else ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done);
+  if (!ok) return fail(BF_ETIMEDOUT, "requests still in flight");
+  return BF_OK;
+}
+
+int bf_server_forget(bf_server* s, uint64_t ticket) {
+  clear_error();
+  if (!s) return fail(BF_EINVAL, "srv must be non-null");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(BF_EINVAL, "unknown ticket");
+  if (!ended(it->second->state)) return fail(BF_EBUSY, "request has not ended");
+  s->reqs.erase(it);
+  return BF_OK;
+}
+
+int bf_server_get_stats(bf_server* s, bf_server_stats* out) {
+  clear_error();
+  if (!s || !out) return fail(BF_EINVAL, "srv and stats must be non-null");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  out->arena_peak = s->dev_arena.peak();
+  out->admitted = s->admitted;
+  out->queued = s->queued;
+  return BF_OK;
+}
+
+double bf_server_clock(const bf_server* s) { return s ? s->now() : 0.0; }
+
+int bf_server_destroy(bf_server* s) {
+  clear_error();
+  if (!s) return BF_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  if (s->aux) (void)hipStreamSynchronize(s->aux);
+  for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  if (s->aux) (void)hipStreamDestroy(s->aux);
+  (void)hipFree(s->dev_base);
+  (void)hipHostFree(s->pin_base);
+  delete s;
+  return BF_OK;
+}
+
+}  // extern "C"

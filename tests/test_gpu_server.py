@@ -1,0 +1,172 @@
+"""GPU tests of the continuous-batching server: every request's result equals
+the same filter run alone through bf_vec_ex, bit for bit, when it is chunked
+into many rounds and batched with requests of other sizes, dimensions,
+windows and precisions; plus status, arrival and error behaviour."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1605_02164_amd as P  # noqa: E402
+from paper_1605_02164_amd import bfvec as B  # noqa: E402
+from synth import voronoi_image, feature_image, random_spd  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def pools():
+    f3 = voronoi_image(256, 300, 3, 24, 0.0, 1.0, 0.02, seed=71)
+    f6 = feature_image(160, 176, 12, seed=72, smooth_sigma=8.0)
+    return torch.from_numpy(f3).to(DEV), torch.from_numpy(f6).to(DEV)
+
+
+# (pool, y0, x0, H, W, sigma_s, K, N, precision, center, cov)
+MIX = [
+    (3, 0, 0, 256, 300, 5.0, 32, 0, "fp16", True, "iso"),
+    (3, 13, 7, 100, 61, 2.0, 17, 0, "fp32", True, "iso"),
+    (3, 40, 200, 1, 37, 1.0, 5, 0, "fp16", True, "iso"),
+    (3, 5, 9, 37, 1, 2.0, 9, 12, "bf16", False, "iso"),
+    (6, 0, 0, 160, 176, 3.4, 24, 0, "fp16", True, "spd"),
+    (6, 9, 21, 70, 50, 2.0, 11, 0, "fp32", False, "spd"),
+    (3, 100, 33, 150, 211, 8.0, 20, 0, "fp16", True, "iso"),
+    (3, 77, 41, 64, 48, 13.0, 3, 0, "fp32", True, "iso"),
+    (6, 31, 3, 33, 17, 0.0, 4, 0, "bf16", True, "spd"),
+    (3, 1, 1, 200, 250, 10.0, 12, 0, "fp16", True, "iso"),
+]
+
+
+def _cov(kind, d):
+    return 0.05 ** 2 * np.eye(d) if kind == "iso" else random_spd(d, -2.5, -1.0, seed=5)
+
+
+def _crop(pools, spec):
+    pool, y0, x0, H, W = spec[:5]
+    f = pools[0] if pool == 3 else pools[1]
+    return f[y0:y0 + H, x0:x0 + W, :]
+
+
+def _alone(fc, spec):
+    _, _, _, _, _, s, K, N, prec, center, cov = spec
+    d = fc.shape[2]
+    out, n = P.bf_vec_ex(fc.contiguous(), s, _cov(cov, d), K, seed=1000 + K, N=N,
+                         precision=prec, center=center)
+    torch.cuda.synchronize()
+    return out, n
+
+
+def test_mix_matches_standalone_bitwise(pools):
+    alone = []
+    for spec in MIX:
+        alone.append(_alone(_crop(pools, spec), spec))
+    # a small quantum splits every request into many chunks and rounds
+    with P.Server(arena_bytes=1 << 30, streams=3, depth=2, quantum_us=20.0) as srv:
+        tickets = []
+        for spec in MIX:
+            fc = _crop(pools, spec)
+            _, _, _, _, _, s, K, N, prec, center, cov = spec
+            print("submit", spec, flush=True)
+            t, out = srv.submit(fc, s, _cov(cov, fc.shape[2]), K, seed=1000 + K, N=N,
+                                precision=prec, center=center)
+            tickets.append((t, out))
+        srv.drain(timeout=60.0)
+        stats = srv.stats()
+        for spec, (t, out), (ref, n_ref) in zip(MIX, tickets, alone):
+            st = srv.poll(t)
+            assert st["state"] == "done", (spec, st)
+            assert st["N_used"] == n_ref, spec
+            assert torch.equal(out, ref), (spec, float((out - ref).abs().max()))
+        assert max(srv.poll(t)["chunks"] for t, _ in tickets) > 3
+        assert stats["completed"] == len(MIX) and stats["failed"] == 0
+        assert stats["rounds"] >= 4 and stats["launches"] >= stats["rounds"]
+
+
+def test_batched_launches_share_requests(pools):
+    # many small requests of one instance: fewer launches than requests
+    f = pools[0]
+    C = 0.05 ** 2 * np.eye(3)
+    specs = [(3 + 7 * i % 50, 2 + 11 * i % 60, 9 + i % 13, 20 + i % 17) for i in range(40)]
+    with P.Server(arena_bytes=1 << 28, max_active=64, quantum_us=1e6) as srv:
+        start = srv.clock() + 0.2   # all arrive together, after submission
+        tickets = []
+        for (y0, x0, H, W) in specs:
+            t, out = srv.submit(f[y0:y0 + H, x0:x0 + W], 2.0, C, 6, seed=9, arrival=start)
+            tickets.append((t, out))
+        srv.drain(timeout=60.0)
+        stats = srv.stats()
+        assert stats["completed"] == 40
+        assert stats["launches"] < 40, stats
+        for (y0, x0, H, W), (t, out) in list(zip(specs, tickets))[::7]:
+            ref, _ = P.bf_vec_ex(f[y0:y0 + H, x0:x0 + W].contiguous(), 2.0, C, 6, seed=9,
+                                 precision="fp16")
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref)
+            st = srv.poll(t)
+            assert st["admitted"] >= start and st["done"] >= st["admitted"]
+            srv.forget(t)
+            with pytest.raises(B.BfError):
+                srv.poll(t)
+
+
+def test_arrival_in_future_and_cancel_on_close(pools):
+    f = pools[0][:64, :64]
+    C = 0.05 ** 2 * np.eye(3)
+    srv = P.Server(arena_bytes=1 << 28)
+    t0 = srv.clock()
+    t1, _ = srv.submit(f, 2.0, C, 4, seed=3, arrival=t0 + 0.3)
+    t2, _ = srv.submit(f, 2.0, C, 4, seed=3, arrival=t0 + 3600.0)
+    st = srv.wait(t1, timeout=30.0)
+    assert st["state"] == "done"
+    assert st["admitted"] >= t0 + 0.3 - 1e-6
+    assert srv.poll(t2)["state"] == "queued"
+    with pytest.raises(B.BfError) as e:
+        srv.wait(t2, timeout=0.05)
+    assert e.value.code == B.BF_ETIMEDOUT
+    srv.close()   # cancels the request that has not arrived
+
+
+def test_submit_errors(pools):
+    f = pools[0][:32, :32]
+    C = 0.05 ** 2 * np.eye(3)
+    with P.Server(arena_bytes=1 << 20) as srv:
+        with pytest.raises(B.BfError) as e:
+            srv.submit(f, 14.0, C, 4, seed=1)           # R = 42 > 40
+        assert e.value.code == B.BF_EUNSUPPORTED
+        with pytest.raises(B.BfError) as e:
+            srv.submit(f, 2.0, -C, 4, seed=1)           # not SPD
+        assert e.value.code == B.BF_ENOTSPD
+        with pytest.raises(B.BfError) as e:
+            srv.submit(f, 2.0, C, 0, seed=1)            # K = 0
+        assert e.value.code == B.BF_EINVAL
+        with pytest.raises(B.BfError) as e:
+            srv.submit(pools[0], 2.0, C, 4, seed=1)   # 1.2 MB of accumulators > 1 MiB arena
+        assert e.value.code == B.BF_ENOMEM
+        with pytest.raises(ValueError):
+            srv.submit(f, 2.0, C, 4, seed=1, out=torch.empty(31, 32, 3, device=DEV))
+        overlap = pools[0].reshape(-1)[:32 * 32 * 3].view(32, 32, 3)
+        with pytest.raises(B.BfError) as e:
+            srv.submit(f, 2.0, C, 4, seed=1, out=overlap)   # out overlaps f
+        assert e.value.code == B.BF_EINVAL
+        t, _ = srv.submit(f, 2.0, C, 4, seed=1)
+        assert srv.wait(t, timeout=30.0)["state"] == "done"
+        assert srv.stats()["failed"] == 0
+
+
+def test_nan_request_fails_alone(pools):
+    f = pools[0][:40, :40].clone()
+    f[5, 7, 1] = float("nan")
+    good = pools[0][40:80, :40]
+    C = 0.05 ** 2 * np.eye(3)
+    with P.Server(arena_bytes=1 << 28) as srv:
+        tb, _ = srv.submit(f, 2.0, C, 4, seed=1)
+        tg, out = srv.submit(good, 2.0, C, 4, seed=1)
+        sb = srv.wait(tb, timeout=30.0)
+        sg = srv.wait(tg, timeout=30.0)
+        assert sb["state"] == "failed" and sb["error"] == B.BF_EINVAL and "NaN" in sb["message"]
+        assert sg["state"] == "done"
+        ref, _ = P.bf_vec_ex(good.contiguous(), 2.0, C, 4, seed=1, precision="fp16")
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
