@@ -26,6 +26,36 @@ PEAK_FP32_VALU = 157.3      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (packed) x
 PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: the same without packed-FP32 issue
 
 
+# HBM bytes per launch of the benchmark's fused kernel, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
+# counters read for a 1 GiB device copy (FETCH_SIZE 524,307 KiB: factor
+# 1.99993; WRITE_SIZE 1,048,576 KiB: factor 1.0).  Valid only for the kernel
+# sources they were taken on (TRAFFIC_SOURCES hash); otherwise reported null.
+TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
+                   "paper_1605_02164_amd/csrc/mcsf_common.h",
+                   "paper_1605_02164_amd/csrc/api.hip"]
+TRAFFIC = {
+    "sha256": "761b48f31bd19a4abb03c11de7b005d045802105e19565486c7f15c44f5a62a4",
+    "fp32": {"fetch_kib": 93608406, "write_kib": 67433176},
+    "fp16": {"fetch_kib": 121065135, "write_kib": 70316061},
+    "fetch_factor": 1048576 / 524307,
+    "write_factor": 1.0,
+}
+
+
+def measured_traffic(prec):
+    """HBM bytes per launch for the current kernel sources, or None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"] or prec not in TRAFFIC:
+        return None
+    t = TRAFFIC[prec]
+    return (t["fetch_kib"] * TRAFFIC["fetch_factor"] + t["write_kib"] * TRAFFIC["write_factor"]) * 1024
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -298,7 +328,10 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU,
             "frac_vs_nonpacked_fma": achieved / PEAK_FP32_NONPACKED,
-            "traffic": None,
+            "traffic": measured_traffic(args.precision),
+            "traffic_unit": "bytes per launch",
+            "hbm_tb_s": (None if measured_traffic(args.precision) is None else
+                         measured_traffic(args.precision) / (kernel_ms * 1e-3) / 1e12),
             "flops_per_launch": flops,
             "kernel_ms": kernel_ms,
         },
