@@ -33,9 +33,9 @@ PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: the same without packed-FP32 issue
 # sources they were taken on (TRAFFIC_SOURCES hash); otherwise reported null.
 TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
-                   "paper_1605_02164_amd/csrc/api.hip"]
+                   "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "761b48f31bd19a4abb03c11de7b005d045802105e19565486c7f15c44f5a62a4",
+    "sha256": "530f4ed5261096aa9c5c4440bcc808a1d63c67a3ad20c6efef7cd8af9f432104",
     "fp32": {"fetch_kib": 93608406, "write_kib": 67433176},
     "fp16": {"fetch_kib": 121065135, "write_kib": 70316061},
     "fetch_factor": 1048576 / 524307,
@@ -246,33 +246,37 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def step(prec, dst):
+    def step(prec, dst, dedup):
         _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=dst, precision=prec,
-                           stream=stream, time_kernel=True, return_opts=True)
-        return o.N_used, o.kernel_ms
+                           stream=stream, time_kernel=True, return_opts=True, dedup=dedup)
+        return o.N_used, o.kernel_ms, o.K_used
 
-    flops = algorithmic_flops_per_pixel(d, R, K) * H * W
-
-    def run(prec, dst):
+    def run(mode, dst):
+        prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
         for _ in range(args.warmup):
-            step(prec, dst)
+            step(prec, dst, dedup)
         torch.cuda.synchronize()
         kms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            N, ms = step(prec, dst)
+            N, ms, K_used = step(prec, dst, dedup)
             kms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         kernel_ms = float(np.mean(kms))
+        # flops of the terms the kernel actually ran
+        flops_run = algorithmic_flops_per_pixel(d, R, K_used) * H * W
         rec = {"value": H * W * args.steps / dt / 1e6, "ms_per_step": 1e3 * dt / args.steps,
-               "kernel_ms": kernel_ms, "achieved_tflops": flops / (kernel_ms * 1e-3) / 1e12, "N": N}
-        log(f"{prec}: N={N} step {rec['ms_per_step']:.2f} ms, kernel {kernel_ms:.2f} ms, "
-            f"{rec['achieved_tflops']:.2f} TFLOP/s algorithmic, {rec['value']:.2f} Mpix/s")
+               "kernel_ms": kernel_ms, "achieved_tflops": flops_run / (kernel_ms * 1e-3) / 1e12,
+               "N": N, "K_used": K_used}
+        log(f"{mode}: N={N} K_used={K_used} step {rec['ms_per_step']:.2f} ms, kernel "
+            f"{kernel_ms:.2f} ms, {rec['achieved_tflops']:.2f} TFLOP/s algorithmic, "
+            f"{rec['value']:.2f} Mpix/s")
         return rec
 
+    flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
-        [q for q in ("fp32", "fp16", "bf16") if q != args.precision]
+        [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + ["fp32_dedup", "fp16_dedup"]
     results, outs = {}, {}
     for prec in precs:
         outs[prec] = torch.empty_like(fg)
@@ -290,6 +294,7 @@ def main():
                 results[prec]["max_dev_vs_fp32"] = float(diff.max())
                 results[prec]["mean_dev_vs_fp32"] = float(diff.mean())
     value, kernel_ms, achieved = main_rec["value"], main_rec["kernel_ms"], main_rec["achieved_tflops"]
+    assert main_rec["K_used"] == K
     dt = main_rec["ms_per_step"] * args.steps / 1e3
 
     serving = None

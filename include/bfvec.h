@@ -71,7 +71,13 @@ typedef struct bf_opts {
   int time_kernel; /* 1: time the fused kernel with HIP events on `stream` and
                       wait for it (fills kernel_ms); 0 (default): no timing      */
   float kernel_ms; /* OUT: fused-kernel duration in ms when time_kernel = 1     */
-  int reserved[5];
+  int dedup;       /* 1: merge draws with equal Y or equal -Y into one weighted
+                      term before filtering (bf_vec_ex only).  Exact in
+                      arithmetic: a term's real part is even in Y, so the sum
+                      over the K draws equals the multiplicity-weighted sum over
+                      the distinct +-Y.  0 (default): K terms as drawn          */
+  int K_used;      /* OUT: terms the kernel ran (K, or the distinct +-Y count)  */
+  int reserved[3];
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,

@@ -54,7 +54,9 @@ class bf_opts(ctypes.Structure):
         ("N_used", ctypes.c_int),
         ("time_kernel", ctypes.c_int),
         ("kernel_ms", ctypes.c_float),
-        ("reserved", ctypes.c_int * 5),
+        ("dedup", ctypes.c_int),
+        ("K_used", ctypes.c_int),
+        ("reserved", ctypes.c_int * 3),
     ]
 
 
@@ -198,7 +200,7 @@ def _check_image(f, out):
 
 
 def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
-              num_out=None, z_out=None, time_kernel=False):
+              num_out=None, z_out=None, time_kernel=False, dedup=False):
     o = bf_opts()
     lib().bf_opts_init(ctypes.byref(o))
     o.N = int(N)
@@ -209,6 +211,7 @@ def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
     o.num_out = None if num_out is None else num_out.data_ptr()
     o.z_out = None if z_out is None else z_out.data_ptr()
     o.time_kernel = 1 if time_kernel else 0
+    o.dedup = 1 if dedup else 0
     return o
 
 
@@ -231,16 +234,17 @@ def bf_vec(f, sigma_s, C, K, seed, out=None):
 
 def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
               tile_h=0, stream=None, num_out=None, z_out=None, time_kernel=False,
-              return_opts=False):
+              return_opts=False, dedup=False):
     """The filter with options, queued on ``stream`` (torch stream; default:
     current stream).  Returns (out, N_used), or (out, opts) with
     ``return_opts`` (opts.kernel_ms holds the fused-kernel time when
-    ``time_kernel`` is set)."""
+    ``time_kernel`` is set; opts.K_used the number of kernel terms, fewer than
+    K with ``dedup``)."""
     out = _check_image(f, out)
     H, W, d = f.shape
     Ch = _host_f64(C, (d, d))
     o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  time_kernel)
+                  time_kernel, dedup)
     _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
     return (out, o) if return_opts else (out, o.N_used)

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -17,7 +19,6 @@ namespace bfvec {
 
 namespace {
 
-constexpr size_t kLdsLimit = 160 * 1024;
 
 int hip_fail(hipError_t e, const char* what) {
   return fail(BF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -137,45 +138,6 @@ int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStr
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Strip height.  Each workgroup streams one strip per term and recomputes 2R
-// halo rows per strip, so tall strips waste less; but all compute units
-// should be busy (two workgroups fit on a CU).  Choose the number of strips
-// down the image that minimises (waves of workgroups) x (rows per strip incl.
-// halo).
-// ---------------------------------------------------------------------------
-
-int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH) {
-  if (fused_lds_bytes(d, R, prec) > kLdsLimit)
-    return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
-  if (requested > 0) {
-    *TH = (requested + kB - 1) / kB * kB;
-    return BF_OK;
-  }
-  const int nsx = (W + kTW - 1) / kTW;
-  // resident workgroups on the GPU
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess)
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int slots = fused_blocks_per_cu(d, R, prec) * std::max(ncu, 1);
-  const int halo = lag_steps(R) * kB;
-  long best = -1;
-  int best_th = kB;
-  for (int nsy = 1; nsy <= (H + kB - 1) / kB; ++nsy) {
-    const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
-    const long nwg = (long)nsx * ((H + th - 1) / th);
-    const long waves = (nwg + slots - 1) / slots;
-    const long cost = waves * (th + halo);
-    if (best < 0 || cost < best) {
-      best = cost;
-      best_th = th;
-    }
-    if (nwg > 16L * slots) break;
-  }
-  *TH = best_th;
-  return BF_OK;
-}
-
 namespace {
 
 int check_opts(const bf_opts* o) {
@@ -184,6 +146,7 @@ int check_opts(const bf_opts* o) {
     return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16 or BF_BF16");
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
+  if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
   return BF_OK;
 }
 
@@ -247,6 +210,39 @@ void frequency_table(int d, const double* Wm, int N, int K, uint64_t seed, doubl
       w[(size_t)t * d + j] = s / sqn;
     }
   }
+}
+
+void distinct_terms(int d, const double* Wm, int N, int K, uint64_t seed, std::vector<double>* w,
+                    std::vector<double>* weight) {
+  // key: Y with the sign of its first nonzero entry made positive
+  std::map<std::array<int, 8>, size_t> index;
+  std::vector<std::array<int, 8>> keys;
+  w->clear();
+  weight->clear();
+  for (int t = 0; t < K; ++t) {
+    std::array<int, 8> Y{};
+    for (int m = 0; m < d; ++m) Y[m] = N - 2 * binomial_draw(seed, t, m, N);
+    int s = 0;
+    for (int m = 0; m < d && s == 0; ++m) s = Y[m] > 0 ? 1 : (Y[m] < 0 ? -1 : 0);
+    if (s < 0)
+      for (int m = 0; m < d; ++m) Y[m] = -Y[m];
+    auto it = index.find(Y);
+    if (it != index.end()) {
+      (*weight)[it->second] += 1.0;
+      continue;
+    }
+    index.emplace(Y, keys.size());
+    keys.push_back(Y);
+    weight->push_back(1.0);
+  }
+  const double sqn = std::sqrt((double)N);
+  w->resize(keys.size() * d);
+  for (size_t u = 0; u < keys.size(); ++u)
+    for (int j = 0; j < d; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) s += (double)keys[u][k] * Wm[k * d + j];
+      (*w)[u * d + j] = s / sqn;
+    }
 }
 
 namespace {
@@ -412,8 +408,16 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   int N = o->N;
   if (N == 0 && (rc = choose_order(d, Wm, lo, hi, &N))) return rc;
   o->N_used = N;
+  if (o->dedup) {
+    std::vector<double> w, weight;
+    distinct_terms(d, Wm, N, K, seed, &w, &weight);
+    o->K_used = (int)weight.size();
+    return run_terms(f, H, W, d, sigma_s, w.data(), weight.data(), o->K_used, out, o, lo, hi,
+                     TH);
+  }
   std::vector<double> w((size_t)K * d);
   frequency_table(d, Wm, N, K, seed, w.data());
+  o->K_used = K;
   return run_terms(f, H, W, d, sigma_s, w.data(), nullptr, K, out, o, lo, hi, TH);
 }
 
@@ -452,6 +456,7 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const doub
   float lo[8] = {0}, hi[8] = {0};
   if (o->center && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   o->N_used = o->N;
+  o->K_used = K;
   return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, lo, hi, TH);
 }
 

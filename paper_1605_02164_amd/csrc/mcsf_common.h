@@ -105,5 +105,9 @@ std::vector<float> term_table(int d, int K, const double* w, const double* weigh
                               double sigma_s, size_t* off_weights, size_t* off_taps);
 // Frequencies w_t = W^T Y_t / sqrt(N) of K terms drawn from seed (K x d, radians).
 void frequency_table(int d, const double* Wm, int N, int K, uint64_t seed, double* w);
+// The same K draws merged by +-Y (first nonzero entry of Y made positive), in
+// order of first occurrence: distinct frequencies (n x d) and multiplicities.
+void distinct_terms(int d, const double* Wm, int N, int K, uint64_t seed, std::vector<double>* w,
+                    std::vector<double>* weight);
 
 }  // namespace bfvec

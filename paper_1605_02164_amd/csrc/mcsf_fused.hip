@@ -3,6 +3,9 @@
 
 #include "mcsf_fused_dev.h"
 
+#include "bfvec.h"
+#include "host.h"
+
 namespace bfvec {
 
 // out = num / Z + c ; optional uncentred numerator and normaliser
@@ -91,6 +94,45 @@ static int bpc_p(int d, int R) {
 
 int fused_blocks_per_cu(int d, int R, int prec) {
   return prec == 0 ? bpc_p<0>(d, R) : prec == 1 ? bpc_p<1>(d, R) : bpc_p<2>(d, R);
+}
+
+// ---------------------------------------------------------------------------
+// Strip height.  Each workgroup streams one strip per term and recomputes 2R
+// halo rows per strip, so tall strips waste less; but all compute units
+// should be busy (two workgroups fit on a CU).  Choose the number of strips
+// down the image that minimises (waves of workgroups) x (rows per strip incl.
+// halo).
+// ---------------------------------------------------------------------------
+
+int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH) {
+  if (fused_lds_bytes(d, R, prec) > 160 * 1024)
+    return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
+  if (requested > 0) {
+    *TH = (requested + kB - 1) / kB * kB;
+    return BF_OK;
+  }
+  const int nsx = (W + kTW - 1) / kTW;
+  // resident workgroups on the GPU
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int slots = fused_blocks_per_cu(d, R, prec) * std::max(ncu, 1);
+  const int halo = lag_steps(R) * kB;
+  long best = -1;
+  int best_th = kB;
+  for (int nsy = 1; nsy <= (H + kB - 1) / kB; ++nsy) {
+    const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
+    const long nwg = (long)nsx * ((H + th - 1) / th);
+    const long waves = (nwg + slots - 1) / slots;
+    const long cost = waves * (th + halo);
+    if (best < 0 || cost < best) {
+      best = cost;
+      best_th = th;
+    }
+    if (nwg > 16L * slots) break;
+  }
+  *TH = best_th;
+  return BF_OK;
 }
 
 hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st) {

@@ -330,3 +330,41 @@ def test_low_precision_edge_shapes(prec, H, W, d, sigma, K):
     mx, mean, sc = lp_errors(host(got), ref, f, Z / (K * O.spatial_taps(sigma).sum() ** 2))
     say(f"  {prec}: max err {mx:.3e} mean err {mean:.3e} conditioning-scaled {sc:.3e}")
     assert sc <= LP_BOUND[prec]
+
+
+# --- merged +-Y terms (exact in arithmetic) ----------------------------------------
+
+def distinct_pm(Y):
+    """Number of distinct Y up to sign among the oracle's draws."""
+    Y = np.asarray(Y, dtype=np.int64)
+    first = np.array([row[np.flatnonzero(row)[0]] if np.any(row) else 1 for row in Y])
+    return len(np.unique(Y * np.sign(first)[:, None], axis=0))
+
+
+@pytest.mark.parametrize("name", ["voronoi128_d3_s2_K64", "lab1024_d3_s5_K128"])
+def test_dedup_equals_full_term_sum(name):
+    # the merged, weighted table must give the K-term estimator: compare with
+    # the oracle's O3 over all K drawn terms, and count the distinct +-Y
+    say(f"case dedup {name}")
+    f, C, p = workload(name)
+    if f.shape[0] > 256:
+        f = f[:256, :320]
+    f = np.ascontiguousarray(f)
+    sigma, K, seed = p["sigma_s"], p["K"], p["term_seed"]
+    fg = cuda(f)
+    got, o = P.bf_vec_ex(fg, sigma, C, K, seed, dedup=True, return_opts=True)
+    got = host(got)
+    f64 = f.astype(np.float64)
+    W = O.whiten(C)
+    N = O.choose_order(f64, W)
+    assert o.N_used == N
+    Y, w = O.sample_terms(C, N, K, seed, W=W)
+    assert o.K_used == distinct_pm(Y)
+    if name.startswith("voronoi128"):   # N = 24: many repeated +-Y among 64 draws
+        assert o.K_used < K
+    ref, num, Z = O.mcsf_separable(f64, sigma, w)
+    sw = O.spatial_taps(sigma).sum() ** 2
+    assert_close(got, ref, f, Z / (K * sw))
+    plain, o2 = P.bf_vec_ex(fg, sigma, C, K, seed, return_opts=True)
+    assert o2.K_used == K
+    assert_close(got, host(plain), f, Z / (K * sw))
