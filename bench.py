@@ -194,6 +194,82 @@ def serving_run(args, P, torch, log_fn):
     return rec
 
 
+def _timed(fn, reps):
+    """Median wall time (ms) of fn() followed by a device synchronisation."""
+    import numpy as np
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - t0))
+    return float(np.median(ts))
+
+
+def mse_db(a, b):
+    """10 log10 of the mean squared difference over pixels and channels
+    (eq. (MSE)), images on a [0, 255] scale."""
+    import math
+    import torch
+    m = float(torch.mean((a.double() - b.double()) ** 2))
+    return 10 * math.log10(m) if m > 0 else float("-inf")
+
+
+def study_table1(P, torch, log_fn):
+    """Runtime against sigma_s (the paper's Table 1 setting on a synthetic
+    stand-in for its 512x512 colour image): direct filter (eq. (BF), exact
+    Gaussian range kernel) against MCSF with N = 10, T = 300 terms, sigma_r =
+    40 on a [0, 255] scale; both on this GPU."""
+    import numpy as np
+    from synth import voronoi_image
+    f = torch.from_numpy(voronoi_image(512, 512, 3, 64, 0.0, 255.0, 5.0, seed=7001)).cuda()
+    C = 40.0 ** 2 * np.eye(3)
+    rows = []
+    for s in (1, 2, 3, 4, 5, 10):
+        ref = torch.empty_like(f)
+        t_direct = _timed(lambda: P.bf_direct(f, s, C, out=ref), 3)
+        rec = {"sigma_s": s, "direct_ms": t_direct}
+        for prec in ("fp32", "fp16"):
+            out = torch.empty_like(f)
+            rec[f"mcsf_{prec}_ms"] = _timed(
+                lambda: P.bf_vec_ex(f, s, C, 300, 11, out=out, N=10, precision=prec), 5)
+            rec[f"mcsf_{prec}_mse_db"] = mse_db(out, ref)
+        log_fn(f"table1 sigma_s={s}: " + ", ".join(f"{k} {v:.3g}" for k, v in rec.items()
+                                                   if k != "sigma_s"))
+        rows.append(rec)
+    return {"study": "runtime_vs_sigma_s", "image": "512x512x3 Voronoi [0,255]",
+            "sigma_r": 40, "N": 10, "K": 300, "rows": rows}
+
+
+def study_mse(P, torch, log_fn, realizations):
+    """MSE against the number of terms for N = 10 and N = 20 (the paper's
+    error-plot setting on a synthetic stand-in for its 876x584 image):
+    sigma_s = 1, sigma_r = 30 on a [0, 255] scale, averaged over
+    `realizations` term seeds; reference = the direct filter on this GPU."""
+    import numpy as np
+    from synth import voronoi_image
+    f = torch.from_numpy(voronoi_image(584, 876, 3, 64, 0.0, 255.0, 5.0, seed=7002)).cuda()
+    C = 30.0 ** 2 * np.eye(3)
+    ref = P.bf_direct(f, 1.0, C)
+    torch.cuda.synchronize()
+    out = torch.empty_like(f)
+    rows = []
+    for N in (10, 20):
+        for K in (10, 20, 50, 100, 200, 300, 500, 1000):
+            acc = 0.0
+            for r in range(realizations):
+                P.bf_vec_ex(f, 1.0, C, K, 100000 + r, out=out, N=N)
+                acc += float(torch.mean((out.double() - ref.double()) ** 2))
+            m = acc / realizations
+            rows.append({"N": N, "K": K, "mse": m, "mse_db": 10 * math.log10(m)})
+            log_fn(f"mse N={N} K={K}: {rows[-1]['mse_db']:.2f} dB")
+    return {"study": "mse_vs_terms", "image": "876x584x3 Voronoi [0,255]", "sigma_s": 1,
+            "sigma_r": 30, "realizations": realizations, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +287,10 @@ def main():
     ap.add_argument("--serve-quantum-us", type=float, default=2000.0)
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-arena-gib", type=int, default=16)
+    ap.add_argument("--study", choices=["table1", "mse"],
+                    help="run one of the paper-study analogues instead of the benchmark and "
+                         "print its JSON")
+    ap.add_argument("--realizations", type=int, default=400)
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters against known traffic) and exit")
@@ -224,6 +304,12 @@ def main():
     import torch
     import paper_1605_02164_amd as P
     from synth import workload
+
+    if args.study:
+        rec = (study_table1(P, torch, log) if args.study == "table1"
+               else study_mse(P, torch, log, args.realizations))
+        print(json.dumps(rec), flush=True)
+        return
 
     if args.copy_kernel_mib:
         n = args.copy_kernel_mib * (1 << 20) // 4
@@ -297,6 +383,20 @@ def main():
     assert main_rec["K_used"] == K
     dt = main_rec["ms_per_step"] * args.steps / 1e3
 
+    # same-GPU comparator: the direct filter of eq. (BF) with the exact
+    # Gaussian range kernel on the same image and window
+    direct = None
+    if not args.only:
+        ref = torch.empty_like(fg)
+        ms = _timed(lambda: P.bf_direct(fg, sigma_s, C, out=ref), 2)
+        span = (fg.reshape(-1, d).amax(0) - fg.reshape(-1, d).amin(0)).clamp_min(1e-30)
+        direct = {"ms": ms, "mpix_s": H * W / ms / 1e3,
+                  "approx_flops_per_pixel": (2 * R + 1) ** 2 * (2 * d + d * d * 2 + 2 * d + 4),
+                  "mcsf_fp32_max_dev": float(((outs[args.precision] - ref).abs().reshape(-1, d)
+                                              / span).max())}
+        log(f"direct filter: {ms:.1f} ms, {direct['mpix_s']:.1f} Mpix/s; MCSF max deviation "
+            f"from it {direct['mcsf_fp32_max_dev']:.3g} of the range")
+
     serving = None
     if not args.no_serving:
         serving = serving_run(args, P, torch, log)
@@ -341,6 +441,7 @@ def main():
             "kernel_ms": kernel_ms,
         },
         "cpu_baseline": cpu,
+        "direct_comparator": direct,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)

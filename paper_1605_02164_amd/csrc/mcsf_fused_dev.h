@@ -112,9 +112,30 @@ __device__ __forceinline__ void swap_halves(unsigned& a, unsigned& b) {
   asm volatile("s_nop 4\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 4" : "+v"(a), "+v"(b));
 }
 
+// Exchange rows 1, 3 of a with rows 0, 2 of b (rows of 16 lanes;
+// v_permlane16_swap_b32), written like swap_halves.
+__device__ __forceinline__ void swap_rows16(unsigned& a, unsigned& b) {
+  asm volatile("s_nop 4\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 4" : "+v"(a), "+v"(b));
+}
+
 // two FP32 values to one packed 16-bit pair (single v_cvt_pk_* instruction)
 typedef float float2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// dot2 with the two halves of a exchanged (free through the instruction's
+// operand-select bits)
+template <int PREC>
+__device__ __forceinline__ float dot2s(unsigned a, unsigned b, float c) {
+  if constexpr (PREC == 1) {
+    const half2_t h = __builtin_bit_cast(half2_t, a);
+    return __builtin_amdgcn_fdot2(__builtin_shufflevector(h, h, 1, 0),
+                                  __builtin_bit_cast(half2_t, b), c, false);
+  } else {
+    const short2_t h = __builtin_bit_cast(short2_t, a);
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_shufflevector(h, h, 1, 0),
+                                           __builtin_bit_cast(short2_t, b), c, false);
+  }
+}
+
 template <int PREC>
 __device__ __forceinline__ unsigned pack2(float lo, float hi) {
   const float2_t v = {lo, hi};
@@ -126,15 +147,18 @@ __device__ __forceinline__ unsigned pack2(float lo, float hi) {
 // over aligned sample pairs x2[j] = (x[2j], x[2j+1]):
 //   out[2q]   = sum_i te[i] . x2[q+i],   te[i] = (w[2i],   w[2i+1])
 //   out[2q+1] = sum_i to[i] . x2[q+i],   to[i] = (w[2i-1], w[2i])
+// The taps are symmetric (w[k] = w[2R-k]), so the odd-parity pair
+// (w[2i-1], w[2i]) is the even-parity pair (w[2(R-i)], w[2(R-i)+1]) with its
+// halves exchanged: only the R+1 even pairs are kept in registers.
 template <int PREC, int R>
 __device__ __forceinline__ void window4_lp(const unsigned* x2, const unsigned* te,
-                                           const unsigned* to, float (&acc)[4]) {
+                                           float (&acc)[4]) {
 #pragma unroll
   for (int i = 0; i <= R; ++i) {
     acc[0] = dot2<PREC>(te[i], x2[i], acc[0]);
-    acc[1] = dot2<PREC>(to[i], x2[i], acc[1]);
+    acc[1] = dot2s<PREC>(te[R - i], x2[i], acc[1]);
     acc[2] = dot2<PREC>(te[i], x2[i + 1], acc[2]);
-    acc[3] = dot2<PREC>(to[i], x2[i + 1], acc[3]);
+    acc[3] = dot2s<PREC>(te[R - i], x2[i + 1], acc[3]);
   }
 }
 
@@ -153,7 +177,7 @@ __device__ __forceinline__ void hpass_lp(const unsigned* src, const unsigned* te
       x2[2 * j] = v.x;
       x2[2 * j + 1] = v.y;
     }
-    window4_lp<PREC, RC>(x2, te, to, acc);
+    window4_lp<PREC, RC>(x2, te, acc);
   } else {
     unsigned cur = src[0];
     for (int i = 0; i <= R; ++i) {
@@ -185,7 +209,7 @@ __device__ __forceinline__ void vpass_lp(const unsigned* col, int pb, int RSP, c
       y2[2 * b] = r[0];
       y2[2 * b + 1] = r[RSTD];
     }
-    window4_lp<PREC, RC>(y2, te, to, acc);
+    window4_lp<PREC, RC>(y2, te, acc);
   } else {
     unsigned cur = col[wrap(pb, RSP) * RSTD];
     for (int i = 0; i <= R; ++i) {
@@ -213,7 +237,7 @@ __device__ __forceinline__ void hpass(const float* src, const float* tapr, const
 #pragma unroll
     for (int u = 0; u <= 2 * RC; ++u)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u], x[p + u], acc[p]);
+      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u <= RC ? u : 2 * RC - u], x[p + u], acc[p]);
   } else {
     const int nblk = ntap4 / 4;
     float ra[4], rb[4], t[8];
@@ -257,7 +281,7 @@ __device__ __forceinline__ void vpass(const float* col, int rb, int RS, const fl
 #pragma unroll
     for (int u = 0; u <= 2 * RC; ++u)
 #pragma unroll
-      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u], x[p + u], acc[p]);
+      for (int p = 0; p < 4; ++p) acc[p] = fmaf(tapr[u <= RC ? u : 2 * RC - u], x[p + u], acc[p]);
   } else {
     const int nblk = ntap4 / 4;
     auto ldb = [&](float* v, int blk) {
@@ -308,7 +332,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   constexpr int RST = NC * TW;       // ring row stride: [ch][x]
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
   constexpr bool LP = PREC != 0;
-  constexpr int NTAPR = (RC >= 0 && !LP) ? 2 * RC + 1 : 1;
+  constexpr int NTAPR = (RC >= 0 && !LP) ? RC + 1 : 1;    // taps 0..R (symmetric)
   constexpr int NTAPP = (RC >= 0 && LP) ? RC + 1 : 1;   // packed tap pairs
 
   extern __shared__ float4 lds4[];
@@ -360,11 +384,10 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   float tapr[NTAPR];
 #pragma unroll
   for (int u = 0; u < NTAPR; ++u) tapr[u] = s_taps[u];
-  unsigned tpe[NTAPP], tpo[NTAPP];
+  unsigned tpe[NTAPP], tpo[1] = {0u};
 #pragma unroll
   for (int i = 0; i < NTAPP; ++i) {
     tpe[i] = LP ? s_te[i] : 0u;
-    tpo[i] = LP ? s_to[i] : 0u;
   }
 
   // ---- per-thread fixed roles -------------------------------------------------
@@ -545,16 +568,25 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       else
         vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rb, RS, tapr, s_taps, ntap4, acc);
       const int cb = cslot_lag + p2_g * 4 + R;
-      float tot[4];
+      float q[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const float cs = s_cs[wrap(cb + p, CRS) * CST + p2_k * TW + p2_x];
-        const float q = cs * acc[p];
-        tot[p] = q + __shfl_xor(q, 16);
+        q[p] = cs * acc[p];
       }
       {  // lane k adds rows 2k and 2k+1 of the pair's 4-row block
+        // The cos half (k = 0, even rows of 16 lanes) and the sin half (k = 1,
+        // odd rows) of a column sit 16 lanes apart.  Exchanging odd rows of
+        // q[0] with even rows of q[2] leaves, in every lane, its own and its
+        // partner's value of row p = 2k (p = 0 on the cos side, 2 on the sin
+        // side); likewise q[1], q[3] for rows 2k + 1.
+        unsigned e0 = __builtin_bit_cast(unsigned, q[0]), e2 = __builtin_bit_cast(unsigned, q[2]);
+        unsigned e1 = __builtin_bit_cast(unsigned, q[1]), e3 = __builtin_bit_cast(unsigned, q[3]);
+        swap_rows16(e0, e2);
+        swap_rows16(e1, e3);
+        const float v0 = __builtin_bit_cast(float, e0) + __builtin_bit_cast(float, e2);
+        const float v1 = __builtin_bit_cast(float, e1) + __builtin_bit_cast(float, e3);
         const unsigned o = acc_lane + (unsigned)(ob * B + p2_g * 4) * Wp;
-        const float v0 = p2_k ? tot[2] : tot[0], v1 = p2_k ? tot[3] : tot[1];
         a.acc[o] = fmaf(tw, v0, t > 0 ? acur[0] : 0.0f);
         a.acc[o + Wp] = fmaf(tw, v1, t > 0 ? acur[1] : 0.0f);
       }
