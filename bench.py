@@ -115,14 +115,16 @@ def serving_run(args, P, torch, log_fn):
         o += m
     torch.cuda.synchronize()
     srv = P.Server(arena_bytes=args.serve_arena_gib << 30, max_active=args.serve_max_active,
-                   quantum_us=args.serve_quantum_us)
+                   quantum_us=args.serve_quantum_us, depth=args.serve_depth,
+                   streams=args.serve_streams)
+    dedup = not args.serve_no_dedup
 
     def submit_all(arrivals):
         ts = []
         for q, f, out, a in zip(reqs, crops, outs, arrivals):
             C = (q["sigma_r"] ** 2) * np.eye(q["d"])
             t, _ = srv.submit(f, q["sigma_s"], C, q["K"], seed=q["term_seed"], out=out,
-                              precision="fp16", arrival=a)
+                              precision="fp16", arrival=a, dedup=dedup)
             ts.append(t)
         return ts
 
@@ -176,7 +178,7 @@ def serving_run(args, P, torch, log_fn):
     for i in (0, n // 2, n - 1):
         q = reqs[i]
         ref, _ = P.bf_vec_ex(crops[i].contiguous(), q["sigma_s"], (q["sigma_r"] ** 2) * np.eye(q["d"]),
-                             q["K"], seed=q["term_seed"], precision="fp16")
+                             q["K"], seed=q["term_seed"], precision="fp16", dedup=dedup)
         torch.cuda.synchronize()
         same = same and bool(torch.equal(ref, outs[i]))
     rec = {
@@ -184,7 +186,8 @@ def serving_run(args, P, torch, log_fn):
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
         "mpix_s": total_px / span / 1e6, "total_mpix": total_px / 1e6,
-        "saturated": sat, "quantum_us": args.serve_quantum_us,
+        "saturated": sat, "quantum_us": args.serve_quantum_us, "depth": args.serve_depth,
+        "streams": args.serve_streams, "dedup": dedup,
         "max_active": args.serve_max_active, "rounds": stats["rounds"],
         "launches": stats["launches"], "arena_peak_gib": stats["arena_peak"] / 2**30,
         "spot_check_bitwise_equal_alone": same,
@@ -270,6 +273,69 @@ def study_mse(P, torch, log_fn, realizations):
             "sigma_r": 30, "realizations": realizations, "rows": rows}
 
 
+def srgb_to_lab(rgb):
+    """sRGB in [0, 255] (D65) to CIE-Lab: inverse companding, the sRGB
+    primaries' XYZ matrix, then the CIE L*a*b* transform."""
+    import numpy as np
+    c = np.clip(rgb / 255.0, 0, 1)
+    lin = np.where(c <= 0.04045, c / 12.92, ((c + 0.055) / 1.055) ** 2.4)
+    M = np.array([[0.4124564, 0.3575761, 0.1804375],
+                  [0.2126729, 0.7151522, 0.0721750],
+                  [0.0193339, 0.1191920, 0.9503041]])
+    xyz = lin @ M.T / np.array([0.95047, 1.0, 1.08883])
+    e = 216 / 24389
+    k = 24389 / 27
+    fx = np.where(xyz > e, np.cbrt(xyz), (k * xyz + 16) / 116)
+    return np.stack([116 * fx[..., 1] - 16, 500 * (fx[..., 0] - fx[..., 1]),
+                     200 * (fx[..., 1] - fx[..., 2])], axis=-1)
+
+
+def lab_to_srgb(lab):
+    """Inverse of srgb_to_lab, to [0, 255] (clipped)."""
+    import numpy as np
+    e = 216 / 24389
+    k = 24389 / 27
+    fy = (lab[..., 0] + 16) / 116
+    fx = fy + lab[..., 1] / 500
+    fz = fy - lab[..., 2] / 200
+    inv = lambda f: np.where(f ** 3 > e, f ** 3, (116 * f - 16) / k)
+    xyz = np.stack([inv(fx), inv(fy), inv(fz)], axis=-1) * np.array([0.95047, 1.0, 1.08883])
+    Minv = np.linalg.inv(np.array([[0.4124564, 0.3575761, 0.1804375],
+                                   [0.2126729, 0.7151522, 0.0721750],
+                                   [0.0193339, 0.1191920, 0.9503041]]))
+    lin = np.clip(xyz @ Minv.T, 0, 1)
+    c = np.where(lin <= 0.0031308, 12.92 * lin, 1.055 * lin ** (1 / 2.4) - 0.055)
+    return 255.0 * c
+
+
+def study_lab(P, torch, log_fn):
+    """Filtering in CIE-Lab (the paper's third example: 256x256, sigma_s = 5,
+    sigma_r = 90 in Lab units, N = 10, T = 300): RGB -> Lab on the host,
+    MCSF and the direct filter on this GPU, back to RGB, MSE in dB on the
+    [0, 255] RGB scale; also the same filters applied in RGB."""
+    import numpy as np
+    from synth import voronoi_image
+    rgb = voronoi_image(256, 256, 3, 32, 0.0, 255.0, 5.0, seed=7003).astype(np.float64)
+    lab = srgb_to_lab(rgb)
+    rows = {}
+    for space, img in (("lab", lab), ("rgb", rgb)):
+        f = torch.from_numpy(img.astype(np.float32)).cuda()
+        C = 90.0 ** 2 * np.eye(3)
+        ref = P.bf_direct(f, 5.0, C)
+        out, _ = P.bf_vec_ex(f, 5.0, C, 300, 13, N=10)
+        torch.cuda.synchronize()
+        a, b = ref.cpu().double().numpy(), out.cpu().double().numpy()
+        if space == "lab":
+            a, b = lab_to_srgb(a), lab_to_srgb(b)
+        m = float(np.mean((a - b) ** 2))
+        rows[space] = {"mse_db_rgb": 10 * math.log10(m)}
+        log_fn(f"lab study: filtered in {space}: MCSF vs direct {rows[space]['mse_db_rgb']:.2f} dB")
+    rt = lab_to_srgb(srgb_to_lab(rgb))
+    return {"study": "cie_lab_pipeline", "image": "256x256x3 Voronoi sRGB [0,255]",
+            "sigma_s": 5, "sigma_r": 90, "N": 10, "K": 300, "rows": rows,
+            "round_trip_max_abs": float(np.abs(rt - rgb).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,7 +353,13 @@ def main():
     ap.add_argument("--serve-quantum-us", type=float, default=2000.0)
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-arena-gib", type=int, default=16)
-    ap.add_argument("--study", choices=["table1", "mse"],
+    ap.add_argument("--serve-depth", type=int, default=2)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-no-dedup", action="store_true",
+                    help="run every drawn term (default: merge equal +-Y draws, exact)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving run (no headline modes, CPU baseline or comparator)")
+    ap.add_argument("--study", choices=["table1", "mse", "lab"],
                     help="run one of the paper-study analogues instead of the benchmark and "
                          "print its JSON")
     ap.add_argument("--realizations", type=int, default=400)
@@ -307,8 +379,13 @@ def main():
 
     if args.study:
         rec = (study_table1(P, torch, log) if args.study == "table1"
+               else study_lab(P, torch, log) if args.study == "lab"
                else study_mse(P, torch, log, args.realizations))
         print(json.dumps(rec), flush=True)
+        return
+
+    if args.serve_only:
+        print(json.dumps({"serving": serving_run(args, P, torch, log)}), flush=True)
         return
 
     if args.copy_kernel_mib:
@@ -390,12 +467,15 @@ def main():
         ref = torch.empty_like(fg)
         ms = _timed(lambda: P.bf_direct(fg, sigma_s, C, out=ref), 2)
         span = (fg.reshape(-1, d).amax(0) - fg.reshape(-1, d).amin(0)).clamp_min(1e-30)
+        dev = (outs[args.precision] - ref).abs().reshape(-1, d) / span
         direct = {"ms": ms, "mpix_s": H * W / ms / 1e3,
                   "approx_flops_per_pixel": (2 * R + 1) ** 2 * (2 * d + d * d * 2 + 2 * d + 4),
-                  "mcsf_fp32_max_dev": float(((outs[args.precision] - ref).abs().reshape(-1, d)
-                                              / span).max())}
-        log(f"direct filter: {ms:.1f} ms, {direct['mpix_s']:.1f} Mpix/s; MCSF max deviation "
-            f"from it {direct['mcsf_fp32_max_dev']:.3g} of the range")
+                  "mcsf_vs_direct": {"max_dev": float(dev.max()), "mean_dev": float(dev.mean()),
+                                     "mse_db_255": mse_db(outs[args.precision] * 255.0,
+                                                          ref * 255.0)}}
+        log(f"direct filter: {ms:.1f} ms, {direct['mpix_s']:.1f} Mpix/s; MCSF deviation from it: "
+            f"mean {direct['mcsf_vs_direct']['mean_dev']:.3g}, max "
+            f"{direct['mcsf_vs_direct']['max_dev']:.3g} of the range")
 
     serving = None
     if not args.no_serving:

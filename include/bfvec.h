@@ -195,7 +195,8 @@ typedef struct bf_request {
   double arrival;       /* server clock (s, see bf_server_clock) at which the
                            request arrives; <= 0: at submit.  Latency is measured
                            from it; a request is not admitted before it.          */
-  int reserved[4];
+  int dedup;            /* as bf_opts.dedup: merge equal +-Y draws (exact)        */
+  int reserved[3];
 } bf_request;
 
 enum {

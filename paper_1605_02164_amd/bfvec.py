@@ -88,7 +88,8 @@ class bf_request(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("center", ctypes.c_int),
         ("arrival", ctypes.c_double),
-        ("reserved", ctypes.c_int * 4),
+        ("dedup", ctypes.c_int),
+        ("reserved", ctypes.c_int * 3),
     ]
 
 
@@ -364,7 +365,7 @@ class Server:
         self._refs = {}
 
     def submit(self, f, sigma_s, C, K, seed, out=None, N=0, precision="fp16", center=True,
-               arrival=0.0):
+               arrival=0.0, dedup=False):
         """Queue the filter of ``f`` (see bf_vec_ex for the arguments);
         ``arrival`` is the server-clock time the request arrives (0: now).
         Returns (ticket, out)."""
@@ -387,6 +388,7 @@ class Server:
         r.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         r.center = 1 if center else 0
         r.arrival = float(arrival)
+        r.dedup = 1 if dedup else 0
         t = ctypes.c_uint64()
         _check(lib().bf_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         self._refs[t.value] = (f, out)

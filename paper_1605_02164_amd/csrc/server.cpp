@@ -75,6 +75,7 @@ struct Req {
   float* pin = nullptr;   // pinned: min/max result (17, padded to 32) then term table
   double cost_term = 0.0;
   int next_t = 0;
+  int K_run = 0;          // kernel terms: K, or the distinct +-Y count
   hipEvent_t ev_mm = nullptr, ev_done = nullptr;
   // shared with callers (guarded by the server mutex)
   int state = BF_REQ_QUEUED, error = 0, N_used = 0, chunks = 0;
@@ -175,11 +176,17 @@ struct Server {
       finish(r, BF_REQ_FAILED, BF_EUNSUPPORTED, bf_last_error());
       return false;
     }
-    std::vector<double> w((size_t)r->in.K * d);
-    frequency_table(d, r->Wm, N, r->in.K, r->in.seed, w.data());
+    std::vector<double> w, weight;
+    if (r->in.dedup) {
+      distinct_terms(d, r->Wm, N, r->in.K, r->in.seed, &w, &weight);
+    } else {
+      w.resize((size_t)r->in.K * d);
+      frequency_table(d, r->Wm, N, r->in.K, r->in.seed, w.data());
+    }
+    const int K = r->in.dedup ? (int)weight.size() : r->in.K;
     size_t off_w = 0, off_taps = 0;
-    const std::vector<float> tab =
-        term_table(d, r->in.K, w.data(), nullptr, r->in.sigma_s, &off_w, &off_taps);
+    const std::vector<float> tab = term_table(d, K, w.data(), r->in.dedup ? weight.data() : nullptr,
+                                              r->in.sigma_s, &off_w, &off_taps);
     float* ptab = r->pin + 32;
     std::memcpy(ptab, tab.data(), tab.size() * sizeof(float));
     float* dtab = reinterpret_cast<float*>(dev_base + r->dev_off) + r->n_acc;
@@ -191,8 +198,9 @@ struct Server {
       return false;
     }
     r->a.terms = dtab;
-    r->a.weights = nullptr;
+    r->a.weights = r->in.dedup ? dtab + off_w : nullptr;
     r->a.taps = dtab + off_taps;
+    r->K_run = K;
     for (int m = 0; m < 8; ++m)
       r->a.cen[m] = (r->in.center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
     std::lock_guard<std::mutex> lk(mu);
@@ -291,7 +299,7 @@ struct Server {
     std::vector<PlanJob> jobs;
     jobs.reserve(active.size());
     for (size_t i = 0; i < active.size(); ++i)
-      jobs.push_back(PlanJob{(int)i, active[i]->variant, active[i]->next_t, active[i]->in.K,
+      jobs.push_back(PlanJob{(int)i, active[i]->variant, active[i]->next_t, active[i]->K_run,
                              active[i]->cost_term});
     const std::vector<PlanLaunch> plan = plan_round(jobs, cfg.quantum_us, kMaxBatch);
     std::set<int> used;
@@ -321,7 +329,7 @@ struct Server {
       for (const PlanItem& it : L.items) {
         Req* r = active[it.job];
         r->next_t = it.t1;
-        if (r->next_t < r->in.K) continue;
+        if (r->next_t < r->K_run) continue;
         FinalizeArgs fa{};
         fa.acc = r->a.acc;
         fa.out = r->in.out;
@@ -366,7 +374,7 @@ struct Server {
     std::vector<Req*> still;
     still.reserve(active.size());
     for (Req* r : active)
-      if (r->next_t < r->in.K) still.push_back(r);
+      if (r->next_t < r->K_run) still.push_back(r);
     active.swap(still);
     return true;
   }
@@ -531,6 +539,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   if (in.precision != BF_FP32 && in.precision != BF_FP16 && in.precision != BF_BF16)
     return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
   if (in.center != 0 && in.center != 1) return fail(BF_EINVAL, "center must be 0 or 1");
+  if (in.dedup != 0 && in.dedup != 1) return fail(BF_EINVAL, "dedup must be 0 or 1");
   if (!in.C) return fail(BF_EINVAL, "C must be non-null");
   if (!std::isfinite(in.arrival)) return fail(BF_EINVAL, "arrival must be finite");
   {
@@ -561,7 +570,8 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   r->a.f = in.f;
   r->a.fpitch = in.pitch;
   r->n_acc = fused_acc_floats(r->a, in.d);
-  r->n_tab = (size_t)in.K * (in.d + 1) + (size_t)(2 * r->R + 1);
+  // term table at most K rows of d+1 floats, K weights (merged draws), 2R+1 taps
+  r->n_tab = (size_t)in.K * (in.d + 2) + (size_t)(2 * r->R + 1);
   r->need_minmax = in.N == 0 || in.center;
   r->nparts = minmax_parts((size_t)in.H * in.W);
   const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMFloats : 0;

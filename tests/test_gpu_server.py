@@ -170,3 +170,24 @@ def test_nan_request_fails_alone(pools):
         ref, _ = P.bf_vec_ex(good.contiguous(), 2.0, C, 4, seed=1, precision="fp16")
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+
+
+def test_merged_terms_match_standalone(pools):
+    # requests with equal +-Y draws merged give the same bits as bf_vec_ex
+    # with the same option
+    C = 0.1 ** 2 * np.eye(3)
+    crops = [pools[0][:96, :128], pools[0][50:163, 31:90]]
+    with P.Server(arena_bytes=1 << 28, quantum_us=30.0) as srv:
+        ts = []
+        for i, fc in enumerate(crops):
+            for prec in ("fp32", "fp16"):
+                t, out = srv.submit(fc, 2.0, C, 64, seed=40 + i, precision=prec, dedup=True)
+                ts.append((fc, prec, i, t, out))
+        srv.drain(timeout=60.0)
+        for fc, prec, i, t, out in ts:
+            assert srv.poll(t)["state"] == "done"
+            ref, o = P.bf_vec_ex(fc.contiguous(), 2.0, C, 64, seed=40 + i, precision=prec,
+                                 dedup=True, return_opts=True)
+            torch.cuda.synchronize()
+            assert o.K_used < 64
+            assert torch.equal(out, ref), (prec, i)
