@@ -28,17 +28,17 @@ PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: the same without packed-FP32 issue
 
 # HBM bytes per launch of the benchmark's fused kernel, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
-# counters read for a 1 GiB device copy (FETCH_SIZE 524,307 KiB: factor
+# counters read for a 1 GiB device copy (FETCH_SIZE 524,306 KiB: factor
 # 1.99993; WRITE_SIZE 1,048,576 KiB: factor 1.0).  Valid only for the kernel
 # sources they were taken on (TRAFFIC_SOURCES hash); otherwise reported null.
 TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "530f4ed5261096aa9c5c4440bcc808a1d63c67a3ad20c6efef7cd8af9f432104",
-    "fp32": {"fetch_kib": 93608406, "write_kib": 67433176},
-    "fp16": {"fetch_kib": 121065135, "write_kib": 70316061},
-    "fetch_factor": 1048576 / 524307,
+    "sha256": "ee278452229269408ec5aac345322fbdc04d314c103b163145db9f07ba7b1443",
+    "fp32": {"fetch_kib": 109361538, "write_kib": 70908568},
+    "fp16": {"fetch_kib": 162775326, "write_kib": 71293754},
+    "fetch_factor": 1048576 / 524306,
     "write_factor": 1.0,
 }
 
@@ -347,6 +347,8 @@ def main():
     ap.add_argument("--only", action="store_true", help="time only --precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the occupancy model's strip height instead of measuring it")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="Poisson arrival rate as a fraction of the measured capacity")
@@ -412,17 +414,23 @@ def main():
     def step(prec, dst, dedup):
         _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=dst, precision=prec,
                            stream=stream, time_kernel=True, return_opts=True, dedup=dedup)
-        return o.N_used, o.kernel_ms, o.K_used
+        return o.N_used, o.kernel_ms, o.K_used, o.tile_h_used
+
+    tuned = {}
 
     def run(mode, dst):
         prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
+        if not args.no_autotune and prec not in tuned:
+            # one-off, untimed: measured strip height for this shape
+            tuned[prec] = P.bf_autotune(fg, sigma_s, precision=prec, stream=stream)
+            log(f"{prec}: autotuned strip height {tuned[prec][0]}")
         for _ in range(args.warmup):
             step(prec, dst, dedup)
         torch.cuda.synchronize()
         kms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            N, ms, K_used = step(prec, dst, dedup)
+            N, ms, K_used, tile_h = step(prec, dst, dedup)
             kms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -431,7 +439,7 @@ def main():
         flops_run = algorithmic_flops_per_pixel(d, R, K_used) * H * W
         rec = {"value": H * W * args.steps / dt / 1e6, "ms_per_step": 1e3 * dt / args.steps,
                "kernel_ms": kernel_ms, "achieved_tflops": flops_run / (kernel_ms * 1e-3) / 1e12,
-               "N": N, "K_used": K_used}
+               "N": N, "K_used": K_used, "tile_h": tile_h}
         log(f"{mode}: N={N} K_used={K_used} step {rec['ms_per_step']:.2f} ms, kernel "
             f"{kernel_ms:.2f} ms, {rec['achieved_tflops']:.2f} TFLOP/s algorithmic, "
             f"{rec['value']:.2f} Mpix/s")

@@ -77,7 +77,8 @@ typedef struct bf_opts {
                       over the K draws equals the multiplicity-weighted sum over
                       the distinct +-Y.  0 (default): K terms as drawn          */
   int K_used;      /* OUT: terms the kernel ran (K, or the distinct +-Y count)  */
-  int reserved[3];
+  int tile_h_used; /* OUT: strip height the fused kernel ran with              */
+  int reserved[2];
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,
@@ -137,6 +138,18 @@ int bf_choose_N(int d, const double* W, const float* lo, const float* hi, int* N
  * stream).  BF_EINVAL if the image holds a NaN or infinity. */
 int bf_minmax(const float* f, int H, int W, int d, float* lo, float* hi,
               void* stream);
+
+/* Autotuner of the fused kernel's strip height (rows of output per
+ * workgroup; the strip width is fixed at 16 columns).  Times the fused kernel
+ * with a few probe terms on the device image f (read only) for candidate
+ * heights around the occupancy model's choice, and records the fastest in a
+ * process-wide table keyed by the current device, d, the window radius,
+ * precision and (H, W); later bf_vec_ex / bf_vec_terms calls with
+ * tile_h = 0, and server requests of that shape, use it.  Synchronous on
+ * `stream`.  Writes the chosen height to *tile_h and its probe time per term
+ * in ms to *ms_per_term (either may be NULL).  Errors as bf_vec_ex. */
+int bf_autotune(const float* f, int H, int W, int d, double sigma_s,
+                int precision, void* stream, int* tile_h, float* ms_per_term);
 
 /* Direct evaluation of eqs. (BF)/(normal) on the GPU with the exact Gaussian
  * range kernel (O(sigma_s^2) work per pixel; the paper's comparison method).

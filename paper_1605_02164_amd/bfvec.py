@@ -26,7 +26,7 @@ PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
 # Every symbol declared in include/bfvec.h.
 EXPORTS = [
     "bf_opts_init", "bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten",
-    "bf_sample_terms", "bf_choose_N", "bf_minmax", "bf_direct",
+    "bf_sample_terms", "bf_choose_N", "bf_minmax", "bf_direct", "bf_autotune",
     "bf_last_error", "bf_version",
     "bf_server_config_init", "bf_request_init", "bf_server_create", "bf_server_submit",
     "bf_server_poll", "bf_server_wait", "bf_server_drain", "bf_server_forget",
@@ -56,7 +56,8 @@ class bf_opts(ctypes.Structure):
         ("kernel_ms", ctypes.c_float),
         ("dedup", ctypes.c_int),
         ("K_used", ctypes.c_int),
-        ("reserved", ctypes.c_int * 3),
+        ("tile_h_used", ctypes.c_int),
+        ("reserved", ctypes.c_int * 2),
     ]
 
 
@@ -146,6 +147,7 @@ def lib():
     L.bf_choose_N.argtypes = [I, P, P, P, ctypes.POINTER(I)]
     L.bf_minmax.argtypes = [P, I, I, I, P, P, P]
     L.bf_direct.argtypes = [P, I, I, I, D, P, P]
+    L.bf_autotune.argtypes = [P, I, I, I, D, I, P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float)]
     L.bf_last_error.argtypes = []
     L.bf_last_error.restype = ctypes.c_char_p
     L.bf_version.argtypes = []
@@ -164,7 +166,8 @@ def lib():
     L.bf_server_clock.restype = D
     L.bf_server_destroy.argtypes = [P]
     for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_sample_terms",
-                 "bf_choose_N", "bf_minmax", "bf_direct", "bf_version", "bf_server_create",
+                 "bf_choose_N", "bf_minmax", "bf_direct", "bf_autotune", "bf_version",
+                 "bf_server_create",
                  "bf_server_submit", "bf_server_poll", "bf_server_wait", "bf_server_drain",
                  "bf_server_forget", "bf_server_get_stats", "bf_server_destroy"):
         getattr(L, name).restype = I
@@ -309,6 +312,19 @@ def bf_minmax(f, stream=None):
     _check(lib().bf_minmax(f.data_ptr(), H, W, d, _ptr(lo), _ptr(hi),
                            _stream_handle(stream)))
     return lo, hi
+
+
+def bf_autotune(f, sigma_s, precision="fp32", stream=None):
+    """Measure and record the fused kernel's fastest strip height for this
+    image shape; returns (tile_h, ms_per_term)."""
+    _check_image(f, None)
+    H, W, d = f.shape
+    th = ctypes.c_int(0)
+    ms = ctypes.c_float(0.0)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().bf_autotune(f.data_ptr(), H, W, d, float(sigma_s), prec, _stream_handle(stream),
+                             ctypes.byref(th), ctypes.byref(ms)))
+    return th.value, ms.value
 
 
 def bf_direct(f, sigma_s, C, out=None):

@@ -272,6 +272,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = K;
+  o->tile_h_used = TH;
 
   // one stream-ordered allocation: accumulators | terms | weights | taps
   const size_t n_acc = fused_acc_floats(a, d);
@@ -458,6 +459,99 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const doub
   o->N_used = o->N;
   o->K_used = K;
   return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, lo, hi, TH);
+}
+
+int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precision, void* stream,
+                int* tile_h, float* ms_per_term) {
+  clear_error();
+  // f is read only; a distinct dummy output pointer passes the common checks
+  int rc = check_common(f, H, W, d, sigma_s, (const char*)f + (size_t)H * W * d * sizeof(float));
+  if (rc) return rc;
+  if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
+    return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
+  const int R = window_radius(sigma_s);
+  if ((rc = check_fused_size(H, W, W, d, R))) return rc;
+  int TH0 = 0;   // validates the window against the LDS budget
+  if ((rc = choose_strip_height(d, R, precision, H, W, 0, &TH0))) return rc;
+  (void)TH0;
+  const int model = model_strip_height(d, R, precision, H, W);
+  // candidate strip counts down the image around the model's
+  const int nsy0 = (H + model - 1) / model, nmax = (H + kB - 1) / kB;
+  std::vector<int> ths;
+  for (int f10 : {3, 5, 7, 10, 13, 15, 20, 30, 40}) {
+    const int nsy = std::min(nmax, std::max(1, (nsy0 * f10 + 5) / 10));
+    const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
+    if (std::find(ths.begin(), ths.end(), th) == ths.end()) ths.push_back(th);
+  }
+  // probe terms: a few fixed frequencies (the cost does not depend on them)
+  constexpr int KP = 4;
+  std::vector<double> w((size_t)KP * d);
+  for (int t = 0; t < KP; ++t)
+    for (int m = 0; m < d; ++m) w[(size_t)t * d + m] = 0.7 + 0.3 * t + 0.1 * m;
+  size_t off_w = 0, off_taps = 0;
+  const std::vector<float> tab = term_table(d, KP, w.data(), nullptr, sigma_s, &off_w, &off_taps);
+  size_t n_acc = 0;
+  for (int th : ths) {
+    FusedArgs a{};
+    fused_geometry(a, H, W, R, precision, th);
+    n_acc = std::max(n_acc, fused_acc_floats(a, d));
+  }
+  hipStream_t st = (hipStream_t)stream;
+  float* dbuf = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&dbuf, (n_acc + tab.size()) * sizeof(float), st),
+          "hipMallocAsync(autotune)");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemcpyAsync(dbuf + n_acc, tab.data(), tab.size() * sizeof(float),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  // The model's own height is timed too; another candidate replaces it only
+  // when it is at least 2% faster (probe timings vary by about 1%).
+  if (std::find(ths.begin(), ths.end(), model) == ths.end()) ths.push_back(model);
+  int best_th = model;
+  float best = -1.0f, model_ms = -1.0f;
+  for (size_t i = 0; i < ths.size() && e == hipSuccess; ++i) {
+    FusedArgs a{};
+    a.f = f;
+    a.acc = dbuf;
+    a.terms = dbuf + n_acc;
+    a.taps = dbuf + n_acc + off_taps;
+    fused_geometry(a, H, W, R, precision, ths[i]);
+    a.fpitch = W;
+    a.t0 = 0;
+    a.t1 = KP;
+    e = launch_fused(d, precision, a, st);   // warm-up
+    float ms = -1.0f;
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) {   // fastest of three probes
+      float m = 0.0f;
+      e = hipEventRecord(e0, st);
+      if (e == hipSuccess) e = launch_fused(d, precision, a, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&m, e0, e1);
+      if (e == hipSuccess && (ms < 0.0f || m < ms)) ms = m;
+    }
+    if (e != hipSuccess) break;
+    if (ths[i] == model) model_ms = ms;
+    if (best < 0.0f || ms < best) {
+      best = ms;
+      best_th = ths[i];
+    }
+  }
+  if (e == hipSuccess && model_ms > 0.0f && best > 0.98f * model_ms) {
+    best_th = model;
+    best = model_ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  hipError_t e2 = hipFreeAsync(dbuf, st);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  record_tuned_height(d, R, precision, H, W, best_th);
+  if (tile_h) *tile_h = best_th;
+  if (ms_per_term) *ms_per_term = best / KP;
+  return BF_OK;
 }
 
 int bf_minmax(const float* f, int H, int W, int d, float* lo, float* hi, void* stream) {

@@ -93,8 +93,15 @@ hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* 
 // BF_EUNSUPPORTED (with the message set) if the fused kernels cannot take
 // this image: radius above kRMax, or sizes past 32-bit element offsets.
 int check_fused_size(int H, int W, int pitch, int d, int R);
-// Strip height for an image alone on the device (requested > 0 forces it).
+// Strip height: requested > 0 forces it; otherwise a height measured by
+// bf_autotune for this device and shape, else the occupancy model.
 int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH);
+// The occupancy model alone: minimises (waves of workgroups) x (rows + halo).
+int model_strip_height(int d, int R, int prec, int H, int W);
+// Process-wide table of measured strip heights, keyed by the current device,
+// d, R, precision and the image shape.
+void record_tuned_height(int d, int R, int prec, int H, int W, int TH);
+int tuned_height(int d, int R, int prec, int H, int W);
 // Strip geometry, staging width and ring sizes of a FusedArgs.
 void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH);
 // Accumulator floats of a planned FusedArgs: (d+1) planes of Hp x Wp.

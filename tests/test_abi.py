@@ -146,3 +146,14 @@ def test_product_path_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         B.lib()
+
+
+def test_autotune_validation_before_device_work():
+    import ctypes
+    L = P.lib()
+    th = ctypes.c_int(0)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.bf_autotune(fake, 16, 16, 9, 2.0, 0, None, ctypes.byref(th), None) == B.BF_EINVAL
+    assert L.bf_autotune(fake, 16, 16, 3, 2.0, 7, None, ctypes.byref(th), None) == B.BF_EINVAL
+    assert L.bf_autotune(fake, 16, 16, 3, 14.0, 0, None, ctypes.byref(th), None) == B.BF_EUNSUPPORTED
+    assert L.bf_autotune(None, 16, 16, 3, 2.0, 0, None, ctypes.byref(th), None) == B.BF_EINVAL

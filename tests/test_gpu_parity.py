@@ -368,3 +368,19 @@ def test_dedup_equals_full_term_sum(name):
     plain, o2 = P.bf_vec_ex(fg, sigma, C, K, seed, return_opts=True)
     assert o2.K_used == K
     assert_close(got, host(plain), f, Z / (K * sw))
+
+
+def test_autotune_records_height_and_keeps_bits():
+    # the tuned strip height is used by later calls and changes no output bit
+    f = np.ascontiguousarray(voronoi_image(200, 330, 3, 20, 0.0, 1.0, 0.02, seed=77))
+    fg = cuda(f)
+    C = 0.08 ** 2 * np.eye(3)
+    for prec in ("fp32", "fp16"):
+        ref, o0 = P.bf_vec_ex(fg, 5.0, C, 8, 3, precision=prec, tile_h=8, return_opts=True)
+        ref = host(ref)
+        th, ms = P.bf_autotune(fg, 5.0, precision=prec)
+        say(f"  {prec}: tuned strip height {th}, {ms:.4f} ms per term")
+        assert th % 8 == 0 and 8 <= th <= 208 and ms > 0
+        got, o = P.bf_vec_ex(fg, 5.0, C, 8, 3, precision=prec, return_opts=True)
+        assert o.tile_h_used == th and o0.tile_h_used == 8
+        assert np.array_equal(host(got), ref)
