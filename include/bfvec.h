@@ -30,7 +30,7 @@
  *     taps, reduction partials) in stream order; the caller owns images.
  *   - Limits: 1 <= H, W <= 65536; 1 <= d <= 8; 1 <= K <= 65536;
  *     1 <= N <= 65536; the fused filter takes window radii R <= 40
- *     (sigma_s <= 13.33) and images with H*W*(d+1) below 2^32 elements
+ *     (sigma_s <= 13.33) and images with H*W*(d+1) below 2^30 elements
  *     (BF_EUNSUPPORTED otherwise); bf_direct takes R <= 96.
  */
 #ifndef BFVEC_H

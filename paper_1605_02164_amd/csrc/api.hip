@@ -154,11 +154,12 @@ int check_opts(const bf_opts* o) {
 
 int check_fused_size(int H, int W, int pitch, int d, int R) {
   if (R > kRMax) return fail(BF_EUNSUPPORTED, "sigma_s too large: window radius above 40");
-  // the kernels address f and the accumulators with 32-bit element offsets
+  // the kernels address f and the accumulators with 32-bit byte offsets
+  // (buffer loads): each must stay below 2^30 floats
   const double elems = (double)(H + 2 * kB) * (double)(W + kTW) * (double)(d + 1);
   const double felems = (double)H * (double)pitch * (double)d;
-  if (elems >= 4294967296.0 - 65536.0 || felems >= 4294967296.0 - 65536.0)
-    return fail(BF_EUNSUPPORTED, "image too large: H*W*(d+1) must stay below 2^32 elements");
+  if (elems >= 1073741824.0 - 65536.0 || felems >= 1073741824.0 - 65536.0)
+    return fail(BF_EUNSUPPORTED, "image too large: H*W*(d+1) must stay below 2^30 elements");
   return BF_OK;
 }
 

@@ -121,21 +121,6 @@ __device__ __forceinline__ void swap_rows16(unsigned& a, unsigned& b) {
 // two FP32 values to one packed 16-bit pair (single v_cvt_pk_* instruction)
 typedef float float2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-// dot2 with the two halves of a exchanged (free through the instruction's
-// operand-select bits)
-template <int PREC>
-__device__ __forceinline__ float dot2s(unsigned a, unsigned b, float c) {
-  if constexpr (PREC == 1) {
-    const half2_t h = __builtin_bit_cast(half2_t, a);
-    return __builtin_amdgcn_fdot2(__builtin_shufflevector(h, h, 1, 0),
-                                  __builtin_bit_cast(half2_t, b), c, false);
-  } else {
-    const short2_t h = __builtin_bit_cast(short2_t, a);
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_shufflevector(h, h, 1, 0),
-                                           __builtin_bit_cast(short2_t, b), c, false);
-  }
-}
-
 template <int PREC>
 __device__ __forceinline__ unsigned pack2(float lo, float hi) {
   const float2_t v = {lo, hi};
@@ -147,18 +132,15 @@ __device__ __forceinline__ unsigned pack2(float lo, float hi) {
 // over aligned sample pairs x2[j] = (x[2j], x[2j+1]):
 //   out[2q]   = sum_i te[i] . x2[q+i],   te[i] = (w[2i],   w[2i+1])
 //   out[2q+1] = sum_i to[i] . x2[q+i],   to[i] = (w[2i-1], w[2i])
-// The taps are symmetric (w[k] = w[2R-k]), so the odd-parity pair
-// (w[2i-1], w[2i]) is the even-parity pair (w[2(R-i)], w[2(R-i)+1]) with its
-// halves exchanged: only the R+1 even pairs are kept in registers.
 template <int PREC, int R>
-__device__ __forceinline__ void window4_lp(const unsigned* x2, const unsigned* te,
+__device__ __forceinline__ void window4_lp(const unsigned* x2, const unsigned* te, const unsigned* to,
                                            float (&acc)[4]) {
 #pragma unroll
   for (int i = 0; i <= R; ++i) {
     acc[0] = dot2<PREC>(te[i], x2[i], acc[0]);
-    acc[1] = dot2s<PREC>(te[R - i], x2[i], acc[1]);
+    acc[1] = dot2<PREC>(to[i], x2[i], acc[1]);
     acc[2] = dot2<PREC>(te[i], x2[i + 1], acc[2]);
-    acc[3] = dot2s<PREC>(te[R - i], x2[i + 1], acc[3]);
+    acc[3] = dot2<PREC>(to[i], x2[i + 1], acc[3]);
   }
 }
 
@@ -177,7 +159,7 @@ __device__ __forceinline__ void hpass_lp(const unsigned* src, const unsigned* te
       x2[2 * j] = v.x;
       x2[2 * j + 1] = v.y;
     }
-    window4_lp<PREC, RC>(x2, te, acc);
+    window4_lp<PREC, RC>(x2, te, to, acc);
   } else {
     unsigned cur = src[0];
     for (int i = 0; i <= R; ++i) {
@@ -209,7 +191,7 @@ __device__ __forceinline__ void vpass_lp(const unsigned* col, int pb, int RSP, c
       y2[2 * b] = r[0];
       y2[2 * b + 1] = r[RSTD];
     }
-    window4_lp<PREC, RC>(y2, te, acc);
+    window4_lp<PREC, RC>(y2, te, to, acc);
   } else {
     unsigned cur = col[wrap(pb, RSP) * RSTD];
     for (int i = 0; i <= R; ++i) {
@@ -313,6 +295,28 @@ __device__ __forceinline__ void vpass(const float* col, int rb, int RS, const fl
 
 }  // namespace
 
+// Buffer-resource access with 32-bit byte offsets (raw buffer, no stride):
+// the address arithmetic stays 32-bit.  Offsets must stay below 4 GiB (the
+// planner limits images accordingly).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+// One pixel's D channels: D dword loads from one address register with
+// immediate offsets.  (The 96-bit buffer-load builtin compiled to a single
+// dword load in this toolchain, so wide loads are not used.)
+template <int D>
+__device__ __forceinline__ void buf_load_px(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float (&v)[D]) {
+#pragma unroll
+  for (int m = 0; m < D; ++m)
+    v[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(byte_off + 4 * m), 0, 0));
+}
+__device__ __forceinline__ float buf_load1(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+__device__ __forceinline__ void buf_store1(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+}
+
 // Read-only table entry through the constant address space: a uniform index
 // then becomes a scalar load.
 __device__ __forceinline__ float ld_const(const float* p, int i) {
@@ -384,10 +388,18 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   float tapr[NTAPR];
 #pragma unroll
   for (int u = 0; u < NTAPR; ++u) tapr[u] = s_taps[u];
-  unsigned tpe[NTAPP], tpo[1] = {0u};
+  // 16-bit tap pairs: the even-parity pairs as scalar operands (SGPRs), the
+  // odd-parity ones in VGPRs (an opaque move keeps the compiler from also
+  // making them scalar: with both sets in SGPRs it ran out and spilled other
+  // scalars to VGPR lanes).  v_dot2 takes no operand-select modifiers on
+  // gfx950, so the odd pairs cannot be derived from the even ones for free.
+  unsigned tpe[NTAPP], tpo[NTAPP];
 #pragma unroll
   for (int i = 0; i < NTAPP; ++i) {
-    tpe[i] = LP ? s_te[i] : 0u;
+    tpe[i] = LP ? __builtin_amdgcn_readfirstlane(s_te[i]) : 0u;
+    unsigned v = LP ? s_to[i] : 0u;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "v"(v));
+    tpo[i] = v;
   }
 
   // ---- per-thread fixed roles -------------------------------------------------
@@ -438,22 +450,22 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   int m_fx[MI];  // clamped column offset of each slot, in floats
 #pragma unroll
   for (int i = 0; i < MI; ++i) m_fx[i] = min(max(m_x[i], 0), Wd - 1) * D;
+  const __amdgpu_buffer_rsrc_t f_rsrc = buf_rsrc(a.f), acc_rsrc = buf_rsrc(a.acc);
   auto load_f = [&](float (&dst)[MI][D], int s) {
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
       if (i * NT < nmod) {
         const int y = min(max(ybase + s * B + m_rr[i], 0), Hd - 1);
         const unsigned o = (unsigned)y * frow + (unsigned)m_fx[i];
-#pragma unroll
-        for (int m = 0; m < D; ++m) dst[i][m] = a.f[o + m];
+        buf_load_px<D>(f_rsrc, 4u * o, dst[i]);
       }
     }
   };
   auto load_acc = [&](float (&dst)[2], int t, int s) {
     if (t > 0 && t < t1 && s >= lag) {
       const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
-      dst[0] = a.acc[o];
-      dst[1] = a.acc[o + Wp];
+      dst[0] = buf_load1(acc_rsrc, 4u * o);
+      dst[1] = buf_load1(acc_rsrc, 4u * (o + Wp));
     }
   };
 
@@ -587,8 +599,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         const float v0 = __builtin_bit_cast(float, e0) + __builtin_bit_cast(float, e2);
         const float v1 = __builtin_bit_cast(float, e1) + __builtin_bit_cast(float, e3);
         const unsigned o = acc_lane + (unsigned)(ob * B + p2_g * 4) * Wp;
-        a.acc[o] = fmaf(tw, v0, t > 0 ? acur[0] : 0.0f);
-        a.acc[o + Wp] = fmaf(tw, v1, t > 0 ? acur[1] : 0.0f);
+        buf_store1(acc_rsrc, 4u * o, fmaf(tw, v0, t > 0 ? acur[0] : 0.0f));
+        buf_store1(acc_rsrc, 4u * (o + Wp), fmaf(tw, v1, t > 0 ? acur[1] : 0.0f));
       }
     }
     load_acc(acur, t2, s2);

@@ -107,6 +107,8 @@ def _call_vec(f=0x1000, H=8, W=8, d=3, sigma=1.0, C=None, K=4, out=0x100000):
     (dict(C=np.array([[1.0, 2, 0], [2, 1, 0], [0, 0, 1]])), B.BF_ENOTSPD),
     (dict(C=np.diag([1.0, 0.0, 1.0])), B.BF_ENOTSPD),
     (dict(sigma=14.0), B.BF_EUNSUPPORTED),               # R = 42 > 40
+    # (H+16)(W+16)(d+1) above 2^30 floats: 32-bit byte offsets would overflow
+    (dict(H=20000, W=20000, out=0x1000 + 20000 * 20000 * 12 + 4096), B.BF_EUNSUPPORTED),
 ])
 def test_argument_errors_before_device_work(kw, code):
     rc, msg = _call_vec(**kw)
