@@ -191,3 +191,25 @@ def test_merged_terms_match_standalone(pools):
             torch.cuda.synchronize()
             assert o.K_used < 64
             assert torch.equal(out, ref), (prec, i)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_every_dimension_served_equals_standalone(prec):
+    # the batched kernel instances for d = 1..8 (runtime window radius except
+    # d = 3, 6 at fixed radii), one launch holding several requests per d
+    specs = [(d, 29 + 3 * d, 41 - 2 * d, 1.0 + 0.5 * (d % 3)) for d in range(1, 9)]
+    imgs = [torch.from_numpy(voronoi_image(H, W, d, 7, 0.0, 1.0, 0.02, seed=300 + d)).to(DEV)
+            for d, H, W, _ in specs]
+    with P.Server(arena_bytes=1 << 28, quantum_us=5.0) as srv:
+        ts = []
+        for (d, H, W, s), f in zip(specs, imgs):
+            C = random_spd(d, -2.5, -1.5, seed=d)
+            for k in (3, 7):
+                t, out = srv.submit(f, s, C, k, seed=d * 10 + k, precision=prec)
+                ts.append((f, s, C, k, d, t, out))
+        srv.drain(timeout=60.0)
+        for f, s, C, k, d, t, out in ts:
+            assert srv.poll(t)["state"] == "done"
+            ref, _ = P.bf_vec_ex(f, s, C, k, seed=d * 10 + k, precision=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (prec, d, k)
