@@ -35,16 +35,19 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "ee278452229269408ec5aac345322fbdc04d314c103b163145db9f07ba7b1443",
-    "fp32": {"fetch_kib": 109361538, "write_kib": 70908568},
-    "fp16": {"fetch_kib": 162775326, "write_kib": 71293754},
+    "sha256": "50575575ffa7792d8f330bc97f3c9496d851a2590d9e5c6642f405329a7eb630",
+    "fp32": {"fetch_kib": 89930162, "write_kib": 67206877,
+             # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
+             "executed_flops": 142493114368 * 64},
+    "fp16": {"fetch_kib": 147246899, "write_kib": 70395246,
+             # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
+             "executed_flops": (145995333632 + 5494587392) * 64},
     "fetch_factor": 1048576 / 524306,
     "write_factor": 1.0,
 }
 
 
-def measured_traffic(prec):
-    """HBM bytes per launch for the current kernel sources, or None."""
+def _counters(prec):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -52,8 +55,22 @@ def measured_traffic(prec):
             h.update(fh.read())
     if h.hexdigest() != TRAFFIC["sha256"] or prec not in TRAFFIC:
         return None
-    t = TRAFFIC[prec]
+    return TRAFFIC[prec]
+
+
+def measured_traffic(prec):
+    """HBM bytes per launch for the current kernel sources, or None."""
+    t = _counters(prec)
+    if t is None:
+        return None
     return (t["fetch_kib"] * TRAFFIC["fetch_factor"] + t["write_kib"] * TRAFFIC["write_factor"]) * 1024
+
+
+def executed_flops(prec):
+    """Executed VALU flops per launch (rocprofv3 counters) for the current
+    kernel sources, or None."""
+    t = _counters(prec)
+    return None if t is None else t["executed_flops"]
 
 
 def log(*a):
@@ -527,6 +544,13 @@ def main():
                          measured_traffic(args.precision) / (kernel_ms * 1e-3) / 1e12),
             "flops_per_launch": flops,
             "kernel_ms": kernel_ms,
+            # executed (not algorithmic) VALU flops from the rocprofv3 counters of
+            # the same kernel build, over this run's launch time
+            "executed_tflops": (None if executed_flops(args.precision) is None else
+                                executed_flops(args.precision) / (kernel_ms * 1e-3) / 1e12),
+            "executed_frac": (None if executed_flops(args.precision) is None else
+                              executed_flops(args.precision) / (kernel_ms * 1e-3) / 1e12
+                              / PEAK_FP32_VALU),
         },
         "cpu_baseline": cpu,
         "direct_comparator": direct,
