@@ -85,7 +85,9 @@ def test_mix_matches_standalone_bitwise(pools):
 
 
 def test_batched_launches_share_requests(pools):
-    # many small requests of one instance: fewer launches than requests
+    # many small requests of one instance arriving together: with N given and
+    # centring off no reduction is needed, so all 40 are ready at admission
+    # and the first round packs them into 16 + 16 + 8 (whole K in one chunk)
     f = pools[0]
     C = 0.05 ** 2 * np.eye(3)
     specs = [(3 + 7 * i % 50, 2 + 11 * i % 60, 9 + i % 13, 20 + i % 17) for i in range(40)]
@@ -93,15 +95,16 @@ def test_batched_launches_share_requests(pools):
         start = srv.clock() + 0.2   # all arrive together, after submission
         tickets = []
         for (y0, x0, H, W) in specs:
-            t, out = srv.submit(f[y0:y0 + H, x0:x0 + W], 2.0, C, 6, seed=9, arrival=start)
+            t, out = srv.submit(f[y0:y0 + H, x0:x0 + W], 2.0, C, 6, seed=9, N=16, center=False,
+                                arrival=start)
             tickets.append((t, out))
         srv.drain(timeout=60.0)
         stats = srv.stats()
         assert stats["completed"] == 40
-        assert stats["launches"] < 40, stats
+        assert stats["rounds"] == 1 and stats["launches"] == 3, stats
         for (y0, x0, H, W), (t, out) in list(zip(specs, tickets))[::7]:
-            ref, _ = P.bf_vec_ex(f[y0:y0 + H, x0:x0 + W].contiguous(), 2.0, C, 6, seed=9,
-                                 precision="fp16")
+            ref, _ = P.bf_vec_ex(f[y0:y0 + H, x0:x0 + W].contiguous(), 2.0, C, 6, seed=9, N=16,
+                                 center=False, precision="fp16")
             torch.cuda.synchronize()
             assert torch.equal(out, ref)
             st = srv.poll(t)
