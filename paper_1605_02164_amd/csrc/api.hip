@@ -164,6 +164,9 @@ int check_fused_size(int H, int W, int pitch, int d, int R) {
 }
 
 void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH) {
+  // The kernel prefetches accumulators two steps ahead, which needs at least
+  // two steps per term: with no look-ahead rows (R = 0) strips are >= 16 rows.
+  if (lag_steps(R) + TH / kB < 2) TH = 2 * kB;
   a.H = H;
   a.W = W;
   a.R = R;
@@ -273,7 +276,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = K;
-  o->tile_h_used = TH;
+  o->tile_h_used = a.TH;
 
   // one stream-ordered allocation: accumulators | terms | weights | taps
   const size_t n_acc = fused_acc_floats(a, d);

@@ -102,7 +102,8 @@ int model_strip_height(int d, int R, int prec, int H, int W);
 // d, R, precision and the image shape.
 void record_tuned_height(int d, int R, int prec, int H, int W, int TH);
 int tuned_height(int d, int R, int prec, int H, int W);
-// Strip geometry, staging width and ring sizes of a FusedArgs.
+// Strip geometry, staging width and ring sizes of a FusedArgs (TH is raised
+// to 16 when R = 0 so that every term has at least two pipeline steps).
 void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH);
 // Accumulator floats of a planned FusedArgs: (d+1) planes of Hp x Wp.
 size_t fused_acc_floats(const FusedArgs& a, int d);

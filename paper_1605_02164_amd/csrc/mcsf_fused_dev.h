@@ -614,6 +614,15 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // the A/B prefetch buffers keep fixed roles.
   load_f(fA, 0);
   load_f(fB, steps > 1 ? 1 : 0);
+  // Accumulators of global steps 0 and 1.  Later steps are prefetched two
+  // ahead inside the loop, which is exact because a term has at least two
+  // steps (the host guarantees it): the rows of step g + 2 were last written
+  // in step g + 2 - steps <= g.  These two only matter when the launch
+  // resumes a term range (t0 > 0) and the vertical pass already writes in
+  // step 0 or 1 (2R <= 8 rows of look-ahead).
+  load_acc(aA, t0, 0);
+  if (steps > 1) load_acc(aB, t0, 1);
+  else load_acc(aB, t0 + 1, 0);
   load_term(t0);
   const int total = (t1 - t0) * steps;
   int t = t0, s = 0;

@@ -384,3 +384,24 @@ def test_autotune_records_height_and_keeps_bits():
         got, o = P.bf_vec_ex(fg, 5.0, C, 8, 3, precision=prec, return_opts=True)
         assert o.tile_h_used == th and o0.tile_h_used == 8
         assert np.array_equal(host(got), ref)
+
+
+def test_normaliser_counts_every_term_without_window():
+    # sigma_s = 0: each term adds cos^2 + sin^2 = 1 to Z at every pixel, so Z
+    # must equal K exactly up to rounding; the output alone (f) cannot show a
+    # lost term (regression: single-step terms with the narrowest strips)
+    say("case sigma_s = 0 normaliser")
+    g = voronoi_image(25, 19, 3, 4, 0.0, 1.0, 0.02, 5)
+    fg = cuda(g)
+    for th in (0, 8, 16):
+        for prec in ("fp32", "fp16"):
+            z = torch.empty(25, 19, device="cuda")
+            out, o = P.bf_vec_ex(fg, 0.0, np.eye(3) * 0.01, 7, 1, z_out=z, tile_h=th,
+                                 precision=prec, return_opts=True)
+            zh = host(z)
+            assert o.tile_h_used >= 16
+            # FP16 stores cos and sin with relative error 2^-11 each: |Z - 7| <= 7e-3;
+            # a lost term would move Z by about 1
+            tol = 1e-4 if prec == "fp32" else 1e-2
+            assert np.max(np.abs(zh - 7.0)) < tol, (th, prec, zh.min(), zh.max())
+            assert np.max(np.abs(host(out) - g)) < 1e-3

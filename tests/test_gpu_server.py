@@ -216,3 +216,88 @@ def test_every_dimension_served_equals_standalone(prec):
             ref, _ = P.bf_vec_ex(f, s, C, k, seed=d * 10 + k, precision=prec)
             torch.cuda.synchronize()
             assert torch.equal(out, ref), (prec, d, k)
+
+
+def test_random_mix_matches_standalone():
+    # 60 seeded random requests: every d, odd sizes, windows up to R = 39,
+    # K up to 40, all precisions, merged draws, centring on/off, given N
+    rng = np.random.default_rng(2024)
+    reqs = []
+    for i in range(60):
+        d = int(rng.integers(1, 9))
+        H, W = int(rng.integers(1, 160)), int(rng.integers(1, 160))
+        sigma = float(rng.choice([0.0, 0.7, 1.5, 2.0, 3.3, 5.0, 8.0, 13.0]))
+        K = int(rng.integers(1, 41))
+        prec = str(rng.choice(["fp32", "fp16", "bf16"]))
+        N = int(rng.choice([0, 0, 12, 40]))
+        center = bool(rng.integers(0, 2))
+        dedup = bool(rng.integers(0, 2))
+        f = torch.from_numpy(voronoi_image(H, W, d, 5, 0.0, 1.0, 0.02, seed=900 + i)).to(DEV)
+        C = random_spd(d, -2.0, -1.0, seed=i)
+        reqs.append((f, sigma, C, K, 77 + i, N, prec, center, dedup))
+    with P.Server(arena_bytes=1 << 28, quantum_us=float(rng.choice([3.0, 50.0, 1e4]))) as srv:
+        ts = []
+        for f, sigma, C, K, seed, N, prec, center, dedup in reqs:
+            t, out = srv.submit(f, sigma, C, K, seed, N=N, precision=prec, center=center,
+                                dedup=dedup)
+            ts.append((t, out))
+        srv.drain(timeout=120.0)
+        for (f, sigma, C, K, seed, N, prec, center, dedup), (t, out) in zip(reqs, ts):
+            st = srv.poll(t)
+            assert st["state"] == "done", st
+            ref, _ = P.bf_vec_ex(f, sigma, C, K, seed, N=N, precision=prec, center=center,
+                                 dedup=dedup)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (tuple(f.shape), sigma, K, prec, N, center, dedup)
+
+
+def test_concurrent_submitters():
+    # four host threads submit at once; every request completes and equals
+    # the standalone call
+    import threading
+    C = 0.08 ** 2 * np.eye(3)
+    imgs = [torch.from_numpy(voronoi_image(64 + 8 * i, 80, 3, 9, 0.0, 1.0, 0.02, seed=40 + i))
+            .to(DEV) for i in range(4)]
+    with P.Server(arena_bytes=1 << 28, quantum_us=20.0) as srv:
+        results, errors = {}, []
+
+        def worker(i):
+            try:
+                for k in range(8):
+                    t, out = srv.submit(imgs[i], 2.0, C, 4 + k, seed=100 * i + k)
+                    results[(i, k)] = (t, out)
+            except Exception as e:   # surfaced below
+                errors.append(e)
+
+        th = [threading.Thread(target=worker, args=(i,)) for i in range(4)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert not errors, errors
+        srv.drain(timeout=60.0)
+        assert srv.stats()["completed"] == 32
+        for (i, k), (t, out) in results.items():
+            ref, _ = P.bf_vec_ex(imgs[i], 2.0, C, 4 + k, seed=100 * i + k, precision="fp16")
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (i, k)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_resumed_term_ranges_small_radius(prec):
+    # one term per round: every launch after the first resumes at t0 > 0; with
+    # 2R <= 8 the vertical pass writes in the launch's first two steps, whose
+    # accumulators must be loaded at launch start (regression)
+    f = torch.from_numpy(voronoi_image(57, 71, 3, 8, 0.0, 1.0, 0.02, seed=5)).to(DEV)
+    C = 0.1 ** 2 * np.eye(3)
+    with P.Server(arena_bytes=1 << 28, quantum_us=1e-9) as srv:   # below any term's cost
+        ts = []
+        for sigma in (0.0, 0.4, 0.7, 1.0, 1.3, 2.0):
+            t, out = srv.submit(f, sigma, C, 24, seed=3, precision=prec)
+            ts.append((sigma, t, out))
+        srv.drain(timeout=60.0)
+        for sigma, t, out in ts:
+            assert srv.poll(t)["chunks"] == 24
+            ref, _ = P.bf_vec_ex(f, sigma, C, 24, seed=3, precision=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), sigma
