@@ -28,22 +28,22 @@ PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: the same without packed-FP32 issue
 
 # HBM bytes per launch of the benchmark's fused kernel, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
-# counters read for a 1 GiB device copy (FETCH_SIZE 524,306 KiB: factor
-# 1.99993; WRITE_SIZE 1,048,576 KiB: factor 1.0).  Valid only for the kernel
+# counters read for a 1 GiB device copy (FETCH_SIZE 524,308.8125 KiB: factor
+# 1.99992; WRITE_SIZE 1,048,576 KiB: factor 1.0).  Valid only for the kernel
 # sources they were taken on (TRAFFIC_SOURCES hash); otherwise reported null.
 TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "50575575ffa7792d8f330bc97f3c9496d851a2590d9e5c6642f405329a7eb630",
-    "fp32": {"fetch_kib": 89930162, "write_kib": 67206877,
+    "sha256": "4978d87ac0d8e06bab3bbd157c7fab40e73bae46a84933e4513cff42d5551e23",
+    "fp32": {"fetch_kib": 90256311, "write_kib": 67477107,
              # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
              "executed_flops": 142493114368 * 64},
-    "fp16": {"fetch_kib": 147246899, "write_kib": 70395246,
+    "fp16": {"fetch_kib": 145170815, "write_kib": 70255194,
              # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
              "executed_flops": (145995333632 + 5494587392) * 64},
-    "fetch_factor": 1048576 / 524306,
-    "write_factor": 1.0,
+    "fetch_factor": 1048576 / 524308.8125,
+    "write_factor": 1048576 / 1048576.0,
 }
 
 
