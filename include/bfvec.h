@@ -158,6 +158,43 @@ int bf_direct(const float* f, int H, int W, int d, double sigma_s,
               const double* C, float* out);
 
 /* ------------------------------------------------------------------------
+ * Fixed-shape plans: Algorithm 1 for a stream of images that share shape,
+ * sigma_s, C, K, seed and options.
+ *
+ * bf_plan_create does the host work of bf_vec_ex once: whitening (eq. (COB)),
+ * the draws of Proposition 2, the term and tap table and its upload, the
+ * strip geometry, and the device allocations (accumulators, table, min/max
+ * partials), all owned by the plan.  bf_plan_execute then queues one HIP
+ * graph on `stream` (NULL = null stream) and returns without waiting: the
+ * per-channel min/max (centring on only), the fused term loop and the final
+ * division of Algorithm 1.  With centring the kernels read the centre from
+ * the device min/max result, formed as bf_vec_ex forms it on the host, so
+ * out is bit-identical to bf_vec_ex with the same arguments and options.
+ * ------------------------------------------------------------------------ */
+typedef struct bf_plan bf_plan;   /* opaque */
+
+/* Create a plan for H x W x d images.  o (NULL = defaults) selects
+ * precision, center, tile_h and dedup as for bf_vec_ex; o->N must be explicit
+ * (1..65536: the automatic rule needs each image's range on the host), and
+ * num_out, z_out and time_kernel must be unset.  o->N_used, o->K_used and
+ * o->tile_h_used are written.  Synchronous (uploads the table).  Errors as
+ * bf_vec_ex; *plan is NULL on failure. */
+int bf_plan_create(int H, int W, int d, double sigma_s, const double* C,
+                   int K, uint64_t seed, bf_opts* o, bf_plan** plan);
+
+/* Filter device image f (H x W x d, contiguous) into out (same layout, not
+ * overlapping f), queued on `stream`.  The graph of each (f, out) pair is
+ * captured on first use; the plan keeps the four most recently used.  f is
+ * not checked for NaN or infinity (the output is then unspecified).
+ * Executions of one plan share its accumulators: queue them on one stream,
+ * or order them, and do not overlap them. */
+int bf_plan_execute(bf_plan* plan, const float* f, float* out, void* stream);
+
+/* Wait for the device, then free the plan's graphs and memory.  NULL is a
+ * no-op. */
+int bf_plan_destroy(bf_plan* plan);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of many filter requests on one GPU.
  *
  * A server owns a device arena (accumulators, term tables, reduction

@@ -31,6 +31,7 @@ EXPORTS = [
     "bf_server_config_init", "bf_request_init", "bf_server_create", "bf_server_submit",
     "bf_server_poll", "bf_server_wait", "bf_server_drain", "bf_server_forget",
     "bf_server_get_stats", "bf_server_clock", "bf_server_destroy",
+    "bf_plan_create", "bf_plan_execute", "bf_plan_destroy",
 ]
 
 
@@ -165,11 +166,15 @@ def lib():
     L.bf_server_clock.argtypes = [P]
     L.bf_server_clock.restype = D
     L.bf_server_destroy.argtypes = [P]
+    L.bf_plan_create.argtypes = [I, I, I, D, P, I, U64, ctypes.POINTER(bf_opts), ctypes.POINTER(P)]
+    L.bf_plan_execute.argtypes = [P, P, P, P]
+    L.bf_plan_destroy.argtypes = [P]
     for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_sample_terms",
                  "bf_choose_N", "bf_minmax", "bf_direct", "bf_autotune", "bf_version",
                  "bf_server_create",
                  "bf_server_submit", "bf_server_poll", "bf_server_wait", "bf_server_drain",
-                 "bf_server_forget", "bf_server_get_stats", "bf_server_destroy"):
+                 "bf_server_forget", "bf_server_get_stats", "bf_server_destroy",
+                 "bf_plan_create", "bf_plan_execute", "bf_plan_destroy"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -334,6 +339,53 @@ def bf_direct(f, sigma_s, C, out=None):
     Ch = _host_f64(C, (d, d))
     _check(lib().bf_direct(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), out.data_ptr()))
     return out
+
+
+class Plan:
+    """A fixed-shape plan (bf_plan_* of the C ABI): the host work of
+    bf_vec_ex done once for (H, W, d, sigma_s, C, K, seed, options), then one
+    HIP graph launch per image.  ``N`` must be explicit."""
+
+    def __init__(self, H, W, d, sigma_s, C, K, seed, N, precision="fp32", center=True,
+                 tile_h=0, dedup=False):
+        Ch = _host_f64(C, (d, d))
+        o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup)
+        h = ctypes.c_void_p()
+        _check(lib().bf_plan_create(int(H), int(W), int(d), float(sigma_s), _ptr(Ch), int(K),
+                                    int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(o),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.shape = (int(H), int(W), int(d))
+        self.N_used, self.K_used, self.tile_h_used = o.N_used, o.K_used, o.tile_h_used
+
+    def __call__(self, f, out=None, stream=None):
+        """Queue the filter of f into out on ``stream`` (default: current
+        stream); returns out without waiting."""
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        out = _check_image(f, out)
+        if tuple(f.shape) != self.shape:
+            raise ValueError(f"plan is for shape {self.shape}, got {tuple(f.shape)}")
+        _check(lib().bf_plan_execute(self._h, f.data_ptr(), out.data_ptr(),
+                                     _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(lib().bf_plan_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version():

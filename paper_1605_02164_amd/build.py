@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbfvec.so")
 
-SOURCES = ["host.cpp", "server.cpp", "api.hip", "mcsf_fused.hip", "mcsf_batch.hip"]
+SOURCES = ["host.cpp", "server.cpp", "plan.cpp", "api.hip", "mcsf_fused.hip",
+           "mcsf_batch.hip"]
 
 # Packed FP32 VALU instructions are disabled for all device code.
 HIPFLAGS = [

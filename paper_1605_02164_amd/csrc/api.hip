@@ -82,18 +82,21 @@ __global__ __launch_bounds__(kMMThreads) void minmax_partial(const float* f, siz
   }
 }
 
-__global__ __launch_bounds__(64) void minmax_final(const float* part, int nparts, float* res) {
+__global__ __launch_bounds__(64) void minmax_final(const float* part, int nparts, int d,
+                                                   float* res) {
   // one wave: lane m < 8 reduces minima of channel m, lanes 8..15 maxima,
-  // lane 16 the non-finite flag
+  // lane 16 the non-finite flag; lanes m < d then form the midpoints
   const int l = threadIdx.x;
+  float v = l < 8 ? INFINITY : (l < 16 ? -INFINITY : 0.0f);
   if (l < 17) {
-    float v = l < 8 ? INFINITY : (l < 16 ? -INFINITY : 0.0f);
     for (int i = 0; i < nparts; ++i) {
       const float x = part[(size_t)i * 17 + l];
       v = l < 8 ? fminf(v, x) : (l < 16 ? fmaxf(v, x) : fmaxf(v, x));
     }
     res[l] = v;
   }
+  const float hi = __shfl_down(v, 8);
+  if (l < 8) res[17 + l] = l < d ? (float)(0.5 * ((double)v + (double)hi)) : 0.0f;
 }
 
 }  // namespace
@@ -109,7 +112,7 @@ hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* 
                      part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(minmax_final, dim3(1), dim3(64), 0, st, part, nparts, res);
+  hipLaunchKernelGGL(minmax_final, dim3(1), dim3(64), 0, st, part, nparts, d, res);
   return hipGetLastError();
 }
 
@@ -118,7 +121,7 @@ namespace {
 int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStream_t st) {
   const int nparts = minmax_parts((size_t)H * W);
   float* dbuf = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&dbuf, ((size_t)nparts * 17 + 17) * sizeof(float), st),
+  HIP_TRY(hipMallocAsync((void**)&dbuf, ((size_t)nparts * 17 + kMMResult) * sizeof(float), st),
           "hipMallocAsync(minmax)");
   float* res = dbuf + (size_t)nparts * 17;
   hipError_t e = launch_minmax(f, H, W, W, d, dbuf, nparts, res, st);

@@ -43,6 +43,7 @@ struct FusedArgs {
   const float* terms;    // term table (device): row t holds w_t / 2pi in its first d of d+1 floats
   const float* weights;  // K term weights (device), or null for equal weights
   float cen[8];          // per-channel centre subtracted before the phase
+  const float* cen_dev;  // or null; else the centre is read here (device, d floats)
   int H, W, R;
   int fpitch;            // pixels between vertically adjacent pixels of f (>= W)
   int t0, t1;            // term range of this launch; the accumulators start at zero at term 0
@@ -68,6 +69,7 @@ struct FinalizeArgs {
   float* out;            // H*W*d
   float* num_out;        // optional H*W*d numerator (uncentred) or null
   float* z_out;          // optional H*W normaliser or null
+  const float* cen_dev;  // or null; else the centre is read here (device)
   float cen[8];
   int H, W, Hp, Wp;
 };
@@ -83,8 +85,10 @@ hipError_t launch_finalize(int d, const FinalizeArgs& a, hipStream_t st);
 
 // Per-channel extrema of an image with row pitch `pitch` pixels, in two
 // kernels: nparts partial blocks into part (nparts*17 floats), then the
-// final reduction into res (17 floats: d minima at 0.., d maxima at 8..,
-// a non-finite flag at 16).
+// final reduction into res (kMMResult floats: d minima at 0.., d maxima at
+// 8.., a non-finite flag at 16, and the midpoints (float)((lo + hi) / 2),
+// formed in FP64 as the host does, at 17.. (zero past d)).
+constexpr int kMMResult = 25;
 int minmax_parts(size_t npx);
 hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* part, int nparts,
                          float* res, hipStream_t st);

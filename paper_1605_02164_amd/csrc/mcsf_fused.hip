@@ -24,8 +24,9 @@ __global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
 #pragma unroll
   for (int m = 0; m < D; ++m) {
     const float num = a.acc[(size_t)m * plane + j];
-    a.out[i * D + m] = num / Z + a.cen[m];
-    if (a.num_out) a.num_out[i * D + m] = fmaf(a.cen[m], Z, num);
+    const float c = a.cen_dev ? a.cen_dev[m] : a.cen[m];
+    a.out[i * D + m] = num / Z + c;
+    if (a.num_out) a.num_out[i * D + m] = fmaf(c, Z, num);
   }
   if (a.z_out) a.z_out[i] = Z;
 }

@@ -444,6 +444,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // stay in flight across the passes, and this lane's accumulators for the
   // output rows of the step.
   const int steps = a.steps, lag = a.lag, t0 = a.t0, t1 = a.t1;
+  float cen[D];   // per-channel centre: kernel argument, or device memory (graph plans)
+#pragma unroll
+  for (int m = 0; m < D; ++m) cen[m] = a.cen_dev ? ld_const(a.cen_dev, m) : a.cen[m];
   const unsigned frow = (unsigned)a.fpitch * D;  // floats per row of f
   float fA[MI][D], fB[MI][D];
   float aA[2] = {0.0f, 0.0f}, aB[2] = {0.0f, 0.0f};
@@ -492,7 +495,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         const bool in = m_xin[i] && y >= 0 && y < Hd;
         float fv[D];
 #pragma unroll
-        for (int m = 0; m < D; ++m) fv[m] = fcur[i][m] - a.cen[m];
+        for (int m = 0; m < D; ++m) fv[m] = fcur[i][m] - cen[m];
         float rho = 0.0f;
 #pragma unroll
         for (int m = 0; m < D; ++m) rho = fmaf(wr[m], fv[m], rho);

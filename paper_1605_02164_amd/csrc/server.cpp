@@ -45,7 +45,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 constexpr size_t kAlign = 256;
-constexpr int kMMFloats = 17;  // min/max result block: 8 minima, 8 maxima, flag
+constexpr int kMMFloats = 17;  // min/max partial block: 8 minima, 8 maxima, flag
 
 // Modelled device cost of one term of a planned request, in microseconds:
 // executed flops of all its workgroup steps (modulation of the haloed rows,
@@ -574,7 +574,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   r->n_tab = (size_t)in.K * (in.d + 2) + (size_t)(2 * r->R + 1);
   r->need_minmax = in.N == 0 || in.center;
   r->nparts = minmax_parts((size_t)in.H * in.W);
-  const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMFloats : 0;
+  const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMResult : 0;
   r->dev_bytes = Arena::round_up((r->n_acc + r->n_tab) * sizeof(float), kAlign) +
                  Arena::round_up(n_part * sizeof(float), kAlign);
   r->pin_bytes = (32 + r->n_tab) * sizeof(float);

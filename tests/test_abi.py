@@ -159,3 +159,30 @@ def test_autotune_validation_before_device_work():
     assert L.bf_autotune(fake, 16, 16, 3, 2.0, 7, None, ctypes.byref(th), None) == B.BF_EINVAL
     assert L.bf_autotune(fake, 16, 16, 3, 14.0, 0, None, ctypes.byref(th), None) == B.BF_EUNSUPPORTED
     assert L.bf_autotune(None, 16, 16, 3, 2.0, 0, None, ctypes.byref(th), None) == B.BF_EINVAL
+
+
+def test_plan_validation_before_device_work():
+    L = P.lib()
+    C = np.eye(3) * 0.01
+    Cp = C.ctypes.data_as(ctypes.c_void_p)
+    h = ctypes.c_void_p(0x1234)
+
+    def create(H=16, W=16, d=3, sigma=2.0, Cp=Cp, K=4, **kw):
+        o = B.make_opts(**{"N": 12, **kw})
+        return L.bf_plan_create(H, W, d, sigma, Cp, K, 1, ctypes.byref(o), ctypes.byref(h))
+
+    assert create(N=0) == B.BF_EINVAL                     # the order must be explicit
+    assert h.value is None                                # *plan is cleared on failure
+    assert create(H=0) == B.BF_EINVAL
+    assert create(d=9) == B.BF_EINVAL
+    assert create(K=0) == B.BF_EINVAL
+    assert create(sigma=float("nan")) == B.BF_EINVAL
+    assert create(Cp=None) == B.BF_EINVAL
+    assert create(precision=7) == B.BF_EINVAL
+    assert create(time_kernel=True) == B.BF_EINVAL
+    bad = np.array([[1.0, 2, 0], [2, 1, 0], [0, 0, 1]])
+    assert create(Cp=bad.ctypes.data_as(ctypes.c_void_p)) == B.BF_ENOTSPD
+    assert create(sigma=14.0) == B.BF_EUNSUPPORTED
+    assert L.bf_plan_create(16, 16, 3, 2.0, Cp, 4, 1, None, None) == B.BF_EINVAL
+    assert L.bf_plan_execute(None, 0x1000, 0x100000, None) == B.BF_EINVAL
+    assert L.bf_plan_destroy(None) == B.BF_OK
