@@ -214,6 +214,56 @@ def serving_run(args, P, torch, log_fn):
     return rec
 
 
+def plan_run(P, torch, log_fn, reps=200):
+    """Fixed-shape plans against bf_vec_ex on serving-sized images (d = 3,
+    FP16 storage, centring on, N = 20, Voronoi colour images): the latency of
+    one image (call + device synchronisation; median and p99 of `reps`), and
+    the rate of `reps` images queued back to back (bf_vec_ex waits for each
+    image's min/max on the host; a plan's execution waits for nothing)."""
+    import numpy as np
+    from synth import voronoi_image
+    dev = torch.device("cuda:0")
+    res = []
+    for side, sigma_s, K in ((256, 2.0, 64), (512, 4.0, 64), (1024, 8.0, 128)):
+        f = torch.from_numpy(voronoi_image(side, side, 3, 24, 0.0, 1.0, 0.02, seed=side)).to(dev)
+        C = 0.1 ** 2 * np.eye(3)
+        o1, o2 = torch.empty_like(f), torch.empty_like(f)
+        kw = dict(N=20, precision="fp16")
+        plan = P.Plan(side, side, 3, sigma_s, C, K, 7, **kw)
+
+        def eager():
+            P.bf_vec_ex(f, sigma_s, C, K, 7, out=o1, **kw)
+
+        def graph():
+            plan(f, o2)
+
+        row = {"side": side, "sigma_s": sigma_s, "K": K}
+        for name, fn in (("bf_vec_ex", eager), ("plan", graph)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            lat = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                lat.append(1e3 * (time.perf_counter() - t0))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            rate = reps / (time.perf_counter() - t0)
+            row[name] = {"p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "images_s": rate}
+        row["bitwise_equal"] = bool(torch.equal(o1, o2))
+        plan.close()
+        log_fn(f"plan {side}^2 K={K}: latency p50 {row['bf_vec_ex']['p50_ms']:.3f} ms -> "
+               f"{row['plan']['p50_ms']:.3f} ms, back-to-back {row['bf_vec_ex']['images_s']:.0f}"
+               f" -> {row['plan']['images_s']:.0f} images/s, equal {row['bitwise_equal']}")
+        res.append(row)
+    return res
+
+
 def _timed(fn, reps):
     """Median wall time (ms) of fn() followed by a device synchronisation."""
     import numpy as np
@@ -364,6 +414,8 @@ def main():
     ap.add_argument("--only", action="store_true", help="time only --precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-plan", action="store_true",
+                    help="skip the fixed-shape plan (HIP graph) latency comparison")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the occupancy model's strip height instead of measuring it")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -506,6 +558,10 @@ def main():
     if not args.no_serving:
         serving = serving_run(args, P, torch, log)
 
+    plans = None
+    if not args.no_plan and not args.only:
+        plans = plan_run(P, torch, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
@@ -555,6 +611,7 @@ def main():
         "cpu_baseline": cpu,
         "direct_comparator": direct,
         "serving": serving,
+        "plan": plans,
     }
     print(json.dumps(rec), flush=True)
 
