@@ -13,6 +13,11 @@ channels last.  ``C`` is a (d, d) SPD covariance.  A term table ``w`` is a
 Readings of the paper taken here (the paper is silent or ambiguous):
   * window radius R = ceil(3 sigma_s) (Section 1, square window
     [-3 sigma_s, 3 sigma_s]^2); sigma_s = 0 gives R = 0, the identity;
+  * the other spatial filters the paper allows in place of the Gaussian
+    (Section 3, remark after Algorithm 1: box or hat filters, any spatial
+    filter) are taken as n-fold convolutions of a box of width 2r + 1 (n = 1
+    box, n = 2 hat, n = 3 the usual three-box stand-in for a Gaussian), with r
+    the integer whose variance n((2r+1)^2 - 1)/12 is nearest sigma_s^2;
   * the spatial kernel is unnormalised (it cancels in the ratio);
   * out-of-domain pixels contribute nothing to numerator or normaliser
     (the sums of eqs. (BF)/(normal) run over i - j in Omega);
@@ -34,18 +39,39 @@ from .philox import philox4x32_10
 # ---------------------------------------------------------------------------
 
 
-def window_radius(sigma_s):
-    """R = ceil(3 sigma_s): the sums of eqs. (BF)/(normal) are restricted to
-    the square window [-3 sigma_s, 3 sigma_s]^2 (Section 1)."""
+def box_radius(sigma_s, n):
+    """Half-width r of the box whose n-fold convolution stands in for the
+    Gaussian of standard deviation sigma_s: the variance of one box of width
+    2r + 1 is ((2r+1)^2 - 1)/12, so r solves n((2r+1)^2 - 1)/12 = sigma_s^2,
+    rounded to the nearest integer (halves up)."""
+    x = (math.sqrt(12.0 * float(sigma_s) ** 2 / n + 1.0) - 1.0) / 2.0
+    return int(math.floor(x + 0.5))
+
+
+def window_radius(sigma_s, spatial=0):
+    """Gaussian (spatial = 0): R = ceil(3 sigma_s), the sums of eqs.
+    (BF)/(normal) are restricted to the square window [-3 sigma_s, 3 sigma_s]^2
+    (Section 1).  n-fold box (spatial = n): R = n r, the support of the
+    filter."""
+    if spatial:
+        return spatial * box_radius(sigma_s, spatial)
     if sigma_s == 0:
         return 0
     return int(math.ceil(3.0 * float(sigma_s)))
 
 
-def spatial_taps(sigma_s):
-    """One-dimensional factor of omega in eq. (kernel):
-    omega_1(u) = exp(-u^2 / (2 sigma_s^2)) for u = -R..R, so that
-    omega(j) = omega_1(j_y) * omega_1(j_x).  Unnormalised."""
+def spatial_taps(sigma_s, spatial=0):
+    """One-dimensional factor omega_1(u), u = -R..R, of the separable spatial
+    filter omega(j) = omega_1(j_y) * omega_1(j_x).  Unnormalised.
+    spatial = 0: omega_1(u) = exp(-u^2 / (2 sigma_s^2)) (eq. (kernel)).
+    spatial = n in {1, 2, 3}: the n-fold convolution of the box of ones of
+    width 2r + 1 (r from ``box_radius``): box, hat, three boxes."""
+    if spatial:
+        r = box_radius(sigma_s, spatial)
+        taps = np.ones(1)
+        for _ in range(spatial):
+            taps = np.convolve(taps, np.ones(2 * r + 1))
+        return taps
     R = window_radius(sigma_s)
     if R == 0:
         return np.ones(1)
@@ -209,7 +235,7 @@ def psi_sampled(Delta, w, weights=None):
 # ---------------------------------------------------------------------------
 
 
-def _direct(f, sigma_s, kernel, pixels=None):
+def _direct(f, sigma_s, kernel, pixels=None, spatial=0):
     """out(i) = sum_j omega(j) k(f(i-j) - f(i)) f(i-j) / sum_j omega(j) k(...),
     the sums running over j in [-R, R]^2 with i - j inside the image
     (eqs. (BF), (normal), Section 1 window).  ``kernel`` maps an (..., d) array
@@ -217,8 +243,8 @@ def _direct(f, sigma_s, kernel, pixels=None):
     (n, 2) integer array of (y, x)), or for all pixels as (H, W, d), (H, W)."""
     f = np.asarray(f, dtype=np.float64)
     H, Wd, d = f.shape
-    R = window_radius(sigma_s)
-    w1 = spatial_taps(sigma_s)
+    R = window_radius(sigma_s, spatial)
+    w1 = spatial_taps(sigma_s, spatial)
     if pixels is None:
         pix = np.stack(np.meshgrid(np.arange(H), np.arange(Wd), indexing="ij"),
                        axis=-1).reshape(-1, 2)
@@ -239,18 +265,18 @@ def _direct(f, sigma_s, kernel, pixels=None):
     return out, Z
 
 
-def direct_exact(f, sigma_s, C, pixels=None):
+def direct_exact(f, sigma_s, C, pixels=None, spatial=0):
     """O1: the bilateral filter of eqs. (BF)/(normal) with the Gaussian range
     kernel of eq. (kernel), evaluated directly (O(sigma_s^2) per pixel)."""
     C = check_covariance(C)
-    return _direct(f, sigma_s, lambda D: psi_gauss(D, C), pixels)
+    return _direct(f, sigma_s, lambda D: psi_gauss(D, C), pixels, spatial)
 
 
-def direct_sampled(f, sigma_s, w, pixels=None, weights=None):
+def direct_sampled(f, sigma_s, w, pixels=None, weights=None, spatial=0):
     """O2: eqs. (BF)/(normal) with phi replaced by the sampled kernel
     psi_K(D) = (1/K) sum_t cos<w_t, D> (eqs. (finalApproxY), (bigExp))."""
     w = np.asarray(w, dtype=np.float64)
-    return _direct(f, sigma_s, lambda D: psi_sampled(D, w, weights), pixels)
+    return _direct(f, sigma_s, lambda D: psi_sampled(D, w, weights), pixels, spatial)
 
 
 def direct_raised_cosine(f, sigma_s, W, N, pixels=None):
@@ -283,7 +309,7 @@ def _gauss_sep(U, w1):
     return A
 
 
-def mcsf_separable(f, sigma_s, w, weights=None):
+def mcsf_separable(f, sigma_s, w, weights=None, spatial=0):
     """O3: Algorithm 1 with the term draws given as the table ``w`` (K, d).
 
     For each term t (Algorithm 1 loop over t):
@@ -293,13 +319,14 @@ def mcsf_separable(f, sigma_s, w, weights=None):
       P += conj(H) Gbar,  Z += conj(H) Hbar
     and finally out = P / Z (Algorithm 1 last step), keeping real parts:
     Re(conj(H) Gbar) = cos*(omega * cos f) + sin*(omega * sin f).
-    A weighted table multiplies term t's contribution by weights[t].
+    A weighted table multiplies term t's contribution by weights[t];
+    ``spatial`` selects omega as in ``spatial_taps``.
     Returns (out (H, W, d), num (H, W, d), Z (H, W)).
     """
     f = np.asarray(f, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64).reshape(-1, f.shape[-1])
     H, Wd, d = f.shape
-    w1 = spatial_taps(sigma_s)
+    w1 = spatial_taps(sigma_s, spatial)
     ft = np.moveaxis(f, -1, 0)                      # (d, H, W)
     num = np.zeros((d, H, Wd))
     Z = np.zeros((H, Wd))
