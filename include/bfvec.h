@@ -57,6 +57,16 @@ enum {
  * intermediates.  Accumulation of both passes and of num/Z is FP32 always. */
 enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2 };
 
+/* Spatial filter omega (separable, unnormalised).  The paper's eq. (kernel)
+ * Gaussian by default; Section 3 allows any spatial filter in its place, such
+ * as a box or a hat.  BF_SPATIAL_BOX / HAT / BOX3 are the 1-, 2- and 3-fold
+ * convolutions of a box of 2r+1 ones per axis, with r the integer nearest the
+ * root of n((2r+1)^2 - 1)/12 = sigma_s^2 (n boxes have variance sigma_s^2),
+ * window radius R = n r.  With BF_FP32 their vertical pass is a running sum
+ * (cost independent of sigma_s); with 16-bit storage both passes are FIR
+ * passes over the same taps. */
+enum { BF_SPATIAL_GAUSS = 0, BF_SPATIAL_BOX = 1, BF_SPATIAL_HAT = 2, BF_SPATIAL_BOX3 = 3 };
+
 typedef struct bf_opts {
   int N;           /* raised-cosine order (eq. (approx)); 0 = automatic rule  */
   int precision;   /* BF_FP32 (default), BF_FP16, BF_BF16                      */
@@ -78,7 +88,8 @@ typedef struct bf_opts {
                       the distinct +-Y.  0 (default): K terms as drawn          */
   int K_used;      /* OUT: terms the kernel ran (K, or the distinct +-Y count)  */
   int tile_h_used; /* OUT: strip height the fused kernel ran with              */
-  int reserved[2];
+  int spatial;     /* BF_SPATIAL_* (default BF_SPATIAL_GAUSS)                  */
+  int reserved[1];
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,
@@ -246,7 +257,8 @@ typedef struct bf_request {
                            request arrives; <= 0: at submit.  Latency is measured
                            from it; a request is not admitted before it.          */
   int dedup;            /* as bf_opts.dedup: merge equal +-Y draws (exact)        */
-  int reserved[3];
+  int spatial;          /* as bf_opts.spatial: BF_SPATIAL_*                        */
+  int reserved[2];
 } bf_request;
 
 enum {

@@ -22,6 +22,13 @@ REQ_STATES = {BF_REQ_QUEUED: "queued", BF_REQ_PREPARING: "preparing", BF_REQ_RUN
               BF_REQ_DONE: "done", BF_REQ_FAILED: "failed", BF_REQ_CANCELLED: "cancelled"}
 BF_FP32, BF_FP16, BF_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
+BF_SPATIAL_GAUSS, BF_SPATIAL_BOX, BF_SPATIAL_HAT, BF_SPATIAL_BOX3 = 0, 1, 2, 3
+SPATIAL = {"gauss": BF_SPATIAL_GAUSS, "box": BF_SPATIAL_BOX, "hat": BF_SPATIAL_HAT,
+           "box3": BF_SPATIAL_BOX3}
+
+
+def _spatial(v):
+    return SPATIAL[v] if isinstance(v, str) else int(v)
 
 # Every symbol declared in include/bfvec.h.
 EXPORTS = [
@@ -58,7 +65,8 @@ class bf_opts(ctypes.Structure):
         ("dedup", ctypes.c_int),
         ("K_used", ctypes.c_int),
         ("tile_h_used", ctypes.c_int),
-        ("reserved", ctypes.c_int * 2),
+        ("spatial", ctypes.c_int),
+        ("reserved", ctypes.c_int * 1),
     ]
 
 
@@ -91,7 +99,8 @@ class bf_request(ctypes.Structure):
         ("center", ctypes.c_int),
         ("arrival", ctypes.c_double),
         ("dedup", ctypes.c_int),
-        ("reserved", ctypes.c_int * 3),
+        ("spatial", ctypes.c_int),
+        ("reserved", ctypes.c_int * 2),
     ]
 
 
@@ -209,7 +218,7 @@ def _check_image(f, out):
 
 
 def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
-              num_out=None, z_out=None, time_kernel=False, dedup=False):
+              num_out=None, z_out=None, time_kernel=False, dedup=False, spatial="gauss"):
     o = bf_opts()
     lib().bf_opts_init(ctypes.byref(o))
     o.N = int(N)
@@ -221,6 +230,7 @@ def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
     o.z_out = None if z_out is None else z_out.data_ptr()
     o.time_kernel = 1 if time_kernel else 0
     o.dedup = 1 if dedup else 0
+    o.spatial = _spatial(spatial)
     return o
 
 
@@ -243,24 +253,24 @@ def bf_vec(f, sigma_s, C, K, seed, out=None):
 
 def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
               tile_h=0, stream=None, num_out=None, z_out=None, time_kernel=False,
-              return_opts=False, dedup=False):
+              return_opts=False, dedup=False, spatial="gauss"):
     """The filter with options, queued on ``stream`` (torch stream; default:
     current stream).  Returns (out, N_used), or (out, opts) with
     ``return_opts`` (opts.kernel_ms holds the fused-kernel time when
     ``time_kernel`` is set; opts.K_used the number of kernel terms, fewer than
-    K with ``dedup``)."""
+    K with ``dedup``).  ``spatial``: "gauss" (default), "box", "hat", "box3"."""
     out = _check_image(f, out)
     H, W, d = f.shape
     Ch = _host_f64(C, (d, d))
     o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  time_kernel, dedup)
+                  time_kernel, dedup, spatial)
     _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
     return (out, o) if return_opts else (out, o.N_used)
 
 
 def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center=True,
-                 tile_h=0, stream=None, num_out=None, z_out=None):
+                 tile_h=0, stream=None, num_out=None, z_out=None, spatial="gauss"):
     """The filter with an explicit (K, d) float64 term table and optional
     weights.  Returns out."""
     out = _check_image(f, out)
@@ -270,7 +280,8 @@ def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center
         raise ValueError("w must be (K, d)")
     K = wh.shape[0]
     wt = None if weights is None else _host_f64(weights, (K,))
-    o = make_opts(0, precision, center, tile_h, _stream_handle(stream), num_out, z_out)
+    o = make_opts(0, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
+                  spatial=spatial)
     _check(lib().bf_vec_terms(f.data_ptr(), H, W, d, float(sigma_s), _ptr(wh),
                               None if wt is None else _ptr(wt), K, out.data_ptr(),
                               ctypes.byref(o)))
@@ -347,9 +358,9 @@ class Plan:
     HIP graph launch per image.  ``N`` must be explicit."""
 
     def __init__(self, H, W, d, sigma_s, C, K, seed, N, precision="fp32", center=True,
-                 tile_h=0, dedup=False):
+                 tile_h=0, dedup=False, spatial="gauss"):
         Ch = _host_f64(C, (d, d))
-        o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup)
+        o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup, spatial)
         h = ctypes.c_void_p()
         _check(lib().bf_plan_create(int(H), int(W), int(d), float(sigma_s), _ptr(Ch), int(K),
                                     int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(o),
@@ -433,7 +444,7 @@ class Server:
         self._refs = {}
 
     def submit(self, f, sigma_s, C, K, seed, out=None, N=0, precision="fp16", center=True,
-               arrival=0.0, dedup=False):
+               arrival=0.0, dedup=False, spatial="gauss"):
         """Queue the filter of ``f`` (see bf_vec_ex for the arguments);
         ``arrival`` is the server-clock time the request arrives (0: now).
         Returns (ticket, out)."""
@@ -457,6 +468,7 @@ class Server:
         r.center = 1 if center else 0
         r.arrival = float(arrival)
         r.dedup = 1 if dedup else 0
+        r.spatial = _spatial(spatial)
         t = ctypes.c_uint64()
         _check(lib().bf_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         self._refs[t.value] = (f, out)

@@ -150,6 +150,8 @@ int check_opts(const bf_opts* o) {
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
+  if (o->spatial < BF_SPATIAL_GAUSS || o->spatial > BF_SPATIAL_BOX3)
+    return fail(BF_EINVAL, "opts.spatial must be a BF_SPATIAL_* value");
   return BF_OK;
 }
 
@@ -166,7 +168,7 @@ int check_fused_size(int H, int W, int pitch, int d, int R) {
   return BF_OK;
 }
 
-void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH) {
+void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox) {
   // The kernel prefetches accumulators two steps ahead, which needs at least
   // two steps per term: with no look-ahead rows (R = 0) strips are >= 16 rows.
   if (lag_steps(R) + TH / kB < 2) TH = 2 * kB;
@@ -176,9 +178,10 @@ void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH) {
   a.TH = TH;
   a.nsx = (W + kTW - 1) / kTW;
   a.nsy = (H + TH - 1) / TH;
-  a.SW = prec == BF_FP32 ? stage_width(R) : stage_width16(R);
+  a.SW = (prec == 1 || prec == 2) ? stage_width16(R) : stage_width(R);
   a.lag = lag_steps(R);
-  a.RSB = a.lag + 1;
+  a.RSB = ring_steps(R, vbox);
+  a.vbox = vbox;
   a.CRB = a.lag + 2;
   a.steps = a.lag + TH / kB;
   a.Hp = a.nsy * TH;
@@ -189,9 +192,9 @@ size_t fused_acc_floats(const FusedArgs& a, int d) {
 }
 
 std::vector<float> term_table(int d, int K, const double* w, const double* weights,
-                              double sigma_s, size_t* off_weights, size_t* off_taps) {
+                              double sigma_s, size_t* off_weights, size_t* off_taps, int spatial) {
   const int NP = d + 1;
-  const int ntaps = 2 * window_radius(sigma_s) + 1;
+  const int ntaps = 2 * window_radius(sigma_s, spatial) + 1;
   const double two_pi = 6.283185307179586476925286766559;
   const size_t n_terms = (size_t)K * NP, n_w = weights ? (size_t)K : 0;
   std::vector<float> h(n_terms + n_w + (size_t)ntaps, 0.0f);
@@ -199,7 +202,7 @@ std::vector<float> term_table(int d, int K, const double* w, const double* weigh
     for (int m = 0; m < d; ++m) h[(size_t)t * NP + m] = (float)(w[(size_t)t * d + m] / two_pi);
   if (weights)
     for (int t = 0; t < K; ++t) h[n_terms + t] = (float)weights[t];
-  const std::vector<double> taps = spatial_taps(sigma_s);
+  const std::vector<double> taps = spatial_taps(sigma_s, spatial);
   for (int u = 0; u < ntaps; ++u) h[n_terms + n_w + u] = (float)taps[u];
   *off_weights = weights ? n_terms : (size_t)-1;
   *off_taps = n_terms + n_w;
@@ -256,10 +259,10 @@ namespace {
 
 // Checks that need no device work: window size, precision, strip height.
 int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
-  const int R = window_radius(sigma_s);
+  const int R = window_radius(sigma_s, o->spatial);
   const int rc = check_fused_size(H, W, W, d, R);
   if (rc) return rc;
-  return choose_strip_height(d, R, o->precision, H, W, o->tile_h, TH);
+  return choose_strip_height(d, R, kernel_variant(o->precision, o->spatial), H, W, o->tile_h, TH);
 }
 
 // Launch the fused filter for a host FP64 term table (radians per unit).
@@ -267,15 +270,17 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
               const double* weights, int K, float* out, bf_opts* o, const float* lo,
               const float* hi, int TH) {
   hipStream_t st = (hipStream_t)o->stream;
-  const int R = window_radius(sigma_s);
+  const int R = window_radius(sigma_s, o->spatial);
+  const int variant = kernel_variant(o->precision, o->spatial);
   size_t off_w = 0, off_taps = 0;
-  const std::vector<float> hbuf = term_table(d, K, w, weights, sigma_s, &off_w, &off_taps);
+  const std::vector<float> hbuf =
+      term_table(d, K, w, weights, sigma_s, &off_w, &off_taps, o->spatial);
 
   FusedArgs a{};
   a.f = f;
   for (int m = 0; m < 8; ++m)
     a.cen[m] = (o->center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
-  fused_geometry(a, H, W, R, o->precision, TH);
+  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? o->spatial : 0);
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = K;
@@ -299,7 +304,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     if (e == hipSuccess) e = hipEventRecord(ev0, st);
   }
-  if (e == hipSuccess) e = launch_fused(d, o->precision, a, st);
+  if (e == hipSuccess) e = launch_fused(d, variant, a, st);
   if (e == hipSuccess && o->time_kernel) e = hipEventRecord(ev1, st);
   if (e == hipSuccess) {
     FinalizeArgs fa{};

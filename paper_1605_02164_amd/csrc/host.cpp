@@ -24,12 +24,30 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-int window_radius(double sigma_s) {
+int box_radius(double sigma_s, int n) {
+  const double x = (std::sqrt(12.0 * sigma_s * sigma_s / n + 1.0) - 1.0) / 2.0;
+  return (int)std::floor(x + 0.5);
+}
+
+int window_radius(double sigma_s, int spatial) {
+  if (spatial > 0) return spatial * box_radius(sigma_s, spatial);
   if (sigma_s == 0.0) return 0;
   return (int)std::ceil(3.0 * sigma_s);
 }
 
-std::vector<double> spatial_taps(double sigma_s) {
+std::vector<double> spatial_taps(double sigma_s, int spatial) {
+  if (spatial > 0) {
+    // repeated convolution with a box of 2r+1 ones, in integers (exact)
+    const int r = box_radius(sigma_s, spatial);
+    std::vector<long long> c(1, 1);
+    for (int k = 0; k < spatial; ++k) {
+      std::vector<long long> nc(c.size() + 2 * r, 0);
+      for (size_t i = 0; i < c.size(); ++i)
+        for (int j = 0; j <= 2 * r; ++j) nc[i + j] += c[i];
+      c.swap(nc);
+    }
+    return std::vector<double>(c.begin(), c.end());
+  }
   const int R = window_radius(sigma_s);
   std::vector<double> t(2 * R + 1, 1.0);
   if (R == 0) return t;

@@ -14,11 +14,20 @@ void clear_error();
 // Returns a status code after recording msg.
 int fail(int code, const std::string& msg);
 
-// Window radius R = ceil(3 sigma_s) (square window of the paper's Section 1).
-int window_radius(double sigma_s);
+// Window radius: R = ceil(3 sigma_s) for the Gaussian (spatial = 0; square
+// window of the paper's Section 1), R = n r for the n-fold box (spatial = n).
+int window_radius(double sigma_s, int spatial = 0);
 
-// One-dimensional factor of the spatial Gaussian, omega_1(u) for u = -R..R.
-std::vector<double> spatial_taps(double sigma_s);
+// Half-width r of one box of the n-fold box filter standing in for a Gaussian
+// of deviation sigma_s: the integer nearest the root of
+// n((2r+1)^2 - 1)/12 = sigma_s^2 (the n-fold box's variance), halves up.
+int box_radius(double sigma_s, int n);
+
+// One-dimensional factor omega_1(u), u = -R..R, of the separable spatial
+// filter: exp(-u^2 / 2 sigma_s^2) (eq. (kernel)) for spatial = 0, the n-fold
+// convolution of a box of 2r+1 ones for spatial = n (1 box, 2 hat, 3 three
+// boxes; Section 3 allows any spatial filter in place of the Gaussian).
+std::vector<double> spatial_taps(double sigma_s, int spatial = 0);
 
 // Whitening per eq. (COB); see bf_whiten in bfvec.h.  Returns a status.
 int whiten(int d, const double* C, double* W);

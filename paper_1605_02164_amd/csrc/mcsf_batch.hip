@@ -13,6 +13,7 @@ hipError_t launch_fused_batch(int d, int R, int prec, const BatchArgs& b, hipStr
     case 0: return launch_p<0>(d, b, R, st);
     case 1: return launch_p<1>(d, b, R, st);
     case 2: return launch_p<2>(d, b, R, st);
+    case 3: return launch_p<3>(d, b, R, st);
     default: return hipErrorInvalidValue;
   }
 }

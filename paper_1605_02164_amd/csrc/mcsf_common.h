@@ -34,6 +34,17 @@ inline constexpr int stage_width16(int R) {
 constexpr int kSWMax = stage_width(kRMax);
 // 2R rows of look-ahead, in steps of kB rows
 inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
+// Ring of horizontal-pass rows, in steps of kB rows: the FIR vertical pass
+// reads the 2R rows behind the newest step (vbox = 0); the running-sum pass
+// of the n-fold box also reads the n rows before those (vbox = n).
+inline constexpr int ring_steps(int R, int vbox) { return (2 * R + vbox + 2 * kB - 1) / kB; }
+
+// Kernel variants: 0 FP32, 1 FP16 storage, 2 BF16 storage (FIR passes with
+// any spatial taps), 3 FP32 with the running-sum vertical pass of the n-fold
+// box filters (spatial = n).  16-bit storage runs box filters as FIR taps.
+inline int kernel_variant(int precision, int spatial) {
+  return precision == 0 && spatial > 0 ? 3 : precision;
+}
 
 struct FusedArgs {
   const float* f;        // input (device), row y at f + y*fpitch*d
@@ -53,6 +64,7 @@ struct FusedArgs {
   int SW;                // staging row width (floats)
   int RSB, CRB;          // ring sizes in blocks of kB rows
   int steps, lag;        // steps per term, and 2R look-ahead in steps
+  int vbox;              // variant 3: n of the n-fold box (R = n r); else 0
 };
 
 // Several requests of one kernel instance (same d, R, precision) in one
@@ -74,7 +86,9 @@ struct FinalizeArgs {
   int H, W, Hp, Wp;
 };
 
-// prec: 0 = FP32 channels, 1 = FP16 storage, 2 = BF16 storage (FP32 accumulation)
+// prec: the kernel variant (kernel_variant): 0 = FP32 channels, 1 = FP16
+// storage, 2 = BF16 storage (FP32 accumulation), 3 = FP32 with the
+// running-sum vertical pass
 size_t fused_lds_bytes(int d, int R, int prec);
 // resident workgroups per compute unit for this kernel instance (device query)
 int fused_blocks_per_cu(int d, int R, int prec);
@@ -107,14 +121,17 @@ int model_strip_height(int d, int R, int prec, int H, int W);
 void record_tuned_height(int d, int R, int prec, int H, int W, int TH);
 int tuned_height(int d, int R, int prec, int H, int W);
 // Strip geometry, staging width and ring sizes of a FusedArgs (TH is raised
-// to 16 when R = 0 so that every term has at least two pipeline steps).
-void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH);
+// to 16 when R = 0 so that every term has at least two pipeline steps);
+// vbox = n for variant 3, else 0.
+void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox = 0);
 // Accumulator floats of a planned FusedArgs: (d+1) planes of Hp x Wp.
 size_t fused_acc_floats(const FusedArgs& a, int d);
 // Host term table: K rows of w_t/2pi (stride d+1) | K weights (if any) | 2R+1
-// taps.  Offsets of the weights and taps are returned in floats.
+// taps of the spatial filter.  Offsets of the weights and taps are returned
+// in floats.
 std::vector<float> term_table(int d, int K, const double* w, const double* weights,
-                              double sigma_s, size_t* off_weights, size_t* off_taps);
+                              double sigma_s, size_t* off_weights, size_t* off_taps,
+                              int spatial = 0);
 // Frequencies w_t = W^T Y_t / sqrt(N) of K terms drawn from seed (K x d, radians).
 void frequency_table(int d, const double* Wm, int N, int K, uint64_t seed, double* w);
 // The same K draws merged by +-Y (first nonzero entry of Y made positive), in

@@ -37,15 +37,17 @@ __global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
 
 size_t fused_lds_bytes(int d, int R, int prec) {
   const int NP = d + 1, NC = 2 * NP;
-  const bool lp = prec != 0;
+  const bool lp = prec == 1 || prec == 2, vb = prec == 3;
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
   const int tapp_al = (R + 1 + 3) / 4 * 4;
   const int lag = lag_steps(R);
-  const int RS = (lag + 1) * kB, CRS = (lag + 2) * kB;
+  // variant 3 sizes the ring for the largest n (three boxes)
+  const int RS = ring_steps(R, vb ? 3 : 0) * kB, CRS = (lag + 2) * kB;
   const size_t fl = (size_t)taps_al + (lp ? 2 * (size_t)tapp_al : 0) +
                     (size_t)kB * NC * (lp ? stage_width16(R) / 2 : stage_width(R)) +
-                    (size_t)(lp ? RS / 2 : RS) * NC * kTW + (size_t)CRS * 2 * kTW;
+                    (size_t)(lp ? RS / 2 : RS) * NC * kTW + (size_t)CRS * 2 * kTW +
+                    (vb ? (size_t)16 * NC * kTW : 0);
   return fl * sizeof(float);
 }
 
@@ -98,7 +100,12 @@ static int bpc_p(int d, int R) {
 }
 
 int fused_blocks_per_cu(int d, int R, int prec) {
-  return prec == 0 ? bpc_p<0>(d, R) : prec == 1 ? bpc_p<1>(d, R) : bpc_p<2>(d, R);
+  switch (prec) {
+    case 0: return bpc_p<0>(d, R);
+    case 1: return bpc_p<1>(d, R);
+    case 2: return bpc_p<2>(d, R);
+    default: return bpc_p<3>(d, R);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -177,6 +184,7 @@ hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st) {
     case 0: return launch_p<0>(d, a, a.R, st);
     case 1: return launch_p<1>(d, a, a.R, st);
     case 2: return launch_p<2>(d, a, a.R, st);
+    case 3: return launch_p<3>(d, a, a.R, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -37,6 +37,18 @@
 // (w[2i-1], w[2i]) against the same aligned pair, so every window read is an
 // aligned 32-bit pair and each output costs R+1 dot2 instead of 2R+1 FMAs.
 // Demodulation, accumulation and the division stay FP32.
+//
+// Variant 3 (FP32) runs the n-fold box filters (box, hat, three boxes; the
+// paper allows any spatial filter in place of the Gaussian) with a vertical
+// pass whose cost does not depend on the radius: the n-fold box sum over
+// rows i-2R..i equals the sparse difference
+//   v(i) = sum_{k=0..n} (-1)^k C(n,k) u(i - k(2r+1))
+// of the horizontal-pass rows u, integrated n times (running sums).  The
+// running sums are FP64 registers of a lane per (column, channel), reset at
+// the top of each term's strip; n+1 ring reads and n+3 FP64 operations per
+// output replace 2R+1 FMAs.  The horizontal pass stays a FIR over the box
+// taps: inside a 16-column strip a running sum would still have to start 2R
+// columns to the left.
 
 #include <hip/hip_runtime.h>
 
@@ -330,12 +342,14 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
 template <int D, int RC, int PREC>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
+  static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
   using G = Geo<D>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
   constexpr int TW = kTW, B = kB;
   constexpr int RST = NC * TW;       // ring row stride: [ch][x]
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
-  constexpr bool LP = PREC != 0;
+  constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
+  constexpr bool VB = PREC == 3;                 // running-sum vertical pass
   constexpr int NTAPR = (RC >= 0 && !LP) ? RC + 1 : 1;    // taps 0..R (symmetric)
   constexpr int NTAPP = (RC >= 0 && LP) ? RC + 1 : 1;   // packed tap pairs
 
@@ -359,6 +373,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   unsigned* s_ring32 = reinterpret_cast<unsigned*>(s_ring);
   unsigned short* s_ring16 = reinterpret_cast<unsigned short*>(s_ring);
   float* s_cs = s_ring + (LP ? RS / 2 : RS) * RST;
+  float* s_vr = s_cs + CRS * CST;   // variant 3: 16-row ring of vertical-pass outputs
 
   const int tid = threadIdx.x;
   const int sx = bid % a.nsx, sy = bid / a.nsx;
@@ -420,6 +435,14 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // owns valid storage; 32-bit element offsets from the (uniform) base
   const int Wp = a.nsx * TW;
   const unsigned acc_lane = (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
+  // variant 3: running sums of one (column, channel) per lane of the first
+  // 16*NC lanes; sparse-difference weights (-1)^k C(n,k), offsets k(2r+1)
+  const int vb_x = tid & 15, vb_ch = tid >> 4;
+  const bool vb_on = VB && vb_ch < NC;
+  const int vn = VB ? a.vbox : 1;
+  const int vw = VB ? 2 * (R / vn) + 1 : 1;
+  const double vc1 = -vn, vc2 = vn == 2 ? 1.0 : 3.0, vc3 = -1.0;
+  double vI1 = 0.0, vI2 = 0.0, vI3 = 0.0;
 
   // Modulation slots: pixel tid + i*NT of the B x MW step tile.  With R fixed
   // the passes read only the TW + 2R window columns; the runtime-R loops also
@@ -572,16 +595,52 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     __syncthreads();
 
     // ---- 3. vertical pass, demodulation, accumulation -------------------------------
+    if constexpr (VB) {
+      // input row i = s*B + j of the term (strip row i - R) completes the box
+      // sum of output row i - 2R; rows before the term's first (i < k w) are
+      // the previous term's and read as zero
+      if (vb_on) {
+        if (s == 0) vI1 = vI2 = vI3 = 0.0;
+        const float* col = s_ring + vb_ch * TW + vb_x;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const int i = s * B + j;
+          const int sl = wrap(rslot + j, RS);
+          double v = (double)col[sl * RST];
+          const double ck[3] = {vc1, vc2, vc3};
+#pragma unroll
+          for (int k = 1; k <= 3; ++k) {
+            if (k <= vn && i >= k * vw) {
+              int sk = sl - k * vw;
+              if (sk < 0) sk += RS;
+              v = fma(ck[k - 1], (double)col[sk * RST], v);
+            }
+          }
+          vI1 += v;
+          vI2 += vI1;
+          vI3 += vI2;
+          const int o = i - 2 * R;
+          if (o >= 0 && o < a.TH)
+            s_vr[(o & 15) * RST + vb_ch * TW + vb_x] = (float)(vn == 1 ? vI1 : vn == 2 ? vI2 : vI3);
+        }
+      }
+      __syncthreads();
+    }
     if (s >= lag) {
-      const int ob = s - lag;
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      const int rb = rslot_lag + p2_g * 4;
-      (void)ob;
-      if constexpr (LP)
-        vpass_lp<PREC, RC, RST>(s_ring32 + p2_ch * TW + p2_x, rb >> 1, RS / 2, tpe, tpo, s_te, s_to,
-                                R, acc);
-      else
-        vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rb, RS, tapr, s_taps, ntap4, acc);
+      if constexpr (VB) {
+        // output rows (s - lag)*B .. +7 of the strip: the first lag*B - 2R of
+        // them were completed in the previous step, the others in this one
+        const int ob = (s - lag) * B + p2_g * 4;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[p] = s_vr[((ob + p) & 15) * RST + p2_ch * TW + p2_x];
+      } else if constexpr (LP) {
+        vpass_lp<PREC, RC, RST>(s_ring32 + p2_ch * TW + p2_x, (rslot_lag + p2_g * 4) >> 1, RS / 2,
+                                tpe, tpo, s_te, s_to, R, acc);
+      } else {
+        vpass<RC, RST>(s_ring + p2_ch * TW + p2_x, rslot_lag + p2_g * 4, RS, tapr, s_taps, ntap4,
+                       acc);
+      }
       const int cb = cslot_lag + p2_g * 4 + R;
       float q[4];
 #pragma unroll
@@ -601,7 +660,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         swap_rows16(e1, e3);
         const float v0 = __builtin_bit_cast(float, e0) + __builtin_bit_cast(float, e2);
         const float v1 = __builtin_bit_cast(float, e1) + __builtin_bit_cast(float, e3);
-        const unsigned o = acc_lane + (unsigned)(ob * B + p2_g * 4) * Wp;
+        const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
         buf_store1(acc_rsrc, 4u * o, fmaf(tw, v0, t > 0 ? acur[0] : 0.0f));
         buf_store1(acc_rsrc, 4u * (o + Wp), fmaf(tw, v1, t > 0 ? acur[1] : 0.0f));
       }

@@ -134,14 +134,17 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
+  if (o->spatial < BF_SPATIAL_GAUSS || o->spatial > BF_SPATIAL_BOX3)
+    return fail(BF_EINVAL, "opts.spatial must be a BF_SPATIAL_* value");
   if (o->num_out || o->z_out || o->time_kernel)
     return fail(BF_EINVAL, "plans take no num_out, z_out or time_kernel");
   double Wm[64];
   if ((rc = whiten(d, C, Wm))) return rc;
-  const int R = window_radius(sigma_s);
+  const int R = window_radius(sigma_s, o->spatial);
+  const int variant = kernel_variant(o->precision, o->spatial);
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;
   int TH = 0;
-  if ((rc = choose_strip_height(d, R, o->precision, H, W, o->tile_h, &TH))) return rc;
+  if ((rc = choose_strip_height(d, R, variant, H, W, o->tile_h, &TH))) return rc;
 
   // the terms, exactly as bf_vec_ex draws them
   const int N = o->N;
@@ -156,16 +159,16 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   }
   size_t off_w = 0, off_taps = 0;
   const std::vector<float> tab = term_table(d, Kr, w.data(), o->dedup ? weight.data() : nullptr,
-                                            sigma_s, &off_w, &off_taps);
+                                            sigma_s, &off_w, &off_taps, o->spatial);
 
   bf_plan* p = new bf_plan;
   p->H = H;
   p->W = W;
   p->d = d;
-  p->prec = o->precision;
+  p->prec = variant;
   p->center = o->center;
   FusedArgs& a = p->a;
-  fused_geometry(a, H, W, R, o->precision, TH);
+  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? o->spatial : 0);
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = Kr;

@@ -49,12 +49,15 @@ constexpr int kMMFloats = 17;  // min/max partial block: 8 minima, 8 maxima, fla
 
 // Modelled device cost of one term of a planned request, in microseconds:
 // executed flops of all its workgroup steps (modulation of the haloed rows,
-// both passes; the 16-bit passes do two taps per instruction) at a nominal
+// both passes; the 16-bit passes do two taps per instruction, the running-sum
+// vertical pass of variant 3 about eight operations per output) at a nominal
 // rate.  Only ratios between requests matter for the chunking.
 double model_term_us(const FusedArgs& a, int d, int prec) {
   const double NC = 2.0 * (d + 1), taps = 2.0 * a.R + 1.0;
   const double mod = (double)kB * (kTW + 2 * a.R) * (4.0 * d + 2.0);
-  const double pass = 2.0 * kB * NC * kTW * taps * 2.0 * (prec == BF_FP32 ? 1.0 : 0.5);
+  const double one = (double)kB * NC * kTW * taps * 2.0;   // one FIR pass, FP32
+  const double pass = prec == 3 ? one + (double)kB * NC * kTW * 8.0
+                                : 2.0 * one * (prec == BF_FP32 ? 1.0 : 0.5);
   const double per_step = mod + pass;
   const double flops = per_step * a.steps * (double)a.nsx * a.nsy;
   return flops / 50e12 * 1e6;
@@ -65,7 +68,8 @@ struct Req {
   bf_request in{};
   double Cm[64] = {0};
   double Wm[64] = {0};
-  int R = 0, variant = 0, stream = 0;
+  int R = 0, variant = 0, stream = 0;   // variant: instance id (d, R, kvar) of the server
+  int kvar = 0;                         // kernel variant (precision, running-sum box pass)
   FusedArgs a{};
   size_t n_acc = 0, n_tab = 0, off_w = 0, off_taps = 0;
   int nparts = 0;
@@ -103,7 +107,7 @@ struct Server {
   std::condition_variable cv_work, cv_done;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   std::deque<Req*> incoming;
-  std::map<std::tuple<int, int, int>, int> variants;  // (d, R, precision) -> id
+  std::map<std::tuple<int, int, int>, int> variants;  // (d, R, kernel variant) -> id
   uint64_t next_ticket = 1;
   bool stop = false;
   int queued = 0, admitted = 0;
@@ -186,7 +190,7 @@ struct Server {
     const int K = r->in.dedup ? (int)weight.size() : r->in.K;
     size_t off_w = 0, off_taps = 0;
     const std::vector<float> tab = term_table(d, K, w.data(), r->in.dedup ? weight.data() : nullptr,
-                                              r->in.sigma_s, &off_w, &off_taps);
+                                              r->in.sigma_s, &off_w, &off_taps, r->in.spatial);
     float* ptab = r->pin + 32;
     std::memcpy(ptab, tab.data(), tab.size() * sizeof(float));
     float* dtab = reinterpret_cast<float*>(dev_base + r->dev_off) + r->n_acc;
@@ -319,7 +323,7 @@ struct Server {
         b.first[k + 1] = b.first[k] + r->a.nsx * r->a.nsy;
       }
       hipStream_t st = streams[r0->stream];
-      hipError_t e = launch_fused_batch(r0->in.d, r0->R, r0->in.precision, b, st);
+      hipError_t e = launch_fused_batch(r0->in.d, r0->R, r0->kvar, b, st);
       if (e != hipSuccess) {
         set_fatal(e, "batched fused launch");
         return true;
@@ -540,6 +544,8 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
   if (in.center != 0 && in.center != 1) return fail(BF_EINVAL, "center must be 0 or 1");
   if (in.dedup != 0 && in.dedup != 1) return fail(BF_EINVAL, "dedup must be 0 or 1");
+  if (in.spatial < BF_SPATIAL_GAUSS || in.spatial > BF_SPATIAL_BOX3)
+    return fail(BF_EINVAL, "spatial must be a BF_SPATIAL_* value");
   if (!in.C) return fail(BF_EINVAL, "C must be non-null");
   if (!std::isfinite(in.arrival)) return fail(BF_EINVAL, "arrival must be finite");
   {
@@ -553,7 +559,8 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   in.C = r->Cm;
   int rc = whiten(in.d, r->Cm, r->Wm);
   if (rc) return rc;
-  r->R = window_radius(in.sigma_s);
+  r->R = window_radius(in.sigma_s, in.spatial);
+  r->kvar = kernel_variant(in.precision, in.spatial);
   if ((rc = check_fused_size(in.H, in.W, in.pitch, in.d, r->R))) return rc;
   int TH = 0;
   {
@@ -562,11 +569,11 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != s->device) e = hipSetDevice(s->device);
     if (e != hipSuccess) return hip_err(e, "hipSetDevice");
-    rc = choose_strip_height(in.d, r->R, in.precision, in.H, in.W, 0, &TH);
+    rc = choose_strip_height(in.d, r->R, r->kvar, in.H, in.W, 0, &TH);
     if (cur != s->device) (void)hipSetDevice(cur);
     if (rc) return rc;
   }
-  fused_geometry(r->a, in.H, in.W, r->R, in.precision, TH);
+  fused_geometry(r->a, in.H, in.W, r->R, r->kvar, TH, r->kvar == 3 ? in.spatial : 0);
   r->a.f = in.f;
   r->a.fpitch = in.pitch;
   r->n_acc = fused_acc_floats(r->a, in.d);
@@ -578,7 +585,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   r->dev_bytes = Arena::round_up((r->n_acc + r->n_tab) * sizeof(float), kAlign) +
                  Arena::round_up(n_part * sizeof(float), kAlign);
   r->pin_bytes = (32 + r->n_tab) * sizeof(float);
-  r->cost_term = model_term_us(r->a, in.d, in.precision);
+  r->cost_term = model_term_us(r->a, in.d, r->kvar);
   if (!s->dev_arena.fits_ever(r->dev_bytes))
     return fail(BF_ENOMEM, "request footprint exceeds the server's device arena");
   if (!s->pin_arena.fits_ever(r->pin_bytes))
@@ -672,7 +679,7 @@ int bf_server_submit(bf_server* s, const bf_request* q, uint64_t* ticket) {
   if (s->fatal) return fail(s->fatal, s->fatal_msg);
   if (s->cfg.max_queued > 0 && s->queued >= s->cfg.max_queued)
     return fail(BF_EBUSY, "serving queue full");
-  const auto key = std::make_tuple(r->in.d, r->R, r->in.precision);
+  const auto key = std::make_tuple(r->in.d, r->R, r->kvar);
   auto it = s->variants.find(key);
   if (it == s->variants.end()) it = s->variants.emplace(key, (int)s->variants.size()).first;
   r->variant = it->second;
