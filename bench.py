@@ -314,6 +314,47 @@ def study_table1(P, torch, log_fn):
             "sigma_r": 40, "N": 10, "K": 300, "rows": rows}
 
 
+def _radius(sigma_s, n):
+    """Window radius for reporting: ceil(3 sigma_s) for the Gaussian, n r for
+    n boxes with r nearest the root of n((2r+1)^2 - 1)/12 = sigma_s^2."""
+    if n == 0:
+        return int(math.ceil(3 * sigma_s))
+    return n * int(math.floor((math.sqrt(12 * sigma_s ** 2 / n + 1) - 1) / 2 + 0.5))
+
+
+def study_spatial(P, torch, log_fn):
+    """Kernel time against sigma_s for the Gaussian and the three-box spatial
+    filter (the paper's O(1)-in-sigma_s remark): 2048^2 x 3 Voronoi image,
+    K = 64, N = 37, C = 0.08^2 I.  FP32: Gaussian and three boxes with FIR
+    passes, and three boxes with the running-sum vertical pass
+    ("box3+runsum"); FP16 storage: FIR passes.  Times are HIP events around
+    the fused kernel (median of 5)."""
+    import numpy as np
+    from synth import voronoi_image
+    f = torch.from_numpy(voronoi_image(2048, 2048, 3, 128, 0.0, 1.0, 0.02, seed=7101)).cuda()
+    C = 0.08 ** 2 * np.eye(3)
+    out = torch.empty_like(f)
+    rows = []
+    for s_ in (1.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0):
+        rec = {"sigma_s": s_}
+        for prec, sp in (("fp32", "gauss"), ("fp32", "box3"), ("fp32", "box3+runsum"),
+                         ("fp16", "gauss"), ("fp16", "box3")):
+            if True:
+                ms = []
+                for _ in range(6):
+                    _, o = P.bf_vec_ex(f, s_, C, 64, 11, out=out, N=37, precision=prec,
+                                       spatial=sp, time_kernel=True, return_opts=True)
+                    ms.append(o.kernel_ms)
+                rec[f"{sp}_{prec}_ms"] = float(np.median(ms[1:]))
+        rec["R_gauss"] = _radius(s_, 0)
+        rec["R_box3"] = _radius(s_, 3)
+        log_fn(f"spatial sigma_s={s_}: " + ", ".join(f"{k} {v:.3g}" for k, v in rec.items()
+                                                     if k != "sigma_s"))
+        rows.append(rec)
+    return {"study": "kernel_time_vs_sigma_s_spatial_filter", "image": "2048x2048x3 Voronoi",
+            "K": 64, "N": 37, "rows": rows}
+
+
 def study_mse(P, torch, log_fn, realizations):
     """MSE against the number of terms for N = 10 and N = 20 (the paper's
     error-plot setting on a synthetic stand-in for its 876x584 image):
@@ -430,7 +471,7 @@ def main():
                     help="run every drawn term (default: merge equal +-Y draws, exact)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving run (no headline modes, CPU baseline or comparator)")
-    ap.add_argument("--study", choices=["table1", "mse", "lab"],
+    ap.add_argument("--study", choices=["table1", "mse", "lab", "spatial"],
                     help="run one of the paper-study analogues instead of the benchmark and "
                          "print its JSON")
     ap.add_argument("--realizations", type=int, default=400)
@@ -451,6 +492,7 @@ def main():
     if args.study:
         rec = (study_table1(P, torch, log) if args.study == "table1"
                else study_lab(P, torch, log) if args.study == "lab"
+               else study_spatial(P, torch, log) if args.study == "spatial"
                else study_mse(P, torch, log, args.realizations))
         print(json.dumps(rec), flush=True)
         return
@@ -480,43 +522,48 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def step(prec, dst, dedup):
+    def step(prec, dst, dedup, spatial="gauss"):
         _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=dst, precision=prec,
-                           stream=stream, time_kernel=True, return_opts=True, dedup=dedup)
+                           stream=stream, time_kernel=True, return_opts=True, dedup=dedup,
+                           spatial=spatial)
         return o.N_used, o.kernel_ms, o.K_used, o.tile_h_used
 
     tuned = {}
 
     def run(mode, dst):
         prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
+        spatial = "box3" if mode.endswith("_box3") else "gauss"
         if not args.no_autotune and prec not in tuned:
             # one-off, untimed: measured strip height for this shape
             tuned[prec] = P.bf_autotune(fg, sigma_s, precision=prec, stream=stream)
             log(f"{prec}: autotuned strip height {tuned[prec][0]}")
         for _ in range(args.warmup):
-            step(prec, dst, dedup)
+            step(prec, dst, dedup, spatial)
         torch.cuda.synchronize()
         kms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            N, ms, K_used, tile_h = step(prec, dst, dedup)
+            N, ms, K_used, tile_h = step(prec, dst, dedup, spatial)
             kms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         kernel_ms = float(np.mean(kms))
-        # flops of the terms the kernel actually ran
+        # flops of the terms the kernel actually ran (Gaussian FIR passes; the
+        # three-box filter is a different filter and reports its rate only)
         flops_run = algorithmic_flops_per_pixel(d, R, K_used) * H * W
+        tf = None if spatial != "gauss" else flops_run / (kernel_ms * 1e-3) / 1e12
         rec = {"value": H * W * args.steps / dt / 1e6, "ms_per_step": 1e3 * dt / args.steps,
-               "kernel_ms": kernel_ms, "achieved_tflops": flops_run / (kernel_ms * 1e-3) / 1e12,
-               "N": N, "K_used": K_used, "tile_h": tile_h}
+               "kernel_ms": kernel_ms, "achieved_tflops": tf,
+               "N": N, "K_used": K_used, "tile_h": tile_h, "spatial": spatial}
         log(f"{mode}: N={N} K_used={K_used} step {rec['ms_per_step']:.2f} ms, kernel "
-            f"{kernel_ms:.2f} ms, {rec['achieved_tflops']:.2f} TFLOP/s algorithmic, "
-            f"{rec['value']:.2f} Mpix/s")
+            f"{kernel_ms:.2f} ms, " + ("" if tf is None else f"{tf:.2f} TFLOP/s algorithmic, ")
+            + f"{rec['value']:.2f} Mpix/s")
         return rec
 
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
-        [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + ["fp32_dedup", "fp16_dedup"]
+        [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + \
+        ["fp32_dedup", "fp16_dedup", "fp32_box3"]
     results, outs = {}, {}
     for prec in precs:
         outs[prec] = torch.empty_like(fg)
@@ -529,7 +576,7 @@ def main():
     if "fp32" in outs:
         span = (fg.reshape(-1, d).amax(0) - fg.reshape(-1, d).amin(0)).clamp_min(1e-30)
         for prec in results:
-            if prec != "fp32":
+            if prec != "fp32" and results[prec]["spatial"] == "gauss":
                 diff = (outs[prec] - outs["fp32"]).abs().reshape(-1, d) / span
                 results[prec]["max_dev_vs_fp32"] = float(diff.max())
                 results[prec]["mean_dev_vs_fp32"] = float(diff.mean())

@@ -62,10 +62,13 @@ enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2 };
  * as a box or a hat.  BF_SPATIAL_BOX / HAT / BOX3 are the 1-, 2- and 3-fold
  * convolutions of a box of 2r+1 ones per axis, with r the integer nearest the
  * root of n((2r+1)^2 - 1)/12 = sigma_s^2 (n boxes have variance sigma_s^2),
- * window radius R = n r.  With BF_FP32 their vertical pass is a running sum
- * (cost independent of sigma_s); with 16-bit storage both passes are FIR
- * passes over the same taps. */
-enum { BF_SPATIAL_GAUSS = 0, BF_SPATIAL_BOX = 1, BF_SPATIAL_HAT = 2, BF_SPATIAL_BOX3 = 3 };
+ * window radius R = n r.  Both passes run as FIR passes over these taps.
+ * BF_SPATIAL_RUNSUM (or-ed into a box value, BF_FP32 only) runs the vertical
+ * pass as exact running sums instead, whose cost does not depend on sigma_s
+ * (the paper's O(1) remark); on MI355X it is slower than the FIR pass for
+ * every supported window (R <= 40), so it is not the default. */
+enum { BF_SPATIAL_GAUSS = 0, BF_SPATIAL_BOX = 1, BF_SPATIAL_HAT = 2, BF_SPATIAL_BOX3 = 3,
+       BF_SPATIAL_RUNSUM = 16 };
 
 typedef struct bf_opts {
   int N;           /* raised-cosine order (eq. (approx)); 0 = automatic rule  */
@@ -88,7 +91,8 @@ typedef struct bf_opts {
                       the distinct +-Y.  0 (default): K terms as drawn          */
   int K_used;      /* OUT: terms the kernel ran (K, or the distinct +-Y count)  */
   int tile_h_used; /* OUT: strip height the fused kernel ran with              */
-  int spatial;     /* BF_SPATIAL_* (default BF_SPATIAL_GAUSS)                  */
+  int spatial;     /* BF_SPATIAL_* (default BF_SPATIAL_GAUSS), optionally
+                      | BF_SPATIAL_RUNSUM with a box filter and BF_FP32       */
   int reserved[1];
 } bf_opts;
 

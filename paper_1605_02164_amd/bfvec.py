@@ -23,12 +23,20 @@ REQ_STATES = {BF_REQ_QUEUED: "queued", BF_REQ_PREPARING: "preparing", BF_REQ_RUN
 BF_FP32, BF_FP16, BF_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
 BF_SPATIAL_GAUSS, BF_SPATIAL_BOX, BF_SPATIAL_HAT, BF_SPATIAL_BOX3 = 0, 1, 2, 3
+BF_SPATIAL_RUNSUM = 16
 SPATIAL = {"gauss": BF_SPATIAL_GAUSS, "box": BF_SPATIAL_BOX, "hat": BF_SPATIAL_HAT,
            "box3": BF_SPATIAL_BOX3}
 
 
 def _spatial(v):
-    return SPATIAL[v] if isinstance(v, str) else int(v)
+    """"gauss", "box", "hat", "box3", optionally with "+runsum" (the
+    running-sum vertical pass, FP32), or the integer value."""
+    if isinstance(v, str):
+        name, _, flag = v.partition("+")
+        if flag not in ("", "runsum"):
+            raise ValueError(f"unknown spatial flag {flag!r}")
+        return SPATIAL[name] | (BF_SPATIAL_RUNSUM if flag else 0)
+    return int(v)
 
 # Every symbol declared in include/bfvec.h.
 EXPORTS = [

@@ -150,12 +150,20 @@ int check_opts(const bf_opts* o) {
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
-  if (o->spatial < BF_SPATIAL_GAUSS || o->spatial > BF_SPATIAL_BOX3)
-    return fail(BF_EINVAL, "opts.spatial must be a BF_SPATIAL_* value");
-  return BF_OK;
+  return check_spatial(o->spatial, o->precision);
 }
 
 }  // namespace
+
+int check_spatial(int spatial, int precision) {
+  if ((spatial & ~(3 | BF_SPATIAL_RUNSUM)) != 0)
+    return fail(BF_EINVAL, "spatial must be a BF_SPATIAL_* value");
+  if (spatial_runsum(spatial) && spatial_boxes(spatial) == 0)
+    return fail(BF_EINVAL, "BF_SPATIAL_RUNSUM applies to the box filters only");
+  if (spatial_runsum(spatial) && precision != BF_FP32)
+    return fail(BF_EUNSUPPORTED, "BF_SPATIAL_RUNSUM needs BF_FP32");
+  return BF_OK;
+}
 
 int check_fused_size(int H, int W, int pitch, int d, int R) {
   if (R > kRMax) return fail(BF_EUNSUPPORTED, "sigma_s too large: window radius above 40");
@@ -259,7 +267,7 @@ namespace {
 
 // Checks that need no device work: window size, precision, strip height.
 int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
-  const int R = window_radius(sigma_s, o->spatial);
+  const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int rc = check_fused_size(H, W, W, d, R);
   if (rc) return rc;
   return choose_strip_height(d, R, kernel_variant(o->precision, o->spatial), H, W, o->tile_h, TH);
@@ -270,17 +278,17 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
               const double* weights, int K, float* out, bf_opts* o, const float* lo,
               const float* hi, int TH) {
   hipStream_t st = (hipStream_t)o->stream;
-  const int R = window_radius(sigma_s, o->spatial);
+  const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int variant = kernel_variant(o->precision, o->spatial);
   size_t off_w = 0, off_taps = 0;
   const std::vector<float> hbuf =
-      term_table(d, K, w, weights, sigma_s, &off_w, &off_taps, o->spatial);
+      term_table(d, K, w, weights, sigma_s, &off_w, &off_taps, spatial_boxes(o->spatial));
 
   FusedArgs a{};
   a.f = f;
   for (int m = 0; m < 8; ++m)
     a.cen[m] = (o->center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
-  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? o->spatial : 0);
+  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0);
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = K;

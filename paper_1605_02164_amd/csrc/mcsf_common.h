@@ -39,12 +39,18 @@ inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
 // of the n-fold box also reads the n rows before those (vbox = n).
 inline constexpr int ring_steps(int R, int vbox) { return (2 * R + vbox + 2 * kB - 1) / kB; }
 
+// Spatial option: the number n of boxes (0 = Gaussian) in the low bits, and
+// the flag (16) asking for the running-sum vertical pass.
+inline int spatial_boxes(int spatial) { return spatial & 3; }
+inline bool spatial_runsum(int spatial) { return (spatial & 16) != 0; }
 // Kernel variants: 0 FP32, 1 FP16 storage, 2 BF16 storage (FIR passes with
 // any spatial taps), 3 FP32 with the running-sum vertical pass of the n-fold
-// box filters (spatial = n).  16-bit storage runs box filters as FIR taps.
+// box filters (requested by the flag).
 inline int kernel_variant(int precision, int spatial) {
-  return precision == 0 && spatial > 0 ? 3 : precision;
+  return precision == 0 && spatial_runsum(spatial) && spatial_boxes(spatial) > 0 ? 3 : precision;
 }
+// BF_OK, or BF_EINVAL / BF_EUNSUPPORTED with the message set.
+int check_spatial(int spatial, int precision);
 
 struct FusedArgs {
   const float* f;        // input (device), row y at f + y*fpitch*d

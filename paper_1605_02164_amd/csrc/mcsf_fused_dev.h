@@ -45,10 +45,12 @@
 //   v(i) = sum_{k=0..n} (-1)^k C(n,k) u(i - k(2r+1))
 // of the horizontal-pass rows u, integrated n times (running sums).  The
 // running sums are FP64 registers of a lane per (column, channel), reset at
-// the top of each term's strip; n+1 ring reads and n+3 FP64 operations per
-// output replace 2R+1 FMAs.  The horizontal pass stays a FIR over the box
+// the top of each term's strip; n+1 ring reads and about 14 FP64 operations
+// per output replace 2R+1 FMAs.  The horizontal pass stays a FIR over the box
 // taps: inside a 16-column strip a running sum would still have to start 2R
-// columns to the left.
+// columns to the left.  (Measured on gfx950 this pass is slower than the FIR
+// vertical pass at every radius up to 40, so the library runs box filters as
+// FIR taps unless the running-sum pass is requested.)
 
 #include <hip/hip_runtime.h>
 
@@ -441,7 +443,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const bool vb_on = VB && vb_ch < NC;
   const int vn = VB ? a.vbox : 1;
   const int vw = VB ? 2 * (R / vn) + 1 : 1;
-  const double vc1 = -vn, vc2 = vn == 2 ? 1.0 : 3.0, vc3 = -1.0;
+  // weights of the lags (zero past n) and 0/1 weights picking running sum n
+  const double vc1 = -vn, vc2 = vn == 2 ? 1.0 : vn == 3 ? 3.0 : 0.0, vc3 = vn == 3 ? -1.0 : 0.0;
+  const double ve1 = vn == 1 ? 1.0 : 0.0, ve2 = vn == 2 ? 1.0 : 0.0, ve3 = vn == 3 ? 1.0 : 0.0;
   double vI1 = 0.0, vI2 = 0.0, vI3 = 0.0;
 
   // Modulation slots: pixel tid + i*NT of the B x MW step tile.  With R fixed
@@ -602,27 +606,46 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       if (vb_on) {
         if (s == 0) vI1 = vI2 = vI3 = 0.0;
         const float* col = s_ring + vb_ch * TW + vb_x;
+        // all ring reads of the step first (no branch between them): row i
+        // and rows i - k w, k <= n; a lag that is not part of the sum (k > n,
+        // or a row before the term's first) reads an in-ring slot and gets
+        // weight zero (ring values are finite)
+        const int o1 = vw, o2 = vn >= 2 ? 2 * vw : 0, o3 = vn >= 3 ? 3 * vw : 0;
+        float u[B][4];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-          const int i = s * B + j;
           const int sl = wrap(rslot + j, RS);
-          double v = (double)col[sl * RST];
-          const double ck[3] = {vc1, vc2, vc3};
-#pragma unroll
-          for (int k = 1; k <= 3; ++k) {
-            if (k <= vn && i >= k * vw) {
-              int sk = sl - k * vw;
-              if (sk < 0) sk += RS;
-              v = fma(ck[k - 1], (double)col[sk * RST], v);
-            }
-          }
-          vI1 += v;
-          vI2 += vI1;
-          vI3 += vI2;
-          const int o = i - 2 * R;
-          if (o >= 0 && o < a.TH)
-            s_vr[(o & 15) * RST + vb_ch * TW + vb_x] = (float)(vn == 1 ? vI1 : vn == 2 ? vI2 : vI3);
+          const int s1 = sl - o1, s2 = sl - o2, s3 = sl - o3;
+          u[j][0] = col[sl * RST];
+          u[j][1] = col[(s1 < 0 ? s1 + RS : s1) * RST];
+          u[j][2] = col[(s2 < 0 ? s2 + RS : s2) * RST];
+          u[j][3] = col[(s3 < 0 ? s3 + RS : s3) * RST];
         }
+        // rows before the term's first only occur in its first steps: one
+        // uniform test per step, then a loop without per-row conditions
+        auto rows = [&](auto head) {
+          constexpr bool HEAD = decltype(head)::value;
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            const int i = s * B + j;
+            const double c1 = !HEAD || i >= o1 ? vc1 : 0.0;
+            const double c2 = !HEAD || i >= o2 ? vc2 : 0.0;
+            const double c3 = !HEAD || i >= o3 ? vc3 : 0.0;
+            double v = (double)u[j][0];
+            v = fma(c1, (double)u[j][1], v);
+            v = fma(c2, (double)u[j][2], v);
+            v = fma(c3, (double)u[j][3], v);
+            vI1 += v;
+            vI2 += vI1;
+            vI3 += vI2;
+            // output row i - 2R; rows outside 0..TH-1 land in ring slots that
+            // are rewritten before the demodulation reads them
+            s_vr[((i - 2 * R) & 15) * RST + vb_ch * TW + vb_x] =
+                (float)fma(ve3, vI3, fma(ve2, vI2, ve1 * vI1));
+          }
+        };
+        if (s * B >= vn * vw) rows(std::false_type{});
+        else rows(std::true_type{});
       }
       __syncthreads();
     }

@@ -134,13 +134,12 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
-  if (o->spatial < BF_SPATIAL_GAUSS || o->spatial > BF_SPATIAL_BOX3)
-    return fail(BF_EINVAL, "opts.spatial must be a BF_SPATIAL_* value");
+  if (int rs = check_spatial(o->spatial, o->precision)) return rs;
   if (o->num_out || o->z_out || o->time_kernel)
     return fail(BF_EINVAL, "plans take no num_out, z_out or time_kernel");
   double Wm[64];
   if ((rc = whiten(d, C, Wm))) return rc;
-  const int R = window_radius(sigma_s, o->spatial);
+  const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int variant = kernel_variant(o->precision, o->spatial);
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;
   int TH = 0;
@@ -159,7 +158,8 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   }
   size_t off_w = 0, off_taps = 0;
   const std::vector<float> tab = term_table(d, Kr, w.data(), o->dedup ? weight.data() : nullptr,
-                                            sigma_s, &off_w, &off_taps, o->spatial);
+                                            sigma_s, &off_w, &off_taps,
+                                            spatial_boxes(o->spatial));
 
   bf_plan* p = new bf_plan;
   p->H = H;
@@ -168,7 +168,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   p->prec = variant;
   p->center = o->center;
   FusedArgs& a = p->a;
-  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? o->spatial : 0);
+  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0);
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = Kr;

@@ -190,7 +190,8 @@ struct Server {
     const int K = r->in.dedup ? (int)weight.size() : r->in.K;
     size_t off_w = 0, off_taps = 0;
     const std::vector<float> tab = term_table(d, K, w.data(), r->in.dedup ? weight.data() : nullptr,
-                                              r->in.sigma_s, &off_w, &off_taps, r->in.spatial);
+                                              r->in.sigma_s, &off_w, &off_taps,
+                                              spatial_boxes(r->in.spatial));
     float* ptab = r->pin + 32;
     std::memcpy(ptab, tab.data(), tab.size() * sizeof(float));
     float* dtab = reinterpret_cast<float*>(dev_base + r->dev_off) + r->n_acc;
@@ -544,8 +545,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
   if (in.center != 0 && in.center != 1) return fail(BF_EINVAL, "center must be 0 or 1");
   if (in.dedup != 0 && in.dedup != 1) return fail(BF_EINVAL, "dedup must be 0 or 1");
-  if (in.spatial < BF_SPATIAL_GAUSS || in.spatial > BF_SPATIAL_BOX3)
-    return fail(BF_EINVAL, "spatial must be a BF_SPATIAL_* value");
+  if (int rs = check_spatial(in.spatial, in.precision)) return rs;
   if (!in.C) return fail(BF_EINVAL, "C must be non-null");
   if (!std::isfinite(in.arrival)) return fail(BF_EINVAL, "arrival must be finite");
   {
@@ -559,7 +559,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   in.C = r->Cm;
   int rc = whiten(in.d, r->Cm, r->Wm);
   if (rc) return rc;
-  r->R = window_radius(in.sigma_s, in.spatial);
+  r->R = window_radius(in.sigma_s, spatial_boxes(in.spatial));
   r->kvar = kernel_variant(in.precision, in.spatial);
   if ((rc = check_fused_size(in.H, in.W, in.pitch, in.d, r->R))) return rc;
   int TH = 0;
@@ -573,7 +573,8 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     if (cur != s->device) (void)hipSetDevice(cur);
     if (rc) return rc;
   }
-  fused_geometry(r->a, in.H, in.W, r->R, r->kvar, TH, r->kvar == 3 ? in.spatial : 0);
+  fused_geometry(r->a, in.H, in.W, r->R, r->kvar, TH,
+                 r->kvar == 3 ? spatial_boxes(in.spatial) : 0);
   r->a.f = in.f;
   r->a.fpitch = in.pitch;
   r->n_acc = fused_acc_floats(r->a, in.d);

@@ -186,3 +186,22 @@ def test_plan_validation_before_device_work():
     assert L.bf_plan_create(16, 16, 3, 2.0, Cp, 4, 1, None, None) == B.BF_EINVAL
     assert L.bf_plan_execute(None, 0x1000, 0x100000, None) == B.BF_EINVAL
     assert L.bf_plan_destroy(None) == B.BF_OK
+
+
+def test_spatial_option_validation_before_device_work():
+    L = P.lib()
+    Ch = np.eye(3) * 0.01
+
+    def vec(spatial, precision="fp32"):
+        o = B.make_opts(precision=precision)
+        o.spatial = spatial
+        return L.bf_vec_ex(0x1000, 8, 8, 3, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                           0x100000, ctypes.byref(o))
+
+    assert vec(4) == B.BF_EINVAL                                   # not a filter
+    assert vec(B.BF_SPATIAL_RUNSUM) == B.BF_EINVAL                 # running sums need boxes
+    assert vec(B.BF_SPATIAL_BOX3 | B.BF_SPATIAL_RUNSUM, "fp16") == B.BF_EUNSUPPORTED
+    assert vec(B.BF_SPATIAL_HAT | 32) == B.BF_EINVAL
+    assert B._spatial("box3+runsum") == 3 | B.BF_SPATIAL_RUNSUM
+    with pytest.raises(ValueError):
+        B._spatial("box3+fast")

@@ -1,8 +1,9 @@
 """GPU parity of the box-family spatial filters (box, hat, three boxes) against
 the FP64 oracle, through the C ABI.
 
-FP32 runs the running-sum vertical pass (FP64 running sums over the
-horizontal-pass rows); 16-bit storage runs FIR passes over the box taps.
+By default both passes are FIR passes over the box taps; with "+runsum"
+(BF_SPATIAL_RUNSUM, FP32) the vertical pass is FP64 running sums over the
+horizontal-pass rows.  Both paths are checked.
 Tolerances as for the Gaussian: 1e-4 of each channel's range for FP32 where
 the normaliser is well conditioned (z >= 1e-2, see test_gpu_parity), 3e-3 for
 FP16 storage.  The full-size case runs the benchmark's launch configuration
@@ -58,13 +59,13 @@ SPATIAL = [("box", 1), ("hat", 2), ("box3", 3)]
 
 
 @pytest.mark.parametrize("name,n", SPATIAL)
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_box_family_full_image(name, n, precision):
-    say(f"case spatial={name} {precision} 96x80x3 sigma_s=2.5 K=24 N=16")
+@pytest.mark.parametrize("precision,flag", [("fp32", ""), ("fp32", "+runsum"), ("fp16", "")])
+def test_box_family_full_image(name, n, precision, flag):
+    say(f"case spatial={name}{flag} {precision} 96x80x3 sigma_s=2.5 K=24 N=16")
     f, C, p = workload("voronoi128_d3_s2_K64", H=96, W=80)
     K, N, seed, sigma = 24, 16, 7, 2.5
     got = host(P.bf_vec_ex(cuda(f), sigma, C, K, seed, N=N, precision=precision,
-                           spatial=name)[0])
+                           spatial=name + flag)[0])
     ref, z = oracle_full(f, sigma, C, K, seed, N, n)
     check(got, ref, f, z, TOL[precision])
 
@@ -86,20 +87,23 @@ EDGE = [
 @pytest.mark.parametrize("H,W,d,sigma,K,n", EDGE)
 def test_box_family_edge_shapes(H, W, d, sigma, K, n):
     say(f"case spatial edge H={H} W={W} d={d} sigma_s={sigma} K={K} n={n} "
-        f"R={O.window_radius(sigma, n)}")
+        f"R={O.window_radius(sigma, n)}, FIR and running-sum vertical passes")
     f = voronoi_image(H, W, d, 3, 0.0, 1.0, 0.02, 11 + H + W + d)
     C = np.eye(d) * 0.15 ** 2 if d % 2 else random_spd(d, -2.0, -1.0, d)
-    got = host(P.bf_vec_ex(cuda(f), sigma, C, K, 5, N=12, spatial=n)[0])
     ref, z = oracle_full(f, sigma, C, K, 5, 12, n)
-    check(got, ref, f, z, TOL["fp32"])
+    for sp in (n, n | B.BF_SPATIAL_RUNSUM):
+        got = host(P.bf_vec_ex(cuda(f), sigma, C, K, 5, N=12, spatial=sp)[0])
+        check(got, ref, f, z, TOL["fp32"])
 
 
-def test_box3_full_size_sampled():
-    say("case spatial=box3 voronoi4096_d3_s10_K256 full size (benchmark launch), sampled pixels")
+@pytest.mark.parametrize("spatial", ["box3", "box3+runsum"])
+def test_box3_full_size_sampled(spatial):
+    say(f"case spatial={spatial} voronoi4096_d3_s10_K256 full size (benchmark launch), "
+        "sampled pixels")
     f, C, p = workload("voronoi4096_d3_s10_K256")
     K, seed, sigma = p["K"], p["term_seed"], p["sigma_s"]
     fg = cuda(f)
-    got, o = P.bf_vec_ex(fg, sigma, C, K, seed, spatial="box3", return_opts=True)
+    got, o = P.bf_vec_ex(fg, sigma, C, K, seed, spatial=spatial, return_opts=True)
     got = host(got)
     say(f"  N={o.N_used} tile_h={o.tile_h_used}")
     f64 = f.astype(np.float64)
@@ -111,7 +115,8 @@ def test_box3_full_size_sampled():
     check(got[pix[:, 0], pix[:, 1]], ref, f, z, TOL["fp32"])
 
 
-@pytest.mark.parametrize("precision,name", [("fp32", "box3"), ("fp16", "hat")])
+@pytest.mark.parametrize("precision,name", [("fp32", "box3+runsum"), ("fp32", "box"),
+                                            ("fp16", "hat")])
 def test_box_family_plan_and_server_match_standalone(precision, name):
     say(f"case spatial={name} {precision}: plan and server bitwise equal to bf_vec_ex")
     H, W, d, sigma, K, N = 72, 90, 3, 3.0, 16, 14
