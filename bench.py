@@ -35,14 +35,14 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "4978d87ac0d8e06bab3bbd157c7fab40e73bae46a84933e4513cff42d5551e23",
-    "fp32": {"fetch_kib": 90256311, "write_kib": 67477107,
+    "sha256": "e67e98a97024a13e4ba26df88969ed4e32822ddd240fbc0a4034c8fda1b321f2",
+    "fp32": {"fetch_kib": 90370698, "write_kib": 67285233,
              # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
              "executed_flops": 142493114368 * 64},
-    "fp16": {"fetch_kib": 145170815, "write_kib": 70255194,
+    "fp16": {"fetch_kib": 144603758, "write_kib": 70556389,
              # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
              "executed_flops": (145995333632 + 5494587392) * 64},
-    "fetch_factor": 1048576 / 524308.8125,
+    "fetch_factor": 1048576 / 524306.75,
     "write_factor": 1048576 / 1048576.0,
 }
 
