@@ -99,8 +99,20 @@ def check_covariance(C):
     return C
 
 
-def whiten(C):
-    """Whitening W with W^T W = C^{-1}, following eq. (COB).
+WHITEN_EIG, WHITEN_CHOL, WHITEN_SYM = 0, 1, 2
+
+
+def whiten(C, mode=WHITEN_EIG):
+    """Whitening W with W^T W = C^{-1}.
+
+    mode = WHITEN_EIG (default) follows eq. (COB), below.  The other two are
+    the other standard square roots of C^{-1}: WHITEN_CHOL, W = L^{-1} with
+    C = L L^T (L lower triangular with positive diagonal); WHITEN_SYM,
+    W = C^{-1/2}, the symmetric positive definite root.  All three give the
+    same Gaussian kernel of eq. (kernel); at finite N the product of raised
+    cosines of eq. (approx) depends on the choice.
+
+    WHITEN_EIG, following eq. (COB):
 
     C^{-1} = Q diag(alpha^2) Q^T with Q orthogonal; row k of W is
     alpha_k q_k^T, so that (W x)_k = alpha_k y_k with y = Q^T x.
@@ -118,7 +130,20 @@ def whiten(C):
     off = C - np.diag(np.diag(C))
     if not np.any(off):
         return np.diag(1.0 / np.sqrt(np.diag(C)))
+    if mode == WHITEN_CHOL:
+        L = np.linalg.cholesky(C)
+        # W = L^{-1} by forward substitution (L W = I), column by column
+        W = np.zeros((d, d))
+        for j in range(d):
+            for i in range(j, d):
+                rhs = (1.0 if i == j else 0.0) - sum(L[i, k] * W[k, j] for k in range(j, i))
+                W[i, j] = rhs / L[i, i]
+        return W
     lam, V = np.linalg.eigh(C)          # ascending eigenvalues
+    if mode == WHITEN_SYM:
+        return (V / np.sqrt(lam)) @ V.T
+    if mode != WHITEN_EIG:
+        raise ValueError("unknown whitening mode")
     W = np.empty((d, d))
     for k in range(d):
         v = V[:, k].copy()

@@ -65,6 +65,41 @@ def test_whiten_diagonal():
     assert np.array_equal(O.whiten(np.eye(3) * 0.0064), np.eye(3) / 0.08)
 
 
+def test_whiten_modes_closed_form_2x2():
+    # C = [[4, 2], [2, 5]] = L L^T with L = [[2, 0], [1, 2]]
+    C = np.array([[4.0, 2.0], [2.0, 5.0]])
+    W = O.whiten(C, O.WHITEN_CHOL)
+    assert np.allclose(W, [[0.5, 0.0], [-0.25, 0.5]], rtol=0, atol=1e-15)
+    # C^{1/2} = (C + sqrt(det C) I) / sqrt(tr C + 2 sqrt(det C)) = [[8, 2], [2, 9]] / sqrt(17)
+    W = O.whiten(C, O.WHITEN_SYM)
+    expect = math.sqrt(17.0) / 68.0 * np.array([[9.0, -2.0], [-2.0, 8.0]])
+    assert np.allclose(W, expect, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("d,seed", [(2, 5), (3, 6), (6, 7), (8, 8)])
+def test_whiten_modes_invariants(d, seed):
+    C = random_spd(d, -3, -1, seed)
+    Ci = np.linalg.inv(C)
+    Wc = O.whiten(C, O.WHITEN_CHOL)
+    Ws = O.whiten(C, O.WHITEN_SYM)
+    for W in (Wc, Ws):
+        assert np.max(np.abs(W.T @ W - Ci)) <= 1e-11 * np.max(np.abs(Ci))
+    # Cholesky: lower triangular with a positive diagonal, and W^{-1} W^{-T} = C
+    assert np.array_equal(Wc, np.tril(Wc)) and np.all(np.diag(Wc) > 0)
+    Li = np.linalg.inv(Wc)
+    assert np.max(np.abs(Li @ Li.T - C)) <= 1e-11 * np.max(np.abs(C))
+    # symmetric root: symmetric, positive definite, squares to C^{-1}
+    assert np.max(np.abs(Ws - Ws.T)) <= 1e-12 * np.max(np.abs(Ws))
+    assert np.min(np.linalg.eigvalsh(Ws)) > 0
+    assert np.max(np.abs(Ws @ Ws - Ci)) <= 1e-11 * np.max(np.abs(Ci))
+
+
+def test_whiten_modes_agree_on_diagonal_covariance():
+    C = np.diag([0.01, 4.0, 0.25])
+    for mode in (O.WHITEN_EIG, O.WHITEN_CHOL, O.WHITEN_SYM):
+        assert np.array_equal(O.whiten(C, mode), np.diag([10.0, 0.5, 2.0]))
+
+
 def test_whiten_rejects_bad_covariance():
     with pytest.raises(ValueError):
         O.whiten(np.array([[1.0, 0.5], [0.4, 1.0]]))
