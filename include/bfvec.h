@@ -57,6 +57,14 @@ enum {
  * intermediates.  Accumulation of both passes and of num/Z is FP32 always. */
 enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2 };
 
+/* Whitening W with W^T W = C^{-1} (eq. (COB) fixes W only up to that): the
+ * eigen-decomposition of eq. (COB) (default, see bf_whiten), W = L^{-1} with
+ * C = L L^T (Cholesky), or the symmetric root W = C^{-1/2}.  The three give
+ * the same Gaussian range kernel; at finite N the product of raised cosines
+ * of eq. (approx) is not rotation invariant, so the filters differ slightly.
+ * All three coincide for diagonal C. */
+enum { BF_WHITEN_EIG = 0, BF_WHITEN_CHOL = 1, BF_WHITEN_SYM = 2 };
+
 /* Spatial filter omega (separable, unnormalised).  The paper's eq. (kernel)
  * Gaussian by default; Section 3 allows any spatial filter in its place, such
  * as a box or a hat.  BF_SPATIAL_BOX / HAT / BOX3 are the 1-, 2- and 3-fold
@@ -93,7 +101,7 @@ typedef struct bf_opts {
   int tile_h_used; /* OUT: strip height the fused kernel ran with              */
   int spatial;     /* BF_SPATIAL_* (default BF_SPATIAL_GAUSS), optionally
                       | BF_SPATIAL_RUNSUM with a box filter and BF_FP32       */
-  int reserved[1];
+  int whiten;      /* BF_WHITEN_* (default BF_WHITEN_EIG)                      */
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,
@@ -131,6 +139,11 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s,
  * 1e-6 of its largest magnitude is positive.  BF_ENOTSPD if C is not
  * symmetric (to 1e-12 relative) or not positive definite. */
 int bf_whiten(int d, const double* C, double* W);
+
+/* The same for any BF_WHITEN_* mode: BF_WHITEN_CHOL gives the lower-triangular
+ * L^{-1} (C = L L^T), BF_WHITEN_SYM the symmetric C^{-1/2}.  Errors as
+ * bf_whiten, and BF_EINVAL for an unknown mode.  Host only. */
+int bf_whiten_mode(int d, const double* C, int mode, double* W);
 
 /* Monte Carlo draws of Proposition 2, host only.  X[t][m] ~ B(N, 1/2) is the
  * number of set bits among the first N bits of the Philox4x32-10 stream with
@@ -262,7 +275,8 @@ typedef struct bf_request {
                            from it; a request is not admitted before it.          */
   int dedup;            /* as bf_opts.dedup: merge equal +-Y draws (exact)        */
   int spatial;          /* as bf_opts.spatial: BF_SPATIAL_*                        */
-  int reserved[2];
+  int whiten;           /* as bf_opts.whiten: BF_WHITEN_*                          */
+  int reserved[1];
 } bf_request;
 
 enum {

@@ -24,6 +24,12 @@ BF_FP32, BF_FP16, BF_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
 BF_SPATIAL_GAUSS, BF_SPATIAL_BOX, BF_SPATIAL_HAT, BF_SPATIAL_BOX3 = 0, 1, 2, 3
 BF_SPATIAL_RUNSUM = 16
+BF_WHITEN_EIG, BF_WHITEN_CHOL, BF_WHITEN_SYM = 0, 1, 2
+WHITEN = {"eig": BF_WHITEN_EIG, "chol": BF_WHITEN_CHOL, "sym": BF_WHITEN_SYM}
+
+
+def _whiten_mode(v):
+    return WHITEN[v] if isinstance(v, str) else int(v)
 SPATIAL = {"gauss": BF_SPATIAL_GAUSS, "box": BF_SPATIAL_BOX, "hat": BF_SPATIAL_HAT,
            "box3": BF_SPATIAL_BOX3}
 
@@ -40,7 +46,7 @@ def _spatial(v):
 
 # Every symbol declared in include/bfvec.h.
 EXPORTS = [
-    "bf_opts_init", "bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten",
+    "bf_opts_init", "bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_whiten_mode",
     "bf_sample_terms", "bf_choose_N", "bf_minmax", "bf_direct", "bf_autotune",
     "bf_last_error", "bf_version",
     "bf_server_config_init", "bf_request_init", "bf_server_create", "bf_server_submit",
@@ -74,7 +80,7 @@ class bf_opts(ctypes.Structure):
         ("K_used", ctypes.c_int),
         ("tile_h_used", ctypes.c_int),
         ("spatial", ctypes.c_int),
-        ("reserved", ctypes.c_int * 1),
+        ("whiten", ctypes.c_int),
     ]
 
 
@@ -108,7 +114,8 @@ class bf_request(ctypes.Structure):
         ("arrival", ctypes.c_double),
         ("dedup", ctypes.c_int),
         ("spatial", ctypes.c_int),
-        ("reserved", ctypes.c_int * 2),
+        ("whiten", ctypes.c_int),
+        ("reserved", ctypes.c_int * 1),
     ]
 
 
@@ -161,6 +168,7 @@ def lib():
     L.bf_vec_ex.argtypes = [P, I, I, I, D, P, I, U64, P, ctypes.POINTER(bf_opts)]
     L.bf_vec_terms.argtypes = [P, I, I, I, D, P, P, I, P, ctypes.POINTER(bf_opts)]
     L.bf_whiten.argtypes = [I, P, P]
+    L.bf_whiten_mode.argtypes = [I, P, I, P]
     L.bf_sample_terms.argtypes = [I, P, I, I, U64, P, P]
     L.bf_choose_N.argtypes = [I, P, P, P, ctypes.POINTER(I)]
     L.bf_minmax.argtypes = [P, I, I, I, P, P, P]
@@ -186,7 +194,8 @@ def lib():
     L.bf_plan_create.argtypes = [I, I, I, D, P, I, U64, ctypes.POINTER(bf_opts), ctypes.POINTER(P)]
     L.bf_plan_execute.argtypes = [P, P, P, P]
     L.bf_plan_destroy.argtypes = [P]
-    for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_sample_terms",
+    for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_whiten_mode",
+                 "bf_sample_terms",
                  "bf_choose_N", "bf_minmax", "bf_direct", "bf_autotune", "bf_version",
                  "bf_server_create",
                  "bf_server_submit", "bf_server_poll", "bf_server_wait", "bf_server_drain",
@@ -226,7 +235,8 @@ def _check_image(f, out):
 
 
 def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
-              num_out=None, z_out=None, time_kernel=False, dedup=False, spatial="gauss"):
+              num_out=None, z_out=None, time_kernel=False, dedup=False, spatial="gauss",
+              whiten="eig"):
     o = bf_opts()
     lib().bf_opts_init(ctypes.byref(o))
     o.N = int(N)
@@ -239,6 +249,7 @@ def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
     o.time_kernel = 1 if time_kernel else 0
     o.dedup = 1 if dedup else 0
     o.spatial = _spatial(spatial)
+    o.whiten = _whiten_mode(whiten)
     return o
 
 
@@ -261,17 +272,18 @@ def bf_vec(f, sigma_s, C, K, seed, out=None):
 
 def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
               tile_h=0, stream=None, num_out=None, z_out=None, time_kernel=False,
-              return_opts=False, dedup=False, spatial="gauss"):
+              return_opts=False, dedup=False, spatial="gauss", whiten="eig"):
     """The filter with options, queued on ``stream`` (torch stream; default:
     current stream).  Returns (out, N_used), or (out, opts) with
     ``return_opts`` (opts.kernel_ms holds the fused-kernel time when
     ``time_kernel`` is set; opts.K_used the number of kernel terms, fewer than
-    K with ``dedup``).  ``spatial``: "gauss" (default), "box", "hat", "box3"."""
+    K with ``dedup``).  ``spatial``: "gauss" (default), "box", "hat", "box3";
+    ``whiten``: "eig" (default), "chol", "sym"."""
     out = _check_image(f, out)
     H, W, d = f.shape
     Ch = _host_f64(C, (d, d))
     o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  time_kernel, dedup, spatial)
+                  time_kernel, dedup, spatial, whiten)
     _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
     return (out, o) if return_opts else (out, o.N_used)
@@ -296,12 +308,13 @@ def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center
     return out
 
 
-def bf_whiten(C):
-    """Host whitening: W with W^T W = C^{-1}."""
+def bf_whiten(C, mode="eig"):
+    """Host whitening: W with W^T W = C^{-1} ("eig" of eq. (COB), "chol",
+    "sym")."""
     Ch = _host_f64(C)
     d = Ch.shape[0]
     W = np.empty((d, d))
-    _check(lib().bf_whiten(d, _ptr(Ch), _ptr(W)))
+    _check(lib().bf_whiten_mode(d, _ptr(Ch), _whiten_mode(mode), _ptr(W)))
     return W
 
 
@@ -366,9 +379,10 @@ class Plan:
     HIP graph launch per image.  ``N`` must be explicit."""
 
     def __init__(self, H, W, d, sigma_s, C, K, seed, N, precision="fp32", center=True,
-                 tile_h=0, dedup=False, spatial="gauss"):
+                 tile_h=0, dedup=False, spatial="gauss", whiten="eig"):
         Ch = _host_f64(C, (d, d))
-        o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup, spatial)
+        o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup, spatial,
+                      whiten)
         h = ctypes.c_void_p()
         _check(lib().bf_plan_create(int(H), int(W), int(d), float(sigma_s), _ptr(Ch), int(K),
                                     int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(o),
@@ -452,7 +466,7 @@ class Server:
         self._refs = {}
 
     def submit(self, f, sigma_s, C, K, seed, out=None, N=0, precision="fp16", center=True,
-               arrival=0.0, dedup=False, spatial="gauss"):
+               arrival=0.0, dedup=False, spatial="gauss", whiten="eig"):
         """Queue the filter of ``f`` (see bf_vec_ex for the arguments);
         ``arrival`` is the server-clock time the request arrives (0: now).
         Returns (ticket, out)."""
@@ -477,6 +491,7 @@ class Server:
         r.arrival = float(arrival)
         r.dedup = 1 if dedup else 0
         r.spatial = _spatial(spatial)
+        r.whiten = _whiten_mode(whiten)
         t = ctypes.c_uint64()
         _check(lib().bf_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         self._refs[t.value] = (f, out)

@@ -150,6 +150,8 @@ int check_opts(const bf_opts* o) {
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
+  if (o->whiten < BF_WHITEN_EIG || o->whiten > BF_WHITEN_SYM)
+    return fail(BF_EINVAL, "opts.whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
   return check_spatial(o->spatial, o->precision);
 }
 
@@ -419,7 +421,7 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   if (!C) return fail(BF_EINVAL, "C must be non-null");
   if ((rc = check_opts(o))) return rc;
   double Wm[64];
-  if ((rc = whiten(d, C, Wm))) return rc;
+  if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
   int TH = 0;
   if ((rc = plan_fused(H, W, d, sigma_s, o, &TH))) return rc;
   float lo[8] = {0}, hi[8] = {0};

@@ -110,8 +110,10 @@ void jacobi_eigen(int n, double* A, double* V) {
 
 }  // namespace
 
-int whiten(int d, const double* C, double* W) {
+int whiten(int d, const double* C, double* W, int mode) {
   if (d < 1 || d > 8) return fail(BF_EINVAL, "d must be in [1, 8]");
+  if (mode != BF_WHITEN_EIG && mode != BF_WHITEN_CHOL && mode != BF_WHITEN_SYM)
+    return fail(BF_EINVAL, "whitening mode must be BF_WHITEN_EIG, _CHOL or _SYM");
   if (!C || !W) return fail(BF_EINVAL, "C and W must be non-null");
   double scale = 0.0;
   for (int i = 0; i < d * d; ++i) {
@@ -137,7 +139,42 @@ int whiten(int d, const double* C, double* W) {
   double A[64], V[64];
   for (int i = 0; i < d; ++i)
     for (int j = 0; j < d; ++j) A[i * d + j] = 0.5 * (C[i * d + j] + C[j * d + i]);
+  if (mode == BF_WHITEN_CHOL) {
+    // C = L L^T (Cholesky-Banachiewicz), then W = L^{-1} by forward substitution
+    double L[64] = {0};
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double s = A[i * d + j];
+        for (int k = 0; k < j; ++k) s -= L[i * d + k] * L[j * d + k];
+        if (i == j) {
+          if (!(s > 0.0)) return fail(BF_ENOTSPD, "C is not positive definite");
+          L[i * d + i] = std::sqrt(s);
+        } else {
+          L[i * d + j] = s / L[j * d + j];
+        }
+      }
+    for (int i = 0; i < d * d; ++i) W[i] = 0.0;
+    for (int j = 0; j < d; ++j)
+      for (int i = j; i < d; ++i) {
+        double s = i == j ? 1.0 : 0.0;
+        for (int k = j; k < i; ++k) s -= L[i * d + k] * W[k * d + j];
+        W[i * d + j] = s / L[i * d + i];
+      }
+    return BF_OK;
+  }
   jacobi_eigen(d, A, V);
+  if (mode == BF_WHITEN_SYM) {
+    // W = V diag(lambda^{-1/2}) V^T
+    for (int k = 0; k < d; ++k)
+      if (!(A[k * d + k] > 0.0)) return fail(BF_ENOTSPD, "C is not positive definite");
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) s += V[i * d + k] * V[j * d + k] / std::sqrt(A[k * d + k]);
+        W[i * d + j] = s;
+      }
+    return BF_OK;
+  }
   int order[8];
   for (int k = 0; k < d; ++k) order[k] = k;
   std::stable_sort(order, order + d,
@@ -255,6 +292,11 @@ int bf_version(void) { return 10000; }
 int bf_whiten(int d, const double* C, double* W) {
   bfvec::clear_error();
   return bfvec::whiten(d, C, W);
+}
+
+int bf_whiten_mode(int d, const double* C, int mode, double* W) {
+  bfvec::clear_error();
+  return bfvec::whiten(d, C, W, mode);
 }
 
 int bf_sample_terms(int d, const double* C, int N, int K, uint64_t seed, int32_t* Y,

@@ -30,7 +30,8 @@ int box_radius(double sigma_s, int n);
 std::vector<double> spatial_taps(double sigma_s, int spatial = 0);
 
 // Whitening per eq. (COB); see bf_whiten in bfvec.h.  Returns a status.
-int whiten(int d, const double* C, double* W);
+// mode: BF_WHITEN_EIG (eq. (COB)), BF_WHITEN_CHOL, BF_WHITEN_SYM.
+int whiten(int d, const double* C, double* W, int mode = 0);
 
 // Philox4x32-10 block function (Salmon et al., SC'11).
 void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

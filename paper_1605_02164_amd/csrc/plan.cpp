@@ -135,10 +135,12 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
   if (int rs = check_spatial(o->spatial, o->precision)) return rs;
+  if (o->whiten < BF_WHITEN_EIG || o->whiten > BF_WHITEN_SYM)
+    return fail(BF_EINVAL, "opts.whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
   if (o->num_out || o->z_out || o->time_kernel)
     return fail(BF_EINVAL, "plans take no num_out, z_out or time_kernel");
   double Wm[64];
-  if ((rc = whiten(d, C, Wm))) return rc;
+  if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int variant = kernel_variant(o->precision, o->spatial);
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;

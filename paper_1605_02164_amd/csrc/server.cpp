@@ -557,7 +557,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   }
   std::memcpy(r->Cm, in.C, sizeof(double) * in.d * in.d);
   in.C = r->Cm;
-  int rc = whiten(in.d, r->Cm, r->Wm);
+  int rc = whiten(in.d, r->Cm, r->Wm, in.whiten);
   if (rc) return rc;
   r->R = window_radius(in.sigma_s, spatial_boxes(in.spatial));
   r->kvar = kernel_variant(in.precision, in.spatial);

@@ -205,3 +205,31 @@ def test_spatial_option_validation_before_device_work():
     assert B._spatial("box3+runsum") == 3 | B.BF_SPATIAL_RUNSUM
     with pytest.raises(ValueError):
         B._spatial("box3+fast")
+
+
+@pytest.mark.parametrize("mode", ["chol", "sym"])
+@pytest.mark.parametrize("d,seed", [(2, 11), (3, 12), (6, 13), (8, 14)])
+def test_whitening_modes_match_oracle(mode, d, seed):
+    C = random_spd(d, -3, -1, seed)
+    W = P.bf_whiten(C, mode)
+    ref = O.whiten(C, {"chol": O.WHITEN_CHOL, "sym": O.WHITEN_SYM}[mode])
+    assert np.max(np.abs(W - ref)) <= 1e-12 * np.max(np.abs(ref))
+    if mode == "chol":
+        assert np.array_equal(W, np.tril(W))
+
+
+def test_whitening_mode_validation():
+    L = P.lib()
+    C = np.eye(3) * 0.01
+    W = np.empty((3, 3))
+    assert L.bf_whiten_mode(3, C.ctypes.data_as(ctypes.c_void_p), 3,
+                            W.ctypes.data_as(ctypes.c_void_p)) == B.BF_EINVAL
+    bad = np.array([[1.0, 2, 0], [2, 1, 0], [0, 0, 1]])
+    for mode in (0, 1, 2):
+        assert L.bf_whiten_mode(3, bad.ctypes.data_as(ctypes.c_void_p), mode,
+                                W.ctypes.data_as(ctypes.c_void_p)) == B.BF_ENOTSPD
+    o = B.make_opts()
+    o.whiten = 5
+    rc = L.bf_vec_ex(0x1000, 8, 8, 3, 1.0, C.ctypes.data_as(ctypes.c_void_p), 4, 1, 0x100000,
+                     ctypes.byref(o))
+    assert rc == B.BF_EINVAL

@@ -405,3 +405,25 @@ def test_normaliser_counts_every_term_without_window():
             tol = 1e-4 if prec == "fp32" else 1e-2
             assert np.max(np.abs(zh - 7.0)) < tol, (th, prec, zh.min(), zh.max())
             assert np.max(np.abs(host(out) - g)) < 1e-3
+
+
+@pytest.mark.parametrize("mode,omode", [("chol", O.WHITEN_CHOL), ("sym", O.WHITEN_SYM)])
+def test_whitening_modes_full_image(mode, omode):
+    # non-diagonal C (the Lab-like recipe): the modes give different filters at
+    # finite N, each checked against the oracle with the same whitening (the
+    # order rule and the draws both use that W)
+    say(f"case whitening={mode} lab-like 96x80 crop, automatic N, full image")
+    f, C, p = workload("lab1024_d3_s5_K128", H=96, W=80)
+    K, seed = 24, p["term_seed"]
+    got, N_used = P.bf_vec_ex(cuda(f), p["sigma_s"], C, K, seed, whiten=mode)
+    got = host(got)
+    f64 = f.astype(np.float64)
+    Wm = O.whiten(C, omode)
+    N = O.choose_order(f64, Wm)
+    assert N_used == N
+    _, w = O.sample_terms(C, N, K, seed, W=Wm)
+    ref, _, Z = O.mcsf_separable(f64, p["sigma_s"], w)
+    assert_close(got, ref, f, Z / (K * O.spatial_taps(p["sigma_s"]).sum() ** 2))
+    # and the filter differs from the default whitening's (C is not diagonal)
+    eig = host(P.bf_vec_ex(cuda(f), p["sigma_s"], C, K, seed)[0])
+    assert not np.array_equal(eig, got)
