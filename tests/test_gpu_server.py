@@ -220,8 +220,11 @@ def test_every_dimension_served_equals_standalone(prec):
 
 def test_random_mix_matches_standalone():
     # 60 seeded random requests: every d, odd sizes, windows up to R = 39,
-    # K up to 40, all precisions, merged draws, centring on/off, given N
+    # K up to 40, all precisions, merged draws, centring on/off, given N, and
+    # (from a second stream of draws) every spatial filter, the running-sum
+    # pass and every whitening mode, so one server mixes all kernel variants
     rng = np.random.default_rng(2024)
+    rng2 = np.random.default_rng(4048)
     reqs = []
     for i in range(60):
         d = int(rng.integers(1, 9))
@@ -232,23 +235,42 @@ def test_random_mix_matches_standalone():
         N = int(rng.choice([0, 0, 12, 40]))
         center = bool(rng.integers(0, 2))
         dedup = bool(rng.integers(0, 2))
+        spatial = str(rng2.choice(["gauss", "gauss", "box", "hat", "box3", "box3+runsum"]))
+        if prec != "fp32":
+            spatial = spatial.replace("+runsum", "")
+        whiten = str(rng2.choice(["eig", "chol", "sym"]))
         f = torch.from_numpy(voronoi_image(H, W, d, 5, 0.0, 1.0, 0.02, seed=900 + i)).to(DEV)
         C = random_spd(d, -2.0, -1.0, seed=i)
-        reqs.append((f, sigma, C, K, 77 + i, N, prec, center, dedup))
+        reqs.append((f, sigma, C, K, 77 + i, N, prec, center, dedup, spatial, whiten))
     with P.Server(arena_bytes=1 << 28, quantum_us=float(rng.choice([3.0, 50.0, 1e4]))) as srv:
         ts = []
-        for f, sigma, C, K, seed, N, prec, center, dedup in reqs:
-            t, out = srv.submit(f, sigma, C, K, seed, N=N, precision=prec, center=center,
-                                dedup=dedup)
+        for f, sigma, C, K, seed, N, prec, center, dedup, spatial, whiten in reqs:
+            try:
+                t, out = srv.submit(f, sigma, C, K, seed, N=N, precision=prec, center=center,
+                                    dedup=dedup, spatial=spatial, whiten=whiten)
+            except B.BfError as e:
+                # only a window too large for the LDS budget is refused, and
+                # the standalone call refuses it too
+                assert e.code == B.BF_EUNSUPPORTED, e
+                with pytest.raises(B.BfError):
+                    P.bf_vec_ex(f, sigma, C, K, seed, N=N, precision=prec, spatial=spatial)
+                t, out = None, None
             ts.append((t, out))
         srv.drain(timeout=120.0)
-        for (f, sigma, C, K, seed, N, prec, center, dedup), (t, out) in zip(reqs, ts):
+        n_run = 0
+        for (f, sigma, C, K, seed, N, prec, center, dedup, spatial, whiten), (t, out) in \
+                zip(reqs, ts):
+            if t is None:
+                continue
             st = srv.poll(t)
             assert st["state"] == "done", st
             ref, _ = P.bf_vec_ex(f, sigma, C, K, seed, N=N, precision=prec, center=center,
-                                 dedup=dedup)
+                                 dedup=dedup, spatial=spatial, whiten=whiten)
             torch.cuda.synchronize()
-            assert torch.equal(out, ref), (tuple(f.shape), sigma, K, prec, N, center, dedup)
+            assert torch.equal(out, ref), (tuple(f.shape), sigma, K, prec, N, center, dedup,
+                                           spatial, whiten)
+            n_run += 1
+        assert n_run >= 50
 
 
 def test_concurrent_submitters():
