@@ -241,6 +241,14 @@ int bf_plan_destroy(bf_plan* plan);
  *
  * Threading: every bf_server_* call is thread-safe; the scheduler runs on its
  * own thread.  The server binds to the HIP device current at creation.
+ *
+ * Errors: a launch the runtime refuses (arguments, resources) fails only the
+ * requests packed into it, with BF_EDEVICE, after their earlier work has
+ * drained; the server keeps serving.  A device error reported later (an
+ * event or synchronisation) fails every request, and later submits return it.
+ * Test hook: with BF_FAULT_INJECT=launch:<n> in the environment at
+ * bf_server_create, the server's n-th batched launch is refused that way
+ * without running anything on the device.
  * ---------------------------------------------------------------------- */
 typedef struct bf_server bf_server;   /* opaque */
 

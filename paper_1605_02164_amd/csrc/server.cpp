@@ -21,6 +21,8 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -121,6 +123,7 @@ struct Server {
   int fatal = 0;
   std::string fatal_msg;
   std::thread worker;
+  uint64_t fault_at = 0, launch_count = 0;   // BF_FAULT_INJECT=launch:<n> (test hook)
 
   double now() const {
     return std::chrono::duration<double>(Clock::now() - epoch).count();
@@ -309,6 +312,9 @@ struct Server {
     const std::vector<PlanLaunch> plan = plan_round(jobs, cfg.quantum_us, kMaxBatch);
     std::set<int> used;
     std::vector<Req*> ended;
+    std::set<Req*> failed;
+    std::string failed_msg;
+    size_t n_failed_launches = 0;
     const double t = now();
     uint64_t wgs = 0;
     for (const PlanLaunch& L : plan) {
@@ -324,10 +330,25 @@ struct Server {
         b.first[k + 1] = b.first[k] + r->a.nsx * r->a.nsy;
       }
       hipStream_t st = streams[r0->stream];
-      hipError_t e = launch_fused_batch(r0->in.d, r0->R, r0->kvar, b, st);
+      const bool injected = fault_at != 0 && ++launch_count == fault_at;
+      hipError_t e = injected ? hipErrorLaunchFailure
+                              : launch_fused_batch(r0->in.d, r0->R, r0->kvar, b, st);
       if (e != hipSuccess) {
-        set_fatal(e, "batched fused launch");
-        return true;
+        // Refused at launch (arguments, resources, or the injected fault):
+        // nothing of it runs and the device stays usable, so only this
+        // launch's requests fail, once their earlier chunks on the stream
+        // have drained (their arena blocks are then free to reuse).
+        (void)hipGetLastError();
+        failed_msg = std::string(injected ? "injected fault: " : "") +
+                     "batched fused launch: " + hipGetErrorString(e);
+        const hipError_t q = hipStreamSynchronize(st);
+        if (q != hipSuccess) {
+          set_fatal(q, "stream drain after a refused launch");
+          return true;
+        }
+        for (const PlanItem& it : L.items) failed.insert(active[it.job]);
+        ++n_failed_launches;
+        continue;
       }
       wgs += (uint64_t)b.first[b.n];
       used.insert(r0->stream);
@@ -368,19 +389,21 @@ struct Server {
       for (const PlanLaunch& L : plan)
         for (const PlanItem& it : L.items) {
           Req* r = active[it.job];
+          if (failed.count(r)) continue;
           ++r->chunks;
           if (r->t_start == 0.0) r->t_start = t;
         }
       ++stats.rounds;
-      stats.launches += plan.size();
+      stats.launches += plan.size() - n_failed_launches;
       stats.workgroups += wgs;
     }
     for (Req* r : ended) finishing.push_back(r);
     std::vector<Req*> still;
     still.reserve(active.size());
     for (Req* r : active)
-      if (r->next_t < r->K_run) still.push_back(r);
+      if (!failed.count(r) && r->next_t < r->K_run) still.push_back(r);
     active.swap(still);
+    for (Req* r : failed) finish(r, BF_REQ_FAILED, BF_EDEVICE, failed_msg);
     return true;
   }
 
@@ -647,6 +670,10 @@ int bf_server_create(const bf_server_config* cfg_in, bf_server** out) {
     return fail(BF_ENOMEM, "pinned staging allocation failed");
   }
   s->dev_arena.reset(cfg.arena_bytes, kAlign);
+  if (const char* fi = std::getenv("BF_FAULT_INJECT")) {
+    unsigned long long n = 0;
+    if (std::sscanf(fi, "launch:%llu", &n) == 1) s->fault_at = n;
+  }
   s->pin_arena.reset(pin_bytes, kAlign);
   for (int i = 0; i <= cfg.streams && e == hipSuccess; ++i) {
     hipStream_t st = nullptr;

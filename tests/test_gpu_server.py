@@ -323,3 +323,29 @@ def test_resumed_term_ranges_small_radius(prec):
             ref, _ = P.bf_vec_ex(f, sigma, C, 24, seed=3, precision=prec)
             torch.cuda.synchronize()
             assert torch.equal(out, ref), sigma
+
+
+def test_injected_launch_fault_fails_only_its_requests(monkeypatch):
+    # The hook refuses the server's second batched launch from the host
+    # (nothing runs on the device for it).  Requests go one at a time, each in
+    # one launch: only the second fails, with BF_EDEVICE; the server keeps
+    # serving, and the others equal their standalone results.
+    monkeypatch.setenv("BF_FAULT_INJECT", "launch:2")
+    C = 0.1 ** 2 * np.eye(3)
+    imgs = [torch.from_numpy(voronoi_image(48 + 8 * i, 56, 3, 7, 0.0, 1.0, 0.02, seed=70 + i))
+            .to(DEV) for i in range(5)]
+    sts, outs = [], []
+    with P.Server(arena_bytes=1 << 26, quantum_us=1e9) as srv:
+        for i, f in enumerate(imgs):
+            t, out = srv.submit(f, 2.0, C, 8, seed=5 + i, N=16, precision="fp32")
+            sts.append(srv.wait(t, 60.0))
+            outs.append(out)
+        stats = srv.stats()
+    assert sts[1]["state"] == "failed" and sts[1]["error"] == B.BF_EDEVICE, sts[1]
+    assert "injected" in sts[1]["message"]
+    for i in (0, 2, 3, 4):
+        assert sts[i]["state"] == "done", sts[i]
+        ref, _ = P.bf_vec_ex(imgs[i], 2.0, C, 8, 5 + i, N=16, precision="fp32")
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), i
+    assert stats["failed"] == 1 and stats["completed"] == 4
