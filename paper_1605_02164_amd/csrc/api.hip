@@ -157,6 +157,19 @@ int check_opts(const bf_opts* o) {
 
 }  // namespace
 
+int phase64_flag(int d, const float* wmax, const float* cen, const float* lo, const float* hi) {
+  if (!lo || !hi) return 1;
+  float bound = 0.0f;
+  for (int m = 0; m < d; ++m) bound = std::fmaf(wmax[m], std::fmax(hi[m] - cen[m], cen[m] - lo[m]), bound);
+  return bound <= kPhaseBound ? 0 : 1;
+}
+
+void table_wmax(int d, int K, const float* tab, float* wmax) {
+  for (int m = 0; m < 8; ++m) wmax[m] = 0.0f;
+  for (int t = 0; t < K; ++t)
+    for (int m = 0; m < d; ++m) wmax[m] = std::fmax(wmax[m], std::fabs(tab[(size_t)t * (d + 1) + m]));
+}
+
 int check_spatial(int spatial, int precision) {
   if ((spatial & ~(3 | BF_SPATIAL_RUNSUM)) != 0)
     return fail(BF_EINVAL, "spatial must be a BF_SPATIAL_* value");
@@ -207,15 +220,20 @@ std::vector<float> term_table(int d, int K, const double* w, const double* weigh
   const int ntaps = 2 * window_radius(sigma_s, spatial) + 1;
   const double two_pi = 6.283185307179586476925286766559;
   const size_t n_terms = (size_t)K * NP, n_w = weights ? (size_t)K : 0;
-  std::vector<float> h(n_terms + n_w + (size_t)ntaps, 0.0f);
+  std::vector<float> h(2 * n_terms + n_w + (size_t)ntaps, 0.0f);
   for (int t = 0; t < K; ++t)
-    for (int m = 0; m < d; ++m) h[(size_t)t * NP + m] = (float)(w[(size_t)t * d + m] / two_pi);
+    for (int m = 0; m < d; ++m) {
+      const double x = w[(size_t)t * d + m] / two_pi;
+      const float hi = (float)x;
+      h[(size_t)t * NP + m] = hi;
+      h[n_terms + (size_t)t * NP + m] = (float)(x - (double)hi);
+    }
   if (weights)
-    for (int t = 0; t < K; ++t) h[n_terms + t] = (float)weights[t];
+    for (int t = 0; t < K; ++t) h[2 * n_terms + t] = (float)weights[t];
   const std::vector<double> taps = spatial_taps(sigma_s, spatial);
-  for (int u = 0; u < ntaps; ++u) h[n_terms + n_w + u] = (float)taps[u];
-  *off_weights = weights ? n_terms : (size_t)-1;
-  *off_taps = n_terms + n_w;
+  for (int u = 0; u < ntaps; ++u) h[2 * n_terms + n_w + u] = (float)taps[u];
+  *off_weights = weights ? 2 * n_terms : (size_t)-1;
+  *off_taps = 2 * n_terms + n_w;
   return h;
 }
 
@@ -276,6 +294,7 @@ int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
 }
 
 // Launch the fused filter for a host FP64 term table (radians per unit).
+// lo/hi: per-channel extrema when known (min/max ran), else null.
 int run_terms(const float* f, int H, int W, int d, double sigma_s, const double* w,
               const double* weights, int K, float* out, bf_opts* o, const float* lo,
               const float* hi, int TH) {
@@ -289,7 +308,9 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   FusedArgs a{};
   a.f = f;
   for (int m = 0; m < 8; ++m)
-    a.cen[m] = (o->center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
+    a.cen[m] = (o->center && lo && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
+  table_wmax(d, K, hbuf.data(), a.wmax);
+  a.p64 = phase64_flag(d, a.wmax, a.cen, lo, hi);
   fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0);
   a.fpitch = W;
   a.t0 = 0;
@@ -306,6 +327,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   hipError_t e = hipMemcpyAsync(dterms, hbuf.data(), hbuf.size() * sizeof(float),
                                 hipMemcpyHostToDevice, st);
   a.terms = dterms;
+  a.terms_lo = dterms + (size_t)K * (d + 1);
   a.weights = weights ? dterms + off_w : nullptr;
   a.taps = dterms + off_taps;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -425,7 +447,8 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   int TH = 0;
   if ((rc = plan_fused(H, W, d, sigma_s, o, &TH))) return rc;
   float lo[8] = {0}, hi[8] = {0};
-  if (o->N == 0 || o->center) {
+  const bool have_range = o->N == 0 || o->center;
+  if (have_range) {
     if ((rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   }
   int N = o->N;
@@ -435,13 +458,14 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
     std::vector<double> w, weight;
     distinct_terms(d, Wm, N, K, seed, &w, &weight);
     o->K_used = (int)weight.size();
-    return run_terms(f, H, W, d, sigma_s, w.data(), weight.data(), o->K_used, out, o, lo, hi,
-                     TH);
+    return run_terms(f, H, W, d, sigma_s, w.data(), weight.data(), o->K_used, out, o,
+                     have_range ? lo : nullptr, have_range ? hi : nullptr, TH);
   }
   std::vector<double> w((size_t)K * d);
   frequency_table(d, Wm, N, K, seed, w.data());
   o->K_used = K;
-  return run_terms(f, H, W, d, sigma_s, w.data(), nullptr, K, out, o, lo, hi, TH);
+  return run_terms(f, H, W, d, sigma_s, w.data(), nullptr, K, out, o,
+                   have_range ? lo : nullptr, have_range ? hi : nullptr, TH);
 }
 
 int bf_vec(const float* f, int H, int W, int d, double sigma_s, const double* C, int K,
@@ -480,7 +504,8 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const doub
   if (o->center && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   o->N_used = o->N;
   o->K_used = K;
-  return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, lo, hi, TH);
+  return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, o->center ? lo : nullptr,
+                   o->center ? hi : nullptr, TH);
 }
 
 int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precision, void* stream,
@@ -537,7 +562,9 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
     a.f = f;
     a.acc = dbuf;
     a.terms = dbuf + n_acc;
+    a.terms_lo = a.terms + (size_t)KP * (d + 1);
     a.taps = dbuf + n_acc + off_taps;
+    a.p64 = 0;   // probe phases are small
     fused_geometry(a, H, W, R, precision, ths[i]);
     a.fpitch = W;
     a.t0 = 0;

@@ -15,6 +15,14 @@ constexpr int kB = 8;     // input rows per pipeline step
 constexpr int kP1 = 4;    // horizontal-pass outputs per item (register block)
 constexpr int kP2 = 4;    // vertical-pass outputs per item (register block)
 constexpr int kRMax = 40; // largest window radius handled by the fused kernels
+// Phases (in turns) above this are reduced in FP64: an FP32 phase of 2^8
+// turns keeps 2^-16 turns of resolution, ~1e-4 rad.  Launches whose phase
+// bound sum_m max_t |w_tm/2pi| max|f_m - c_m| stays at or below kPhaseBound
+// (a margin below kPhaseExact for the bound's own rounding) run the kernel
+// instance without the FP64 path; in the other instance lanes below
+// kPhaseExact compute the same operations, so both give the same bits there.
+constexpr float kPhaseExact = 256.0f;
+constexpr float kPhaseBound = 255.0f;
 
 // Staging row width for radius R: at least TW + 2R + 4 floats (the
 // horizontal window of a 4-output block plus one spare block), and equal to
@@ -58,6 +66,7 @@ struct FusedArgs {
                          // padded to whole strips: Hp = nsy*TH, Wp = nsx*kTW
   const float* taps;     // 2R+1 spatial taps (device), zero padded to a multiple of 4
   const float* terms;    // term table (device): row t holds w_t / 2pi in its first d of d+1 floats
+  const float* terms_lo; // same layout: w_t / 2pi minus its FP32 value (for large phases)
   const float* weights;  // K term weights (device), or null for equal weights
   float cen[8];          // per-channel centre subtracted before the phase
   const float* cen_dev;  // or null; else the centre is read here (device, d floats)
@@ -71,7 +80,16 @@ struct FusedArgs {
   int RSB, CRB;          // ring sizes in blocks of kB rows
   int steps, lag;        // steps per term, and 2R look-ahead in steps
   int vbox;              // variant 3: n of the n-fold box (R = n r); else 0
+  int p64;               // 1: instance with the FP64 phase path (phase bound unknown or
+                         // above kPhaseBound), 0: without it
+  float wmax[8];         // max_t |w_tm / 2pi| over the table's FP32 values
 };
+
+// Host side of the FP64-phase decision: 1 unless the per-channel ranges
+// [lo, hi] (or none known: lo = hi = null) bound every phase by kPhaseBound.
+int phase64_flag(int d, const float* wmax, const float* cen, const float* lo, const float* hi);
+// max_t |row t, channel m| of a term table's FP32 frequency rows.
+void table_wmax(int d, int K, const float* tab, float* wmax);
 
 // Several requests of one kernel instance (same d, R, precision) in one
 // launch: workgroups first[i] .. first[i+1]-1 take the strips of req[i].
@@ -132,9 +150,10 @@ int tuned_height(int d, int R, int prec, int H, int W);
 void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox = 0);
 // Accumulator floats of a planned FusedArgs: (d+1) planes of Hp x Wp.
 size_t fused_acc_floats(const FusedArgs& a, int d);
-// Host term table: K rows of w_t/2pi (stride d+1) | K weights (if any) | 2R+1
-// taps of the spatial filter.  Offsets of the weights and taps are returned
-// in floats.
+// Host term table: K rows of w_t/2pi (stride d+1, FP32) | K rows of the
+// remainders w_t/2pi - FP32(w_t/2pi) | K weights (if any) | 2R+1 taps of the
+// spatial filter.  The remainders start at K*(d+1); the offsets of the
+// weights and taps are returned in floats.
 std::vector<float> term_table(int d, int K, const double* w, const double* weights,
                               double sigma_s, size_t* off_weights, size_t* off_taps,
                               int spatial = 0);

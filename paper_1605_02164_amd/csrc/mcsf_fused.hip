@@ -59,7 +59,7 @@ static int blocks_per_cu_drp(int R) {
   const size_t lds = fused_lds_bytes(D, R, PREC);
   hipFuncAttributes at{};
   int vgpr = 256;
-  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC>)) ==
+  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>)) ==
           hipSuccess &&
       at.numRegs > 0)
     vgpr = at.numRegs;

@@ -342,7 +342,7 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // a.t0 .. a.t1-1 (Algorithm 1's term loop over one strip).
 // RC: window radius fixed at compile time, or -1 for a runtime radius.
 // PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
-template <int D, int RC, int PREC>
+template <int D, int RC, int PREC, bool P64>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
   using G = Geo<D>;
@@ -526,7 +526,18 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         float rho = 0.0f;
 #pragma unroll
         for (int m = 0; m < D; ++m) rho = fmaf(wr[m], fv[m], rho);
-        const float fr = __builtin_amdgcn_fractf(rho);
+        float fr = __builtin_amdgcn_fractf(rho);
+        if (P64 && fabsf(rho) > kPhaseExact) {
+          // beyond 2^8 turns the FP32 phase keeps too few fraction bits:
+          // reduce it in FP64 from w/2pi to ~48 bits (FP32 value + remainder)
+          // and the exact difference f - c
+          double rd = 0.0;
+#pragma unroll
+          for (int m = 0; m < D; ++m)
+            rd = fma((double)wr[m] + (double)ld_const(a.terms_lo, t * NP + m),
+                     (double)fcur[i][m] - (double)cen[m], rd);
+          fr = (float)(rd - floor(rd));
+        }
         float c = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
         c = in ? c : 0.0f;
         sn = in ? sn : 0.0f;
@@ -734,20 +745,22 @@ __device__ __forceinline__ int xcd_order(int bid, int n) {
   return n % 8 == 0 ? (bid % 8) * (n / 8) + bid / 8 : bid;
 }
 
-// One request: one workgroup per strip.
-template <int D, int RC, int PREC>
+// One request: one workgroup per strip.  P64: instance with the FP64 phase
+// path (its branches cost the common path a few percent, so launches whose
+// phases are bounded below 2^8 turns use the instance without it).
+template <int D, int RC, int PREC, bool P64>
 __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused(FusedArgs a) {
-  fused_strip<D, RC, PREC>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
+  fused_strip<D, RC, PREC, P64>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
 }
 
 // Several requests of the same instance in one launch (continuous batching):
 // the workgroup finds its request in the prefix table.
-template <int D, int RC, int PREC>
+template <int D, int RC, int PREC, bool P64>
 __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_batch(BatchArgs g) {
   const int bid = xcd_order(blockIdx.x, g.first[g.n]);
   int i = 0;
   while (i + 1 < g.n && bid >= g.first[i + 1]) ++i;
-  fused_strip<D, RC, PREC>(g.req[i], bid - g.first[i]);
+  fused_strip<D, RC, PREC, P64>(g.req[i], bid - g.first[i]);
 }
 
 
@@ -757,11 +770,11 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
   const size_t lds = fused_lds_bytes(D, R, PREC);
   int nwg;
   void (*kern)(A);
-  if constexpr (std::is_same_v<A, BatchArgs>) {
-    kern = mcsf_fused_batch<D, RC, PREC>;
+  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64
+    kern = a.req[0].p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
     nwg = a.first[a.n];
   } else {
-    kern = mcsf_fused<D, RC, PREC>;
+    kern = a.p64 ? mcsf_fused<D, RC, PREC, true> : mcsf_fused<D, RC, PREC, false>;
     nwg = a.nsx * a.nsy;
   }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

@@ -190,6 +190,9 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   }
   a.acc = p->dev;
   a.terms = p->dev + n_acc;
+  a.terms_lo = a.terms + (size_t)Kr * (d + 1);
+  table_wmax(d, Kr, tab.data(), a.wmax);
+  a.p64 = 1;   // the image's range is not known when the graph is captured
   a.weights = o->dedup ? a.terms + off_w : nullptr;
   a.taps = a.terms + off_taps;
   if (o->center) {

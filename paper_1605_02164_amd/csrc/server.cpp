@@ -109,7 +109,7 @@ struct Server {
   std::condition_variable cv_work, cv_done;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   std::deque<Req*> incoming;
-  std::map<std::tuple<int, int, int>, int> variants;  // (d, R, kernel variant) -> id
+  std::map<std::tuple<int, int, int, int>, int> variants;  // (d, R, kernel variant, p64) -> id
   uint64_t next_ticket = 1;
   bool stop = false;
   int queued = 0, admitted = 0;
@@ -195,6 +195,20 @@ struct Server {
     const std::vector<float> tab = term_table(d, K, w.data(), r->in.dedup ? weight.data() : nullptr,
                                               r->in.sigma_s, &off_w, &off_taps,
                                               spatial_boxes(r->in.spatial));
+    for (int m = 0; m < 8; ++m)
+      r->a.cen[m] = (r->in.center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
+    // the extrema are known when the min/max ran (order rule or centring)
+    table_wmax(d, K, tab.data(), r->a.wmax);
+    r->a.p64 = phase64_flag(d, r->a.wmax, r->a.cen, r->need_minmax ? lo : nullptr,
+                            r->need_minmax ? hi : nullptr);
+    {  // kernel instance (d, R, variant, FP64-phase path): its id picks the stream
+      std::lock_guard<std::mutex> lk(mu);
+      const auto key = std::make_tuple(d, r->R, r->kvar, r->a.p64);
+      auto it = variants.find(key);
+      if (it == variants.end()) it = variants.emplace(key, (int)variants.size()).first;
+      r->variant = it->second;
+      r->stream = r->variant % cfg.streams;
+    }
     float* ptab = r->pin + 32;
     std::memcpy(ptab, tab.data(), tab.size() * sizeof(float));
     float* dtab = reinterpret_cast<float*>(dev_base + r->dev_off) + r->n_acc;
@@ -206,11 +220,10 @@ struct Server {
       return false;
     }
     r->a.terms = dtab;
+    r->a.terms_lo = dtab + (size_t)K * (d + 1);
     r->a.weights = r->in.dedup ? dtab + off_w : nullptr;
     r->a.taps = dtab + off_taps;
     r->K_run = K;
-    for (int m = 0; m < 8; ++m)
-      r->a.cen[m] = (r->in.center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
     std::lock_guard<std::mutex> lk(mu);
     r->N_used = N;
     r->state = BF_REQ_RUNNING;
@@ -602,7 +615,8 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   r->a.fpitch = in.pitch;
   r->n_acc = fused_acc_floats(r->a, in.d);
   // term table at most K rows of d+1 floats, K weights (merged draws), 2R+1 taps
-  r->n_tab = (size_t)in.K * (in.d + 2) + (size_t)(2 * r->R + 1);
+  // hi and lo term rows, weights, taps (term_table's layout)
+  r->n_tab = (size_t)in.K * (2 * in.d + 3) + (size_t)(2 * r->R + 1);
   r->need_minmax = in.N == 0 || in.center;
   r->nparts = minmax_parts((size_t)in.H * in.W);
   const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMResult : 0;
@@ -707,11 +721,6 @@ int bf_server_submit(bf_server* s, const bf_request* q, uint64_t* ticket) {
   if (s->fatal) return fail(s->fatal, s->fatal_msg);
   if (s->cfg.max_queued > 0 && s->queued >= s->cfg.max_queued)
     return fail(BF_EBUSY, "serving queue full");
-  const auto key = std::make_tuple(r->in.d, r->R, r->kvar);
-  auto it = s->variants.find(key);
-  if (it == s->variants.end()) it = s->variants.emplace(key, (int)s->variants.size()).first;
-  r->variant = it->second;
-  r->stream = r->variant % s->cfg.streams;
   r->ticket = s->next_ticket++;
   *ticket = r->ticket;
   Req* raw = r.get();

@@ -427,3 +427,31 @@ def test_whitening_modes_full_image(mode, omode):
     # and the filter differs from the default whitening's (C is not diagonal)
     eig = host(P.bf_vec_ex(cuda(f), p["sigma_s"], C, K, seed)[0])
     assert not np.array_equal(eig, got)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4)])
+def test_large_phases_reduced_in_fp64(precision, tol):
+    # Uncentred data near 100 with sigma_r = 0.02: phases <w_t, f> reach ~3e3
+    # turns, where an FP32 phase keeps ~1e-4 turns of resolution; the kernel
+    # then reduces the phase in FP64.  Same bound as the centred filter.
+    # (16-bit storage of uncentred data this far from zero spends its 11
+    # mantissa bits on the offset; centring, the default, is what keeps those
+    # modes accurate, so they are not run here.)
+    say(f"case large phases {precision}: 48x40x3 in [100, 101], sigma_r = 0.02, no centring")
+    f = voronoi_image(48, 40, 3, 5, 100.0, 101.0, 0.02, 123)
+    C = 0.02 ** 2 * np.eye(3)
+    K, seed, sigma = 32, 17, 0.5
+    got, N_used = P.bf_vec_ex(cuda(f), sigma, C, K, seed, center=False, precision=precision)
+    got = host(got)
+    f64 = f.astype(np.float64)
+    Nref, w = oracle_terms(f64, C, K, seed)
+    assert N_used == Nref
+    turns = np.abs(np.tensordot(f64, w.T, axes=(2, 0))).max() / (2 * math.pi)
+    say(f"  N={N_used} max |phase| = {turns:.0f} turns")
+    assert turns > 256
+    ref, _, Z = O.mcsf_separable(f64, sigma, w)
+    z = Z / (K * O.spatial_taps(sigma).sum() ** 2)
+    ok = z >= ZMIN
+    err = rel_err_per_channel(got[ok], ref[ok], f)
+    say(f"  rel_err={err} ill-conditioned={int((~ok).sum())}")
+    assert np.all(err <= tol), err
