@@ -35,14 +35,14 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "e67e98a97024a13e4ba26df88969ed4e32822ddd240fbc0a4034c8fda1b321f2",
-    "fp32": {"fetch_kib": 90370698, "write_kib": 67285233,
+    "sha256": "18b25fbb896e982dbe535ae3cc2eca9ef710047de63c1f60ffbb20035cfc3e1d",
+    "fp32": {"fetch_kib": 92901649, "write_kib": 67527142,
              # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
              "executed_flops": 142493114368 * 64},
-    "fp16": {"fetch_kib": 144603758, "write_kib": 70556389,
+    "fp16": {"fetch_kib": 147122033, "write_kib": 70242442,
              # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
              "executed_flops": (145995333632 + 5494587392) * 64},
-    "fetch_factor": 1048576 / 524306.75,
+    "fetch_factor": 1048576 / 524313.5625,
     "write_factor": 1048576 / 1048576.0,
 }
 
