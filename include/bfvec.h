@@ -198,6 +198,10 @@ int bf_direct(const float* f, int H, int W, int d, double sigma_s,
  * division of Algorithm 1.  With centring the kernels read the centre from
  * the device min/max result, formed as bf_vec_ex forms it on the host, so
  * out is bit-identical to bf_vec_ex with the same arguments and options.
+ * The image's range is unknown when a graph is captured, so plans always
+ * run the kernel instance that can reduce large phases in FP64 (about 2%
+ * slower than the one bf_vec_ex picks for phases below 2^8 turns; results
+ * are the same bits).
  * ------------------------------------------------------------------------ */
 typedef struct bf_plan bf_plan;   /* opaque */
 

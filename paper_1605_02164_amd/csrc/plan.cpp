@@ -26,7 +26,7 @@
 #include "mcsf_common.h"
 
 struct bf_plan {
-  int H = 0, W = 0, d = 0, prec = 0, center = 0;
+  int H = 0, W = 0, d = 0, variant = 0, center = 0;   // variant: kernel_variant()
   bfvec::FusedArgs a{};        // geometry, tables and accumulators (no f)
   float* dev = nullptr;        // accumulators | term table | min/max partials | result
   int nparts = 0;
@@ -72,7 +72,7 @@ hipError_t record_steps(bf_plan* p, const float* f, float* out) {
   FusedArgs a = p->a;
   a.f = f;
   a.cen_dev = cen;
-  if (e == hipSuccess) e = launch_fused(p->d, p->prec, a, p->cap);
+  if (e == hipSuccess) e = launch_fused(p->d, p->variant, a, p->cap);
   if (e == hipSuccess) {
     FinalizeArgs fa{};
     fa.acc = a.acc;
@@ -167,7 +167,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   p->H = H;
   p->W = W;
   p->d = d;
-  p->prec = variant;
+  p->variant = variant;
   p->center = o->center;
   FusedArgs& a = p->a;
   fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0);
