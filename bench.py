@@ -339,13 +339,12 @@ def study_spatial(P, torch, log_fn):
         rec = {"sigma_s": s_}
         for prec, sp in (("fp32", "gauss"), ("fp32", "box3"), ("fp32", "box3+runsum"),
                          ("fp16", "gauss"), ("fp16", "box3")):
-            if True:
-                ms = []
-                for _ in range(6):
-                    _, o = P.bf_vec_ex(f, s_, C, 64, 11, out=out, N=37, precision=prec,
-                                       spatial=sp, time_kernel=True, return_opts=True)
-                    ms.append(o.kernel_ms)
-                rec[f"{sp}_{prec}_ms"] = float(np.median(ms[1:]))
+            ms = []
+            for _ in range(6):
+                _, o = P.bf_vec_ex(f, s_, C, 64, 11, out=out, N=37, precision=prec,
+                                   spatial=sp, time_kernel=True, return_opts=True)
+                ms.append(o.kernel_ms)
+            rec[f"{sp}_{prec}_ms"] = float(np.median(ms[1:]))
         rec["R_gauss"] = _radius(s_, 0)
         rec["R_box3"] = _radius(s_, 3)
         log_fn(f"spatial sigma_s={s_}: " + ", ".join(f"{k} {v:.3g}" for k, v in rec.items()

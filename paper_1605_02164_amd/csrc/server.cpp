@@ -70,7 +70,7 @@ struct Req {
   bf_request in{};
   double Cm[64] = {0};
   double Wm[64] = {0};
-  int R = 0, variant = 0, stream = 0;   // variant: instance id (d, R, kvar) of the server
+  int R = 0, variant = 0, stream = 0;   // variant: the server's instance id (d, R, kvar, p64)
   int kvar = 0;                         // kernel variant (precision, running-sum box pass)
   FusedArgs a{};
   size_t n_acc = 0, n_tab = 0, off_w = 0, off_taps = 0;
