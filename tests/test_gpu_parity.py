@@ -303,9 +303,11 @@ def test_low_precision_voronoi128_full_image(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_low_precision_voronoi4096_sampled(prec):
-    say(f"case {prec} voronoi4096_d3_s10_K256 full size, sampled pixels")
-    f, C, p = workload("voronoi4096_d3_s10_K256")
+@pytest.mark.parametrize("name", ["voronoi4096_d3_s10_K256", "feature2048_d6_s4_K256",
+                                  "lab1024_d3_s5_K128"])
+def test_low_precision_full_size_sampled(prec, name):
+    say(f"case {prec} {name} full size, sampled pixels")
+    f, C, p = workload(name)
     pix = sample_pixels(p["H"], p["W"], 32, 5, R=O.window_radius(p["sigma_s"]))
     got, N = P.bf_vec_ex(cuda(f), p["sigma_s"], C, p["K"], p["term_seed"], precision=prec)
     f64 = f.astype(np.float64)
