@@ -480,7 +480,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "the filter shards by image strips or by requests, see DESIGN.md", file=sys.stderr)
+              "the filter would shard by bands of image rows (R halo rows copied once per "
+              "neighbour) or by requests", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
