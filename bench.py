@@ -479,7 +479,7 @@ def main():
                          "FETCH_SIZE/WRITE_SIZE counters against known traffic) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}); "
               "the filter would shard by bands of image rows (R halo rows copied once per "
               "neighbour) or by requests", file=sys.stderr)
         sys.exit(2)
