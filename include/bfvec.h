@@ -102,6 +102,11 @@ typedef struct bf_opts {
   int spatial;     /* BF_SPATIAL_* (default BF_SPATIAL_GAUSS), optionally
                       | BF_SPATIAL_RUNSUM with a box filter and BF_FP32       */
   int whiten;      /* BF_WHITEN_* (default BF_WHITEN_EIG)                      */
+  int tile_w_used; /* OUT: strip width in columns the fused kernel ran with:
+                      32 for d = 3 at the radii with compile-time kernels
+                      (3 sigma_s in {6, 9, ..., 24, 30}) when the FP32/FP16/
+                      BF16 variant runs without the FP64 phase path, W >= 32
+                      and occupancy allows; else 16.  Same output bits.       */
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,

@@ -81,6 +81,7 @@ class bf_opts(ctypes.Structure):
         ("tile_h_used", ctypes.c_int),
         ("spatial", ctypes.c_int),
         ("whiten", ctypes.c_int),
+        ("tile_w_used", ctypes.c_int),
     ]
 
 
@@ -390,6 +391,7 @@ class Plan:
         self._h = h
         self.shape = (int(H), int(W), int(d))
         self.N_used, self.K_used, self.tile_h_used = o.N_used, o.K_used, o.tile_h_used
+        self.tile_w_used = o.tile_w_used
 
     def __call__(self, f, out=None, stream=None):
         """Queue the filter of f into out on ``stream`` (default: current

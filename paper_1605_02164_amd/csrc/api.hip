@@ -184,14 +184,14 @@ int check_fused_size(int H, int W, int pitch, int d, int R) {
   if (R > kRMax) return fail(BF_EUNSUPPORTED, "sigma_s too large: window radius above 40");
   // the kernels address f and the accumulators with 32-bit byte offsets
   // (buffer loads): each must stay below 2^30 floats
-  const double elems = (double)(H + 2 * kB) * (double)(W + kTW) * (double)(d + 1);
+  const double elems = (double)(H + 2 * kB) * (double)(W + kTWMax) * (double)(d + 1);
   const double felems = (double)H * (double)pitch * (double)d;
   if (elems >= 1073741824.0 - 65536.0 || felems >= 1073741824.0 - 65536.0)
     return fail(BF_EUNSUPPORTED, "image too large: H*W*(d+1) must stay below 2^30 elements");
   return BF_OK;
 }
 
-void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox) {
+void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox, int TW) {
   // The kernel prefetches accumulators two steps ahead, which needs at least
   // two steps per term: with no look-ahead rows (R = 0) strips are >= 16 rows.
   if (lag_steps(R) + TH / kB < 2) TH = 2 * kB;
@@ -199,9 +199,10 @@ void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbo
   a.W = W;
   a.R = R;
   a.TH = TH;
-  a.nsx = (W + kTW - 1) / kTW;
+  a.TWc = TW;
+  a.nsx = (W + TW - 1) / TW;
   a.nsy = (H + TH - 1) / TH;
-  a.SW = (prec == 1 || prec == 2) ? stage_width16(R) : stage_width(R);
+  a.SW = (prec == 1 || prec == 2) ? stage_width16(R, TW) : stage_width(R, TW);
   a.lag = lag_steps(R);
   a.RSB = ring_steps(R, vbox);
   a.vbox = vbox;
@@ -211,7 +212,7 @@ void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbo
 }
 
 size_t fused_acc_floats(const FusedArgs& a, int d) {
-  return (size_t)(d + 1) * a.Hp * a.nsx * kTW;
+  return (size_t)(d + 1) * a.Hp * a.nsx * a.TWc;
 }
 
 std::vector<float> term_table(int d, int K, const double* w, const double* weights,
@@ -311,11 +312,19 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
     a.cen[m] = (o->center && lo && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
   table_wmax(d, K, hbuf.data(), a.wmax);
   a.p64 = phase64_flag(d, a.wmax, a.cen, lo, hi);
-  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0);
+  // the strip width depends on the phase path; a width other than kTW has
+  // its own strip height unless the caller fixed one
+  const int TW = choose_strip_width(d, R, variant, a.p64, W);
+  if (TW != kTW && o->tile_h <= 0) {
+    const int rc = choose_strip_height(d, R, variant, H, W, 0, &TH, TW);
+    if (rc) return rc;
+  }
+  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0, TW);
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = K;
   o->tile_h_used = a.TH;
+  o->tile_w_used = a.TWc;
 
   // one stream-ordered allocation: accumulators | terms | weights | taps
   const size_t n_acc = fused_acc_floats(a, d);
@@ -348,7 +357,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
     fa.H = H;
     fa.W = W;
     fa.Hp = a.Hp;
-    fa.Wp = a.nsx * kTW;
+    fa.Wp = a.nsx * a.TWc;
     e = launch_finalize(d, fa, st);
   }
   if (e == hipSuccess && o->time_kernel) {
@@ -521,7 +530,9 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   int TH0 = 0;   // validates the window against the LDS budget
   if ((rc = choose_strip_height(d, R, precision, H, W, 0, &TH0))) return rc;
   (void)TH0;
-  const int model = model_strip_height(d, R, precision, H, W);
+  // the probes run without the FP64 phase path, at that path's strip width
+  const int TW = choose_strip_width(d, R, precision, 0, W);
+  const int model = model_strip_height(d, R, precision, H, W, TW);
   // candidate strip counts down the image around the model's
   const int nsy0 = (H + model - 1) / model, nmax = (H + kB - 1) / kB;
   std::vector<int> ths;
@@ -540,7 +551,7 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   size_t n_acc = 0;
   for (int th : ths) {
     FusedArgs a{};
-    fused_geometry(a, H, W, R, precision, th);
+    fused_geometry(a, H, W, R, precision, th, 0, TW);
     n_acc = std::max(n_acc, fused_acc_floats(a, d));
   }
   hipStream_t st = (hipStream_t)stream;
@@ -565,7 +576,7 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
     a.terms_lo = a.terms + (size_t)KP * (d + 1);
     a.taps = dbuf + n_acc + off_taps;
     a.p64 = 0;   // probe phases are small
-    fused_geometry(a, H, W, R, precision, ths[i]);
+    fused_geometry(a, H, W, R, precision, ths[i], 0, TW);
     a.fpitch = W;
     a.t0 = 0;
     a.t1 = KP;
@@ -597,7 +608,7 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "autotune");
-  record_tuned_height(d, R, precision, H, W, best_th);
+  record_tuned_height(d, R, precision, H, W, best_th, TW);
   if (tile_h) *tile_h = best_th;
   if (ms_per_term) *ms_per_term = best / KP;
   return BF_OK;

@@ -10,7 +10,8 @@
 namespace bfvec {
 
 // Tile geometry of the fused kernels.
-constexpr int kTW = 16;   // output columns per workgroup strip
+constexpr int kTW = 16;   // output columns per workgroup strip (the default width)
+constexpr int kTWMax = 32; // the wide strips of some instances (64 (d+1) * 2 threads)
 constexpr int kB = 8;     // input rows per pipeline step
 constexpr int kP1 = 4;    // horizontal-pass outputs per item (register block)
 constexpr int kP2 = 4;    // vertical-pass outputs per item (register block)
@@ -29,14 +30,14 @@ constexpr float kPhaseBound = 255.0f;
 // 16 modulo 32: measured on gfx950, that residue makes the 128-bit window
 // loads of the horizontal pass free of LDS bank conflicts for the lane order
 // used (widths of other residues cost one to two extra passes per load).
-inline constexpr int stage_width(int R) {
-  return 32 * ((kTW + 2 * R + 4 - 16 + 31) / 32) + 16;
+inline constexpr int stage_width(int R, int TW = kTW) {
+  return 32 * ((TW + 2 * R + 4 - 16 + 31) / 32) + 16;
 }
 // Same for 16-bit storage (elements, always even): at least TW + 2R + 4, with
 // the row width in dwords not a multiple of 16 -- measured on gfx950, 64-bit
 // window loads then conflict 2-way, against 4- to 8-way for multiples of 16.
-inline constexpr int stage_width16(int R) {
-  const int dw = (kTW + 2 * R + 4 + 3) / 4 * 2;   // dwords, even (64-bit aligned rows)
+inline constexpr int stage_width16(int R, int TW = kTW) {
+  const int dw = (TW + 2 * R + 4 + 3) / 4 * 2;   // dwords, even (64-bit aligned rows)
   return 2 * (dw % 16 == 0 ? dw + 2 : dw);
 }
 constexpr int kSWMax = stage_width(kRMax);
@@ -63,7 +64,7 @@ int check_spatial(int spatial, int precision);
 struct FusedArgs {
   const float* f;        // input (device), row y at f + y*fpitch*d
   float* acc;            // (d+1)*Hp*Wp accumulators, planar [m][y][x] (device),
-                         // padded to whole strips: Hp = nsy*TH, Wp = nsx*kTW
+                         // padded to whole strips: Hp = nsy*TH, Wp = nsx*TWc
   const float* taps;     // 2R+1 spatial taps (device), zero padded to a multiple of 4
   const float* terms;    // term table (device): row t holds w_t / 2pi in its first d of d+1 floats
   const float* terms_lo; // same layout: w_t / 2pi minus its FP32 value (for large phases)
@@ -80,6 +81,7 @@ struct FusedArgs {
   int RSB, CRB;          // ring sizes in blocks of kB rows
   int steps, lag;        // steps per term, and 2R look-ahead in steps
   int vbox;              // variant 3: n of the n-fold box (R = n r); else 0
+  int TWc;               // strip width: kTW, or kTWMax for the wide-strip instances
   int p64;               // 1: instance with the FP64 phase path (phase bound unknown or
                          // above kPhaseBound), 0: without it
   float wmax[8];         // max_t |w_tm / 2pi| over the table's FP32 values
@@ -112,10 +114,15 @@ struct FinalizeArgs {
 
 // prec: the kernel variant (kernel_variant): 0 = FP32 channels, 1 = FP16
 // storage, 2 = BF16 storage (FP32 accumulation), 3 = FP32 with the
-// running-sum vertical pass
-size_t fused_lds_bytes(int d, int R, int prec);
+// running-sum vertical pass; TW: strip width
+size_t fused_lds_bytes(int d, int R, int prec, int TW = kTW);
 // resident workgroups per compute unit for this kernel instance (device query)
-int fused_blocks_per_cu(int d, int R, int prec);
+int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW);
+// Strip width for a launch: kTWMax where a wide-strip instance exists (d = 3,
+// a specialised radius, variants 0-2, no FP64 phase path, W >= kTWMax) and
+// keeps at least three quarters of the waves per CU resident that kTW strips
+// keep; else kTW.
+int choose_strip_width(int d, int R, int prec, int p64, int W);
 hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st);
 // All requests of b share d, R and prec (and hence LDS size and staging width).
 hipError_t launch_fused_batch(int d, int R, int prec, const BatchArgs& b, hipStream_t st);
@@ -137,17 +144,19 @@ hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* 
 int check_fused_size(int H, int W, int pitch, int d, int R);
 // Strip height: requested > 0 forces it; otherwise a height measured by
 // bf_autotune for this device and shape, else the occupancy model.
-int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH);
+int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH,
+                        int TW = kTW);
 // The occupancy model alone: minimises (waves of workgroups) x (rows + halo).
-int model_strip_height(int d, int R, int prec, int H, int W);
+int model_strip_height(int d, int R, int prec, int H, int W, int TW = kTW);
 // Process-wide table of measured strip heights, keyed by the current device,
-// d, R, precision and the image shape.
-void record_tuned_height(int d, int R, int prec, int H, int W, int TH);
-int tuned_height(int d, int R, int prec, int H, int W);
+// d, R, precision, the image shape and the strip width.
+void record_tuned_height(int d, int R, int prec, int H, int W, int TH, int TW = kTW);
+int tuned_height(int d, int R, int prec, int H, int W, int TW = kTW);
 // Strip geometry, staging width and ring sizes of a FusedArgs (TH is raised
 // to 16 when R = 0 so that every term has at least two pipeline steps);
 // vbox = n for variant 3, else 0.
-void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox = 0);
+void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbox = 0,
+                    int TW = kTW);
 // Accumulator floats of a planned FusedArgs: (d+1) planes of Hp x Wp.
 size_t fused_acc_floats(const FusedArgs& a, int d);
 // Host term table: K rows of w_t/2pi (stride d+1, FP32) | K rows of the

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
 // Host-side launch helpers
 // ---------------------------------------------------------------------------
 
-size_t fused_lds_bytes(int d, int R, int prec) {
+size_t fused_lds_bytes(int d, int R, int prec, int TW) {
   const int NP = d + 1, NC = 2 * NP;
   const bool lp = prec == 1 || prec == 2, vb = prec == 3;
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
@@ -45,67 +45,89 @@ size_t fused_lds_bytes(int d, int R, int prec) {
   // variant 3 sizes the ring for the largest n (three boxes)
   const int RS = ring_steps(R, vb ? 3 : 0) * kB, CRS = (lag + 2) * kB;
   const size_t fl = (size_t)taps_al + (lp ? 2 * (size_t)tapp_al : 0) +
-                    (size_t)kB * NC * (lp ? stage_width16(R) / 2 : stage_width(R)) +
-                    (size_t)(lp ? RS / 2 : RS) * NC * kTW + (size_t)CRS * 2 * kTW +
-                    (vb ? (size_t)16 * NC * kTW : 0);
+                    (size_t)kB * NC * (lp ? stage_width16(R, TW) / 2 : stage_width(R, TW)) +
+                    (size_t)(lp ? RS / 2 : RS) * NC * TW + (size_t)CRS * 2 * TW +
+                    (vb ? (size_t)16 * NC * TW : 0);
   return fl * sizeof(float);
 }
 
 // Resident workgroups per CU from the instance's register count and LDS:
 // a CU has 160 KB of LDS and 4 SIMDs of 512 VGPRs per lane (at most 8 waves
-// each); a workgroup of D+1 waves puts ceil((D+1)/4) waves on a SIMD.
+// each); a workgroup of (D+1)*TW/16 waves puts a quarter of them, rounded
+// up, on a SIMD.
 template <int D, int RC, int PREC>
-static int blocks_per_cu_drp(int R) {
-  const size_t lds = fused_lds_bytes(D, R, PREC);
+static int blocks_per_cu_drp(int R, int TW) {
+  const size_t lds = fused_lds_bytes(D, R, PREC, TW);
+  const void* kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>);
+  if constexpr (kHasWide<D, RC, PREC>)
+    if (TW == kTWMax) kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax>);
   hipFuncAttributes at{};
   int vgpr = 256;
-  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>)) ==
-          hipSuccess &&
-      at.numRegs > 0)
-    vgpr = at.numRegs;
+  if (hipFuncGetAttributes(&at, kern) == hipSuccess && at.numRegs > 0) vgpr = at.numRegs;
   const int waves_per_simd = std::min(8, 512 / ((vgpr + 7) / 8 * 8));
-  const int per_block = (D + 1 + 3) / 4;
+  const int per_block = ((D + 1) * (TW / kTW) + 3) / 4;
   const int by_vgpr = waves_per_simd / per_block;
   const int by_lds = (int)((160 * 1024) / lds);
   return std::max(1, std::min(by_vgpr, by_lds));
 }
 
 template <int D, int PREC>
-static int bpc_dp(int R) {
+static int bpc_dp(int R, int TW) {
   switch (R) {
-    case 6: return blocks_per_cu_drp<D, 6, PREC>(R);
-    case 9: return blocks_per_cu_drp<D, 9, PREC>(R);
-    case 12: return blocks_per_cu_drp<D, 12, PREC>(R);
-    case 15: return blocks_per_cu_drp<D, 15, PREC>(R);
-    case 18: return blocks_per_cu_drp<D, 18, PREC>(R);
-    case 21: return blocks_per_cu_drp<D, 21, PREC>(R);
-    case 24: return blocks_per_cu_drp<D, 24, PREC>(R);
-    case 30: return blocks_per_cu_drp<D, 30, PREC>(R);
-    default: return blocks_per_cu_drp<D, -1, PREC>(R);
+    case 6: return blocks_per_cu_drp<D, 6, PREC>(R, TW);
+    case 9: return blocks_per_cu_drp<D, 9, PREC>(R, TW);
+    case 12: return blocks_per_cu_drp<D, 12, PREC>(R, TW);
+    case 15: return blocks_per_cu_drp<D, 15, PREC>(R, TW);
+    case 18: return blocks_per_cu_drp<D, 18, PREC>(R, TW);
+    case 21: return blocks_per_cu_drp<D, 21, PREC>(R, TW);
+    case 24: return blocks_per_cu_drp<D, 24, PREC>(R, TW);
+    case 30: return blocks_per_cu_drp<D, 30, PREC>(R, TW);
+    default: return blocks_per_cu_drp<D, -1, PREC>(R, TW);
   }
 }
 
 template <int PREC>
-static int bpc_p(int d, int R) {
+static int bpc_p(int d, int R, int TW) {
   switch (d) {
-    case 1: return blocks_per_cu_drp<1, -1, PREC>(R);
-    case 2: return blocks_per_cu_drp<2, -1, PREC>(R);
-    case 3: return bpc_dp<3, PREC>(R);
-    case 4: return blocks_per_cu_drp<4, -1, PREC>(R);
-    case 5: return blocks_per_cu_drp<5, -1, PREC>(R);
-    case 6: return bpc_dp<6, PREC>(R);
-    case 7: return blocks_per_cu_drp<7, -1, PREC>(R);
-    default: return blocks_per_cu_drp<8, -1, PREC>(R);
+    case 1: return blocks_per_cu_drp<1, -1, PREC>(R, TW);
+    case 2: return blocks_per_cu_drp<2, -1, PREC>(R, TW);
+    case 3: return bpc_dp<3, PREC>(R, TW);
+    case 4: return blocks_per_cu_drp<4, -1, PREC>(R, TW);
+    case 5: return blocks_per_cu_drp<5, -1, PREC>(R, TW);
+    case 6: return bpc_dp<6, PREC>(R, TW);
+    case 7: return blocks_per_cu_drp<7, -1, PREC>(R, TW);
+    default: return blocks_per_cu_drp<8, -1, PREC>(R, TW);
   }
 }
 
-int fused_blocks_per_cu(int d, int R, int prec) {
-  switch (prec) {
-    case 0: return bpc_p<0>(d, R);
-    case 1: return bpc_p<1>(d, R);
-    case 2: return bpc_p<2>(d, R);
-    default: return bpc_p<3>(d, R);
+// the radii with compile-time instances (launch_dp in the device header)
+static bool specialised_radius(int R) {
+  switch (R) {
+    case 6: case 9: case 12: case 15: case 18: case 21: case 24: case 30: return true;
+    default: return false;
   }
+}
+
+int fused_blocks_per_cu(int d, int R, int prec, int TW) {
+  switch (prec) {
+    case 0: return bpc_p<0>(d, R, TW);
+    case 1: return bpc_p<1>(d, R, TW);
+    case 2: return bpc_p<2>(d, R, TW);
+    default: return bpc_p<3>(d, R, TW);
+  }
+}
+
+int choose_strip_width(int d, int R, int prec, int p64, int W) {
+  if (d != 3 || prec > 2 || p64 || W < kTWMax || !specialised_radius(R)) return kTW;
+  if (fused_lds_bytes(d, R, prec, kTWMax) > 160 * 1024) return kTW;
+  // Wide strips halve the halo columns each workgroup modulates and filters
+  // but hold more registers and LDS per wave.  Measured at 4096^2, K = 32,
+  // every radius: they ran 3-13% faster wherever they kept at least three
+  // quarters of the narrow strips' resident waves (also at 16 of 20 waves
+  // with 16-bit storage), and 4.8% slower at FP32, R = 18 (8 of 12 waves).
+  const int narrow_waves = fused_blocks_per_cu(d, R, prec, kTW) * (d + 1);
+  const int wide_waves = fused_blocks_per_cu(d, R, prec, kTWMax) * 2 * (d + 1);
+  return 4 * wide_waves >= 3 * narrow_waves ? kTWMax : kTW;
 }
 
 // ---------------------------------------------------------------------------
@@ -118,43 +140,44 @@ int fused_blocks_per_cu(int d, int R, int prec) {
 
 namespace {
 std::mutex g_tuned_mu;
-std::map<std::array<int, 6>, int> g_tuned;  // (device, d, R, precision, H, W) -> strip height
+// (device, d, R, precision, H, W, strip width) -> strip height
+std::map<std::array<int, 7>, int> g_tuned;
 }  // namespace
 
-void record_tuned_height(int d, int R, int prec, int H, int W, int TH) {
+void record_tuned_height(int d, int R, int prec, int H, int W, int TH, int TW) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tuned_mu);
-  g_tuned[{dev, d, R, prec, H, W}] = TH;
+  g_tuned[{dev, d, R, prec, H, W, TW}] = TH;
 }
 
-int tuned_height(int d, int R, int prec, int H, int W) {
+int tuned_height(int d, int R, int prec, int H, int W, int TW) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tuned_mu);
-  auto it = g_tuned.find({dev, d, R, prec, H, W});
+  auto it = g_tuned.find({dev, d, R, prec, H, W, TW});
   return it == g_tuned.end() ? 0 : it->second;
 }
 
-int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH) {
-  if (fused_lds_bytes(d, R, prec) > 160 * 1024)
+int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH, int TW) {
+  if (fused_lds_bytes(d, R, prec, TW) > 160 * 1024)
     return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
   if (requested > 0) {
     *TH = (requested + kB - 1) / kB * kB;
     return BF_OK;
   }
-  if ((*TH = tuned_height(d, R, prec, H, W)) > 0) return BF_OK;
-  *TH = model_strip_height(d, R, prec, H, W);
+  if ((*TH = tuned_height(d, R, prec, H, W, TW)) > 0) return BF_OK;
+  *TH = model_strip_height(d, R, prec, H, W, TW);
   return BF_OK;
 }
 
-int model_strip_height(int d, int R, int prec, int H, int W) {
-  const int nsx = (W + kTW - 1) / kTW;
+int model_strip_height(int d, int R, int prec, int H, int W, int TW) {
+  const int nsx = (W + TW - 1) / TW;
   // resident workgroups on the GPU
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int slots = fused_blocks_per_cu(d, R, prec) * std::max(ncu, 1);
+  const int slots = fused_blocks_per_cu(d, R, prec, TW) * std::max(ncu, 1);
   const int halo = lag_steps(R) * kB;
   // The accumulators of the resident workgroups are read and written once
   // per term.  On the 4096^2 workload, strips half as tall (two waves of
@@ -168,7 +191,7 @@ int model_strip_height(int d, int R, int prec, int H, int W) {
     const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
     const long nwg = (long)nsx * ((H + th - 1) / th);
     const long waves = (nwg + slots - 1) / slots;
-    const double resident = (double)std::min<long>(nwg, slots) * th * kTW * (d + 1) * 4.0;
+    const double resident = (double)std::min<long>(nwg, slots) * th * TW * (d + 1) * 4.0;
     const double cost = (double)waves * (th + halo) * (resident > kCacheShare ? 1.1 : 1.0);
     if (best < 0 || cost < best) {
       best = cost;

@@ -63,12 +63,12 @@ namespace bfvec {
 
 namespace {
 
-template <int D>
+template <int D, int TW = kTW>
 struct Geo {
   static constexpr int NP = D + 1;   // channel pairs (d numerators + Z)
   static constexpr int NC = 2 * NP;  // real channels
-  static constexpr int NT = 64 * NP; // threads per workgroup
-  static constexpr int MI = (kB * kSWMax + NT - 1) / NT;  // modulation slots
+  static constexpr int NT = 64 * NP * (TW / 16);  // threads per workgroup
+  static constexpr int MI = (kB * stage_width(kRMax, TW) + NT - 1) / NT;  // modulation slots
 };
 
 __device__ __forceinline__ int wrap(int r, int n) { return r >= n ? r - n : r; }
@@ -342,12 +342,13 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // a.t0 .. a.t1-1 (Algorithm 1's term loop over one strip).
 // RC: window radius fixed at compile time, or -1 for a runtime radius.
 // PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
-template <int D, int RC, int PREC, bool P64>
+template <int D, int RC, int PREC, bool P64, int TW = kTW>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
-  using G = Geo<D>;
+  static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
+  using G = Geo<D, TW>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
-  constexpr int TW = kTW, B = kB;
+  constexpr int B = kB;
   constexpr int RST = NC * TW;       // ring row stride: [ch][x]
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
@@ -358,8 +359,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int R = RC >= 0 ? RC : a.R;
-  const int SW = RC >= 0 ? (LP ? stage_width16(RC) : stage_width(RC)) : a.SW;
-  const int MW = RC >= 0 ? kTW + 2 * RC : SW;   // modulated columns per staging row
+  const int SW = RC >= 0 ? (LP ? stage_width16(RC, TW) : stage_width(RC, TW)) : a.SW;
+  const int MW = RC >= 0 ? TW + 2 * RC : SW;   // modulated columns per staging row
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
   const int tapp_al = (R + 1 + 3) / 4 * 4;
@@ -423,15 +424,27 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // pass 1 item: 4-column block xq, channel ch, row rr of the step.  xq varies
   // fastest across lanes: the items' 128-bit ring writes then cover contiguous
   // LDS (a channel-fastest order measured a 7-way bank conflict on them).
-  const int p1_xq = tid % 4;
-  const int p1_ch = (tid / 4) % NC;
-  const int p1_rr = tid / (4 * NC);
-  // pass 2 item: column x, cos/sin half k, pair m, 4-row group g
-  const int p2_x = tid & 15;
-  const int p2_k = (tid >> 4) & 1;
-  const int p2_m = (tid >> 5) % NP;
-  int p2_g = (tid >> 5) / NP;
-  if constexpr (NP % 2 == 0) p2_g = __builtin_amdgcn_readfirstlane(p2_g);
+  // Wide strips: 8 blocks x 4 channels x a row pair per wave, the pair's rows
+  // in lanes l and l + 32 (as for d = 3 in 16-column strips).
+  int p1_xq, p1_ch, p1_rr;
+  if constexpr (TW == 16) {
+    p1_xq = tid % 4;
+    p1_ch = (tid / 4) % NC;
+    p1_rr = tid / (4 * NC);
+  } else {
+    const int wv = tid >> 6;
+    p1_xq = tid % 8;
+    p1_ch = (wv % (NC / 4)) * 4 + (tid / 8) % 4;
+    p1_rr = 2 * (wv / (NC / 4)) + ((tid >> 5) & 1);
+  }
+  // pass 2 item: column x, cos/sin half k, pair m, 4-row group g (the cos and
+  // sin halves of a column in lanes TW apart)
+  constexpr int LTW = TW == 16 ? 4 : 5;
+  const int p2_x = tid & (TW - 1);
+  const int p2_k = (tid >> LTW) & 1;
+  const int p2_m = (tid >> (LTW + 1)) % NP;
+  int p2_g = (tid >> (LTW + 1)) / NP;
+  if constexpr (NP % 2 == 0 || TW == 32) p2_g = __builtin_amdgcn_readfirstlane(p2_g);
   const int p2_ch = 2 * p2_m + p2_k;
   // accumulators: planar [m][Hp][Wp] padded to whole strips, so every lane
   // owns valid storage; 32-bit element offsets from the (uniform) base
@@ -583,7 +596,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         hpass_lp<PREC, RC>(src, tpe, tpo, s_te, s_to, R, acc);
         // row r goes to the low (even r) or high (odd r) half of pair-row r/2
         const int r = rslot + p1_rr;
-        if constexpr (4 * NC == 32) {
+        if constexpr ((TW == 16 && 4 * NC == 32) || TW == 32) {
           // rows 2w and 2w+1 of this item sit in lanes l and l+32: swap halves so
           // the lower lanes hold both rows of columns 2,3 and the upper lanes
           // both rows of columns 0,1, then write one packed 64-bit chunk each
@@ -690,8 +703,13 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         // side); likewise q[1], q[3] for rows 2k + 1.
         unsigned e0 = __builtin_bit_cast(unsigned, q[0]), e2 = __builtin_bit_cast(unsigned, q[2]);
         unsigned e1 = __builtin_bit_cast(unsigned, q[1]), e3 = __builtin_bit_cast(unsigned, q[3]);
-        swap_rows16(e0, e2);
-        swap_rows16(e1, e3);
+        if constexpr (TW == 16) {
+          swap_rows16(e0, e2);
+          swap_rows16(e1, e3);
+        } else {   // halves 32 lanes apart: the same exchange across wave halves
+          swap_halves(e0, e2);
+          swap_halves(e1, e3);
+        }
         const float v0 = __builtin_bit_cast(float, e0) + __builtin_bit_cast(float, e2);
         const float v1 = __builtin_bit_cast(float, e1) + __builtin_bit_cast(float, e3);
         const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
@@ -748,9 +766,9 @@ __device__ __forceinline__ int xcd_order(int bid, int n) {
 // One request: one workgroup per strip.  P64: instance with the FP64 phase
 // path (its branches cost the common path a few percent, so launches whose
 // phases are bounded below 2^8 turns use the instance without it).
-template <int D, int RC, int PREC, bool P64>
-__global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused(FusedArgs a) {
-  fused_strip<D, RC, PREC, P64>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
+template <int D, int RC, int PREC, bool P64, int TW = kTW>
+__global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused(FusedArgs a) {
+  fused_strip<D, RC, PREC, P64, TW>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
 }
 
 // Several requests of the same instance in one launch (continuous batching):
@@ -765,23 +783,35 @@ __global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_batch(BatchArgs g) {
 
 
 // One instance's launch: A is FusedArgs (one request) or BatchArgs.
+// Instances with wide strips: d = 3 with a compile-time radius, variants
+// 0-2, without the FP64 phase path (choose_strip_width selects them).
+template <int D, int RC, int PREC>
+inline constexpr bool kHasWide = D == 3 && RC >= 0 && PREC <= 2;
+
 template <int D, int RC, int PREC, class A>
 static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
-  const size_t lds = fused_lds_bytes(D, R, PREC);
-  int nwg;
+  int nwg, TW = kTW;
   void (*kern)(A);
-  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64
+  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64; 16-column strips
     kern = a.req[0].p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
     nwg = a.first[a.n];
   } else {
     kern = a.p64 ? mcsf_fused<D, RC, PREC, true> : mcsf_fused<D, RC, PREC, false>;
+    if constexpr (kHasWide<D, RC, PREC>) {
+      if (a.TWc == kTWMax && !a.p64) {
+        kern = mcsf_fused<D, RC, PREC, false, kTWMax>;
+        TW = kTWMax;
+      }
+    }
+    if (a.TWc != TW) return hipErrorInvalidValue;   // no instance for this width
     nwg = a.nsx * a.nsy;
   }
+  const size_t lds = fused_lds_bytes(D, R, PREC, TW);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (nwg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(nwg), dim3(64 * (D + 1)), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(64 * (D + 1) * (TW / 16)), lds, st, a);
   return hipGetLastError();
 }
 

@@ -81,7 +81,7 @@ hipError_t record_steps(bf_plan* p, const float* f, float* out) {
     fa.H = p->H;
     fa.W = p->W;
     fa.Hp = a.Hp;
-    fa.Wp = a.nsx * kTW;
+    fa.Wp = a.nsx * a.TWc;
     e = launch_finalize(p->d, fa, p->cap);
   }
   return e;
@@ -202,6 +202,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   o->N_used = N;
   o->K_used = Kr;
   o->tile_h_used = a.TH;
+  o->tile_w_used = a.TWc;
   *plan = p;
   return BF_OK;
 }

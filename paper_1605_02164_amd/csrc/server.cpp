@@ -376,7 +376,7 @@ struct Server {
         fa.H = r->in.H;
         fa.W = r->in.W;
         fa.Hp = r->a.Hp;
-        fa.Wp = r->a.nsx * kTW;
+        fa.Wp = r->a.nsx * r->a.TWc;
         e = launch_finalize(r->in.d, fa, st);
         if (e == hipSuccess) e = hipEventRecord(r->ev_done, st);
         if (e != hipSuccess) {
