@@ -102,11 +102,14 @@ typedef struct bf_opts {
   int spatial;     /* BF_SPATIAL_* (default BF_SPATIAL_GAUSS), optionally
                       | BF_SPATIAL_RUNSUM with a box filter and BF_FP32       */
   int whiten;      /* BF_WHITEN_* (default BF_WHITEN_EIG)                      */
-  int tile_w_used; /* OUT: strip width in columns the fused kernel ran with:
-                      32 for d = 3 at the radii with compile-time kernels
-                      (3 sigma_s in {6, 9, ..., 24, 30}) when the FP32/FP16/
-                      BF16 variant runs without the FP64 phase path, W >= 32
-                      and occupancy allows; else 16.  Same output bits.       */
+  int tile_w;      /* strip width in columns: 0 = automatic (default), 16, or
+                      32.  32 needs d = 3, a window radius with a compile-time
+                      kernel (6, 9, 12, 15, 18, 21, 24 or 30: the Gaussian's
+                      3 sigma_s), BF_FP32/FP16/BF16 without BF_SPATIAL_RUNSUM,
+                      and W >= 32 (else BF_EUNSUPPORTED); automatic picks 32
+                      there unless it cuts resident waves per CU below 3/4.
+                      The width changes no output bit.                        */
+  int tile_w_used; /* OUT: strip width the fused kernel ran with (16 or 32)   */
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,

@@ -81,6 +81,7 @@ class bf_opts(ctypes.Structure):
         ("tile_h_used", ctypes.c_int),
         ("spatial", ctypes.c_int),
         ("whiten", ctypes.c_int),
+        ("tile_w", ctypes.c_int),
         ("tile_w_used", ctypes.c_int),
     ]
 
@@ -237,7 +238,7 @@ def _check_image(f, out):
 
 def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
               num_out=None, z_out=None, time_kernel=False, dedup=False, spatial="gauss",
-              whiten="eig"):
+              whiten="eig", tile_w=0):
     o = bf_opts()
     lib().bf_opts_init(ctypes.byref(o))
     o.N = int(N)
@@ -251,6 +252,7 @@ def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
     o.dedup = 1 if dedup else 0
     o.spatial = _spatial(spatial)
     o.whiten = _whiten_mode(whiten)
+    o.tile_w = int(tile_w)
     return o
 
 
@@ -273,25 +275,26 @@ def bf_vec(f, sigma_s, C, K, seed, out=None):
 
 def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
               tile_h=0, stream=None, num_out=None, z_out=None, time_kernel=False,
-              return_opts=False, dedup=False, spatial="gauss", whiten="eig"):
+              return_opts=False, dedup=False, spatial="gauss", whiten="eig", tile_w=0):
     """The filter with options, queued on ``stream`` (torch stream; default:
     current stream).  Returns (out, N_used), or (out, opts) with
     ``return_opts`` (opts.kernel_ms holds the fused-kernel time when
     ``time_kernel`` is set; opts.K_used the number of kernel terms, fewer than
-    K with ``dedup``).  ``spatial``: "gauss" (default), "box", "hat", "box3";
-    ``whiten``: "eig" (default), "chol", "sym"."""
+    K with ``dedup``; opts.tile_h_used / tile_w_used the strip shape).
+    ``spatial``: "gauss" (default), "box", "hat", "box3"; ``whiten``: "eig"
+    (default), "chol", "sym"; ``tile_w``: strip width 0 (auto), 16 or 32."""
     out = _check_image(f, out)
     H, W, d = f.shape
     Ch = _host_f64(C, (d, d))
     o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  time_kernel, dedup, spatial, whiten)
+                  time_kernel, dedup, spatial, whiten, tile_w)
     _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
     return (out, o) if return_opts else (out, o.N_used)
 
 
 def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center=True,
-                 tile_h=0, stream=None, num_out=None, z_out=None, spatial="gauss"):
+                 tile_h=0, stream=None, num_out=None, z_out=None, spatial="gauss", tile_w=0):
     """The filter with an explicit (K, d) float64 term table and optional
     weights.  Returns out."""
     out = _check_image(f, out)
@@ -302,7 +305,7 @@ def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center
     K = wh.shape[0]
     wt = None if weights is None else _host_f64(weights, (K,))
     o = make_opts(0, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  spatial=spatial)
+                  spatial=spatial, tile_w=tile_w)
     _check(lib().bf_vec_terms(f.data_ptr(), H, W, d, float(sigma_s), _ptr(wh),
                               None if wt is None else _ptr(wt), K, out.data_ptr(),
                               ctypes.byref(o)))
@@ -380,10 +383,10 @@ class Plan:
     HIP graph launch per image.  ``N`` must be explicit."""
 
     def __init__(self, H, W, d, sigma_s, C, K, seed, N, precision="fp32", center=True,
-                 tile_h=0, dedup=False, spatial="gauss", whiten="eig"):
+                 tile_h=0, dedup=False, spatial="gauss", whiten="eig", tile_w=0):
         Ch = _host_f64(C, (d, d))
         o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup, spatial,
-                      whiten)
+                      whiten, tile_w)
         h = ctypes.c_void_p()
         _check(lib().bf_plan_create(int(H), int(W), int(d), float(sigma_s), _ptr(Ch), int(K),
                                     int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(o),

@@ -149,6 +149,8 @@ int check_opts(const bf_opts* o) {
     return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16 or BF_BF16");
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
+  if (o->tile_w != 0 && o->tile_w != kTW && o->tile_w != kTWMax)
+    return fail(BF_EINVAL, "opts.tile_w must be 0 (auto), 16 or 32");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
   if (o->whiten < BF_WHITEN_EIG || o->whiten > BF_WHITEN_SYM)
     return fail(BF_EINVAL, "opts.whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
@@ -287,18 +289,20 @@ void distinct_terms(int d, const double* Wm, int N, int K, uint64_t seed, std::v
 namespace {
 
 // Checks that need no device work: window size, precision, strip height.
-int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH) {
+int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH, int* TW) {
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
-  const int rc = check_fused_size(H, W, W, d, R);
+  int rc = check_fused_size(H, W, W, d, R);
   if (rc) return rc;
-  return choose_strip_height(d, R, kernel_variant(o->precision, o->spatial), H, W, o->tile_h, TH);
+  const int v = kernel_variant(o->precision, o->spatial);
+  if ((rc = choose_strip_width(d, R, v, W, o->tile_w, TW))) return rc;
+  return choose_strip_height(d, R, v, H, W, o->tile_h, TH, *TW);
 }
 
 // Launch the fused filter for a host FP64 term table (radians per unit).
 // lo/hi: per-channel extrema when known (min/max ran), else null.
 int run_terms(const float* f, int H, int W, int d, double sigma_s, const double* w,
               const double* weights, int K, float* out, bf_opts* o, const float* lo,
-              const float* hi, int TH) {
+              const float* hi, int TH, int TW) {
   hipStream_t st = (hipStream_t)o->stream;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int variant = kernel_variant(o->precision, o->spatial);
@@ -312,13 +316,6 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
     a.cen[m] = (o->center && lo && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
   table_wmax(d, K, hbuf.data(), a.wmax);
   a.p64 = phase64_flag(d, a.wmax, a.cen, lo, hi);
-  // the strip width depends on the phase path; a width other than kTW has
-  // its own strip height unless the caller fixed one
-  const int TW = choose_strip_width(d, R, variant, a.p64, W);
-  if (TW != kTW && o->tile_h <= 0) {
-    const int rc = choose_strip_height(d, R, variant, H, W, 0, &TH, TW);
-    if (rc) return rc;
-  }
   fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0, TW);
   a.fpitch = W;
   a.t0 = 0;
@@ -453,8 +450,8 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   if ((rc = check_opts(o))) return rc;
   double Wm[64];
   if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
-  int TH = 0;
-  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH))) return rc;
+  int TH = 0, TW = 0;
+  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
   float lo[8] = {0}, hi[8] = {0};
   const bool have_range = o->N == 0 || o->center;
   if (have_range) {
@@ -468,13 +465,13 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
     distinct_terms(d, Wm, N, K, seed, &w, &weight);
     o->K_used = (int)weight.size();
     return run_terms(f, H, W, d, sigma_s, w.data(), weight.data(), o->K_used, out, o,
-                     have_range ? lo : nullptr, have_range ? hi : nullptr, TH);
+                     have_range ? lo : nullptr, have_range ? hi : nullptr, TH, TW);
   }
   std::vector<double> w((size_t)K * d);
   frequency_table(d, Wm, N, K, seed, w.data());
   o->K_used = K;
   return run_terms(f, H, W, d, sigma_s, w.data(), nullptr, K, out, o,
-                   have_range ? lo : nullptr, have_range ? hi : nullptr, TH);
+                   have_range ? lo : nullptr, have_range ? hi : nullptr, TH, TW);
 }
 
 int bf_vec(const float* f, int H, int W, int d, double sigma_s, const double* C, int K,
@@ -507,14 +504,14 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const doub
     for (int t = 0; t < K; ++t)
       if (!(weights[t] >= 0.0) || !std::isfinite(weights[t]))
         return fail(BF_EINVAL, "weights must be finite and nonnegative");
-  int TH = 0;
-  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH))) return rc;
+  int TH = 0, TW = 0;
+  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
   float lo[8] = {0}, hi[8] = {0};
   if (o->center && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   o->N_used = o->N;
   o->K_used = K;
   return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, o->center ? lo : nullptr,
-                   o->center ? hi : nullptr, TH);
+                   o->center ? hi : nullptr, TH, TW);
 }
 
 int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precision, void* stream,
@@ -530,8 +527,8 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   int TH0 = 0;   // validates the window against the LDS budget
   if ((rc = choose_strip_height(d, R, precision, H, W, 0, &TH0))) return rc;
   (void)TH0;
-  // the probes run without the FP64 phase path, at that path's strip width
-  const int TW = choose_strip_width(d, R, precision, 0, W);
+  int TW = kTW;   // the probes run at the automatic strip width
+  if ((rc = choose_strip_width(d, R, precision, W, 0, &TW))) return rc;
   const int model = model_strip_height(d, R, precision, H, W, TW);
   // candidate strip counts down the image around the model's
   const int nsy0 = (H + model - 1) / model, nmax = (H + kB - 1) / kB;

@@ -118,11 +118,14 @@ struct FinalizeArgs {
 size_t fused_lds_bytes(int d, int R, int prec, int TW = kTW);
 // resident workgroups per compute unit for this kernel instance (device query)
 int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW);
-// Strip width for a launch: kTWMax where a wide-strip instance exists (d = 3,
-// a specialised radius, variants 0-2, no FP64 phase path, W >= kTWMax) and
-// keeps at least three quarters of the waves per CU resident that kTW strips
-// keep; else kTW.
-int choose_strip_width(int d, int R, int prec, int p64, int W);
+// Strip width for a launch into *TW.  requested: kTW or kTWMax forces it
+// (kTWMax needs a wide-strip instance: d = 3, a specialised radius, variants
+// 0-2, W >= kTWMax; else BF_EUNSUPPORTED); 0 picks kTWMax where such an
+// instance exists, fits the LDS and keeps at least three quarters of the
+// waves per CU resident that kTW strips keep, else kTW.
+int choose_strip_width(int d, int R, int prec, int W, int requested, int* TW);
+// The occupancy rule alone, for an instance that has both widths.
+int model_strip_width(int d, int R, int prec);
 hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st);
 // All requests of b share d, R and prec (and hence LDS size and staging width).
 hipError_t launch_fused_batch(int d, int R, int prec, const BatchArgs& b, hipStream_t st);

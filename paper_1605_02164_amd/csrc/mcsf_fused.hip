@@ -117,9 +117,22 @@ int fused_blocks_per_cu(int d, int R, int prec, int TW) {
   }
 }
 
-int choose_strip_width(int d, int R, int prec, int p64, int W) {
-  if (d != 3 || prec > 2 || p64 || W < kTWMax || !specialised_radius(R)) return kTW;
-  if (fused_lds_bytes(d, R, prec, kTWMax) > 160 * 1024) return kTW;
+int choose_strip_width(int d, int R, int prec, int W, int requested, int* TW) {
+  const bool wide_ok = d == 3 && prec <= 2 && W >= kTWMax && specialised_radius(R) &&
+                       fused_lds_bytes(d, R, prec, kTWMax) <= 160 * 1024;
+  if (requested == kTWMax && !wide_ok)
+    return fail(BF_EUNSUPPORTED,
+                "32-column strips need d = 3, a window radius with a compile-time kernel "
+                "(6, 9, ..., 24 or 30), FP32/FP16/BF16 without the running-sum pass, and W >= 32");
+  if (requested == kTW || requested == kTWMax) {
+    *TW = requested;
+    return BF_OK;
+  }
+  *TW = wide_ok ? model_strip_width(d, R, prec) : kTW;
+  return BF_OK;
+}
+
+int model_strip_width(int d, int R, int prec) {
   // Wide strips halve the halo columns each workgroup modulates and filters
   // but hold more registers and LDS per wave.  Measured at 4096^2, K = 32,
   // every radius: they ran 3-13% faster wherever they kept at least three

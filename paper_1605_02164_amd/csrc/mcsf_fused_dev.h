@@ -765,7 +765,8 @@ __device__ __forceinline__ int xcd_order(int bid, int n) {
 
 // One request: one workgroup per strip.  P64: instance with the FP64 phase
 // path (its branches cost the common path a few percent, so launches whose
-// phases are bounded below 2^8 turns use the instance without it).
+// phases are bounded below 2^8 turns use the instance without it).  TW: strip
+// width, 16 columns (D+1 waves) or 32 (2(D+1) waves).
 template <int D, int RC, int PREC, bool P64, int TW = kTW>
 __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused(FusedArgs a) {
   fused_strip<D, RC, PREC, P64, TW>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
@@ -773,18 +774,18 @@ __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused(FusedArgs
 
 // Several requests of the same instance in one launch (continuous batching):
 // the workgroup finds its request in the prefix table.
-template <int D, int RC, int PREC, bool P64>
-__global__ __launch_bounds__(64 * (D + 1)) void mcsf_fused_batch(BatchArgs g) {
+template <int D, int RC, int PREC, bool P64, int TW = kTW>
+__global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused_batch(BatchArgs g) {
   const int bid = xcd_order(blockIdx.x, g.first[g.n]);
   int i = 0;
   while (i + 1 < g.n && bid >= g.first[i + 1]) ++i;
-  fused_strip<D, RC, PREC, P64>(g.req[i], bid - g.first[i]);
+  fused_strip<D, RC, PREC, P64, TW>(g.req[i], bid - g.first[i]);
 }
 
 
 // One instance's launch: A is FusedArgs (one request) or BatchArgs.
-// Instances with wide strips: d = 3 with a compile-time radius, variants
-// 0-2, without the FP64 phase path (choose_strip_width selects them).
+// Instances with wide strips: d = 3 with a compile-time radius, variants 0-2
+// (choose_strip_width selects them).
 template <int D, int RC, int PREC>
 inline constexpr bool kHasWide = D == 3 && RC >= 0 && PREC <= 2;
 
@@ -792,14 +793,25 @@ template <int D, int RC, int PREC, class A>
 static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
   int nwg, TW = kTW;
   void (*kern)(A);
-  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64; 16-column strips
-    kern = a.req[0].p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
+  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64 and the strip width
+    const bool p64 = a.req[0].p64;
+    for (int k = 1; k < a.n; ++k)
+      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc) return hipErrorInvalidValue;
+    kern = p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
+    if constexpr (kHasWide<D, RC, PREC>) {
+      if (a.req[0].TWc == kTWMax) {
+        kern = p64 ? mcsf_fused_batch<D, RC, PREC, true, kTWMax>
+                   : mcsf_fused_batch<D, RC, PREC, false, kTWMax>;
+        TW = kTWMax;
+      }
+    }
+    if (a.req[0].TWc != TW) return hipErrorInvalidValue;   // no instance for this width
     nwg = a.first[a.n];
   } else {
     kern = a.p64 ? mcsf_fused<D, RC, PREC, true> : mcsf_fused<D, RC, PREC, false>;
     if constexpr (kHasWide<D, RC, PREC>) {
-      if (a.TWc == kTWMax && !a.p64) {
-        kern = mcsf_fused<D, RC, PREC, false, kTWMax>;
+      if (a.TWc == kTWMax) {
+        kern = a.p64 ? mcsf_fused<D, RC, PREC, true, kTWMax> : mcsf_fused<D, RC, PREC, false, kTWMax>;
         TW = kTWMax;
       }
     }

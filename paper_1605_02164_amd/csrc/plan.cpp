@@ -144,8 +144,9 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int variant = kernel_variant(o->precision, o->spatial);
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;
-  int TH = 0;
-  if ((rc = choose_strip_height(d, R, variant, H, W, o->tile_h, &TH))) return rc;
+  int TH = 0, TW = 0;
+  if ((rc = choose_strip_width(d, R, variant, W, o->tile_w, &TW))) return rc;
+  if ((rc = choose_strip_height(d, R, variant, H, W, o->tile_h, &TH, TW))) return rc;
 
   // the terms, exactly as bf_vec_ex draws them
   const int N = o->N;
@@ -170,7 +171,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   p->variant = variant;
   p->center = o->center;
   FusedArgs& a = p->a;
-  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0);
+  fused_geometry(a, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0, TW);
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = Kr;

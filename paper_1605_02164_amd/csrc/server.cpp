@@ -56,9 +56,9 @@ constexpr int kMMFloats = 17;  // min/max partial block: 8 minima, 8 maxima, fla
 // rate.  Only ratios between requests matter for the chunking.
 double model_term_us(const FusedArgs& a, int d, int prec) {
   const double NC = 2.0 * (d + 1), taps = 2.0 * a.R + 1.0;
-  const double mod = (double)kB * (kTW + 2 * a.R) * (4.0 * d + 2.0);
-  const double one = (double)kB * NC * kTW * taps * 2.0;   // one FIR pass, FP32
-  const double pass = prec == 3 ? one + (double)kB * NC * kTW * 8.0
+  const double mod = (double)kB * (a.TWc + 2 * a.R) * (4.0 * d + 2.0);
+  const double one = (double)kB * NC * a.TWc * taps * 2.0;   // one FIR pass, FP32
+  const double pass = prec == 3 ? one + (double)kB * NC * a.TWc * 8.0
                                 : 2.0 * one * (prec == BF_FP32 ? 1.0 : 0.5);
   const double per_step = mod + pass;
   const double flops = per_step * a.steps * (double)a.nsx * a.nsy;
@@ -70,7 +70,7 @@ struct Req {
   bf_request in{};
   double Cm[64] = {0};
   double Wm[64] = {0};
-  int R = 0, variant = 0, stream = 0;   // variant: the server's instance id (d, R, kvar, p64)
+  int R = 0, variant = 0, stream = 0;   // variant: the server's instance id (d, R, kvar, p64, TW)
   int kvar = 0;                         // kernel variant (precision, running-sum box pass)
   FusedArgs a{};
   size_t n_acc = 0, n_tab = 0, off_w = 0, off_taps = 0;
@@ -109,7 +109,8 @@ struct Server {
   std::condition_variable cv_work, cv_done;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   std::deque<Req*> incoming;
-  std::map<std::tuple<int, int, int, int>, int> variants;  // (d, R, kernel variant, p64) -> id
+  // (d, R, kernel variant, p64, strip width) -> id
+  std::map<std::tuple<int, int, int, int, int>, int> variants;
   uint64_t next_ticket = 1;
   bool stop = false;
   int queued = 0, admitted = 0;
@@ -201,9 +202,9 @@ struct Server {
     table_wmax(d, K, tab.data(), r->a.wmax);
     r->a.p64 = phase64_flag(d, r->a.wmax, r->a.cen, r->need_minmax ? lo : nullptr,
                             r->need_minmax ? hi : nullptr);
-    {  // kernel instance (d, R, variant, FP64-phase path): its id picks the stream
+    {  // kernel instance (d, R, variant, FP64-phase path, strip width): its id picks the stream
       std::lock_guard<std::mutex> lk(mu);
-      const auto key = std::make_tuple(d, r->R, r->kvar, r->a.p64);
+      const auto key = std::make_tuple(d, r->R, r->kvar, r->a.p64, r->a.TWc);
       auto it = variants.find(key);
       if (it == variants.end()) it = variants.emplace(key, (int)variants.size()).first;
       r->variant = it->second;
@@ -598,19 +599,20 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   r->R = window_radius(in.sigma_s, spatial_boxes(in.spatial));
   r->kvar = kernel_variant(in.precision, in.spatial);
   if ((rc = check_fused_size(in.H, in.W, in.pitch, in.d, r->R))) return rc;
-  int TH = 0;
+  int TH = 0, TW = 0;
   {
     // occupancy queries need the server's device current on this thread
     int cur = 0;
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != s->device) e = hipSetDevice(s->device);
     if (e != hipSuccess) return hip_err(e, "hipSetDevice");
-    rc = choose_strip_height(in.d, r->R, r->kvar, in.H, in.W, 0, &TH);
+    rc = choose_strip_width(in.d, r->R, r->kvar, in.W, 0, &TW);
+    if (!rc) rc = choose_strip_height(in.d, r->R, r->kvar, in.H, in.W, 0, &TH, TW);
     if (cur != s->device) (void)hipSetDevice(cur);
     if (rc) return rc;
   }
   fused_geometry(r->a, in.H, in.W, r->R, r->kvar, TH,
-                 r->kvar == 3 ? spatial_boxes(in.spatial) : 0);
+                 r->kvar == 3 ? spatial_boxes(in.spatial) : 0, TW);
   r->a.f = in.f;
   r->a.fpitch = in.pitch;
   r->n_acc = fused_acc_floats(r->a, in.d);

@@ -207,6 +207,24 @@ def test_spatial_option_validation_before_device_work():
         B._spatial("box3+fast")
 
 
+def test_strip_width_validation_before_device_work():
+    L = P.lib()
+
+    def vec(tile_w, d=3, W=64, sigma=3.0, precision="fp32", spatial="gauss"):
+        o = B.make_opts(precision=precision, spatial=spatial, tile_w=tile_w)
+        Ch = np.eye(d) * 0.01
+        return L.bf_vec_ex(0x1000, 40, W, d, sigma, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                           0x10000000, ctypes.byref(o))
+
+    assert vec(7) == B.BF_EINVAL                                   # not 0, 16 or 32
+    assert vec(-16) == B.BF_EINVAL
+    assert vec(32, d=4) == B.BF_EUNSUPPORTED                       # d = 3 only
+    assert vec(32, W=31) == B.BF_EUNSUPPORTED                      # narrower than a strip
+    assert vec(32, sigma=2.5) == B.BF_EUNSUPPORTED                 # R = 8: runtime radius
+    assert vec(32, spatial="box3+runsum") == B.BF_EUNSUPPORTED     # running-sum variant
+    assert b"32-column" in L.bf_last_error()
+
+
 @pytest.mark.parametrize("mode", ["chol", "sym"])
 @pytest.mark.parametrize("d,seed", [(2, 11), (3, 12), (6, 13), (8, 14)])
 def test_whitening_modes_match_oracle(mode, d, seed):
