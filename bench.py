@@ -35,14 +35,14 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "18b25fbb896e982dbe535ae3cc2eca9ef710047de63c1f60ffbb20035cfc3e1d",
-    "fp32": {"fetch_kib": 92901649, "write_kib": 67527142,
+    "sha256": "9727fb58977baf4e459919f5fb9adb85d8a891e3b0fbaf15e457424254b6f2e9",
+    "fp32": {"fetch_kib": 87857081, "write_kib": 67108864,
              # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
-             "executed_flops": 142493114368 * 64},
-    "fp16": {"fetch_kib": 147122033, "write_kib": 70242442,
+             "executed_flops": 140068806656 * 64},
+    "fp16": {"fetch_kib": 89291650, "write_kib": 67108864,
              # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
-             "executed_flops": (145995333632 + 5494587392) * 64},
-    "fetch_factor": 1048576 / 524313.5625,
+             "executed_flops": (144183394304 + 3833643008) * 64},
+    "fetch_factor": 1048576 / 524306.6875,
     "write_factor": 1048576 / 1048576.0,
 }
 
