@@ -35,7 +35,7 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "9727fb58977baf4e459919f5fb9adb85d8a891e3b0fbaf15e457424254b6f2e9",
+    "sha256": "be4037b3b20761c360a7cff99e35d87fcb6673f965a6e4d9536fff5a4cb379e3",
     "fp32": {"fetch_kib": 87857081, "write_kib": 67108864,
              # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
              "executed_flops": 140068806656 * 64},

@@ -107,8 +107,10 @@ typedef struct bf_opts {
                       kernel (6, 9, 12, 15, 18, 21, 24 or 30: the Gaussian's
                       3 sigma_s), BF_FP32/FP16/BF16 without BF_SPATIAL_RUNSUM,
                       and W >= 32 (else BF_EUNSUPPORTED); automatic picks 32
-                      there unless it cuts resident waves per CU below 3/4.
-                      The width changes no output bit.                        */
+                      there unless it cuts resident waves per CU below 3/4 or
+                      the image is too small to fill the GPU (fewer than two
+                      16-column, 8-row strips per compute unit).  The width
+                      changes no output bit.                                  */
   int tile_w_used; /* OUT: strip width the fused kernel ran with (16 or 32)   */
 } bf_opts;
 

@@ -294,7 +294,7 @@ int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH, i
   int rc = check_fused_size(H, W, W, d, R);
   if (rc) return rc;
   const int v = kernel_variant(o->precision, o->spatial);
-  if ((rc = choose_strip_width(d, R, v, W, o->tile_w, TW))) return rc;
+  if ((rc = choose_strip_width(d, R, v, H, W, o->tile_w, TW))) return rc;
   return choose_strip_height(d, R, v, H, W, o->tile_h, TH, *TW);
 }
 
@@ -528,7 +528,7 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   if ((rc = choose_strip_height(d, R, precision, H, W, 0, &TH0))) return rc;
   (void)TH0;
   int TW = kTW;   // the probes run at the automatic strip width
-  if ((rc = choose_strip_width(d, R, precision, W, 0, &TW))) return rc;
+  if ((rc = choose_strip_width(d, R, precision, H, W, 0, &TW))) return rc;
   const int model = model_strip_height(d, R, precision, H, W, TW);
   // candidate strip counts down the image around the model's
   const int nsy0 = (H + model - 1) / model, nmax = (H + kB - 1) / kB;

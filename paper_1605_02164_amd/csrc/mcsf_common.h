@@ -121,9 +121,10 @@ int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW);
 // Strip width for a launch into *TW.  requested: kTW or kTWMax forces it
 // (kTWMax needs a wide-strip instance: d = 3, a specialised radius, variants
 // 0-2, W >= kTWMax; else BF_EUNSUPPORTED); 0 picks kTWMax where such an
-// instance exists, fits the LDS and keeps at least three quarters of the
-// waves per CU resident that kTW strips keep, else kTW.
-int choose_strip_width(int d, int R, int prec, int W, int requested, int* TW);
+// instance exists, fits the LDS, keeps at least three quarters of the waves
+// per CU resident that kTW strips keep, and the image is large enough that
+// kTW strips of kB rows would give at least two workgroups per CU; else kTW.
+int choose_strip_width(int d, int R, int prec, int H, int W, int requested, int* TW);
 // The occupancy rule alone, for an instance that has both widths.
 int model_strip_width(int d, int R, int prec);
 hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st);

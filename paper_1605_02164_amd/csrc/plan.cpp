@@ -145,7 +145,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   const int variant = kernel_variant(o->precision, o->spatial);
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;
   int TH = 0, TW = 0;
-  if ((rc = choose_strip_width(d, R, variant, W, o->tile_w, &TW))) return rc;
+  if ((rc = choose_strip_width(d, R, variant, H, W, o->tile_w, &TW))) return rc;
   if ((rc = choose_strip_height(d, R, variant, H, W, o->tile_h, &TH, TW))) return rc;
 
   // the terms, exactly as bf_vec_ex draws them

@@ -606,7 +606,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != s->device) e = hipSetDevice(s->device);
     if (e != hipSuccess) return hip_err(e, "hipSetDevice");
-    rc = choose_strip_width(in.d, r->R, r->kvar, in.W, 0, &TW);
+    rc = choose_strip_width(in.d, r->R, r->kvar, in.H, in.W, 0, &TW);
     if (!rc) rc = choose_strip_height(in.d, r->R, r->kvar, in.H, in.W, 0, &TH, TW);
     if (cur != s->device) (void)hipSetDevice(cur);
     if (rc) return rc;

@@ -2,7 +2,8 @@
 
 For d = 3 at the radii with compile-time kernels the fused kernel has
 instances with 32-column strips (eight waves per workgroup) beside the
-16-column ones; opts.tile_w forces a width (0 = automatic) and
+16-column ones; opts.tile_w forces a width (0 = automatic: 32 where such an
+instance exists, occupancy allows and the image fills the GPU) and
 opts.tile_w_used reports it.  Each output pixel is computed by the same
 operations in the same order at either width, so the two must agree bit for
 bit: in bf_vec_ex, in plans (one HIP graph each), in the serving scheduler's
@@ -102,37 +103,45 @@ def test_wide_strips_against_oracle(precision):
 
 
 def test_wide_strips_with_fp64_phase_path():
-    say("case strips 48x96x3 sigma_s=3, uncentred data near 3000 (FP64 phase path): "
+    say("case strips 256x320x3 sigma_s=3, uncentred data near 3000 (FP64 phase path): "
         "32 vs 16 columns")
     C = np.eye(3) * 0.1 ** 2
-    fg = cuda(voronoi_image(48, 96, 3, 6, 0.0, 1.0, 0.02, 4) + 3000.0)
+    fg = cuda(voronoi_image(256, 320, 3, 6, 0.0, 1.0, 0.02, 4) + 3000.0)
     narrow, _ = run(fg, 3.0, C, 6, 1, 12, "fp32", 16, center=False)
     wide, o = run(fg, 3.0, C, 6, 1, 12, "fp32", 0, center=False)
     assert o.tile_w_used == 32
     assert np.array_equal(wide, narrow)
 
 
-def test_automatic_width_is_narrow_without_a_wide_instance():
-    say("case strips: d = 4, W < 32, a radius without a compile-time kernel, the "
-        "running-sum variant -> 16 columns")
+def test_automatic_width():
+    say("case strips: automatic width -> 32 columns on a 256x320 image at R = 9, 16 for "
+        "d = 4, W < 32, a radius without a compile-time kernel, the running-sum variant, "
+        "an image too small to fill the GPU")
     C3 = np.eye(3) * 0.1 ** 2
-    f3 = voronoi_image(40, 20, 3, 6, 0.0, 1.0, 0.02, 3)
-    assert run(cuda(f3), 3.0, C3, 4, 1, 12, "fp32", 0)[1].tile_w_used == 16   # W < 32
-    f3 = voronoi_image(40, 64, 3, 6, 0.0, 1.0, 0.02, 4)
-    assert run(cuda(f3), 2.5, C3, 4, 1, 12, "fp32", 0)[1].tile_w_used == 16   # R = 8
-    _, o = run(cuda(f3), 3.0, C3, 4, 1, 12, "fp32", 0, spatial="box3+runsum")
-    assert o.tile_w_used == 16                                               # running sums
-    f4 = voronoi_image(40, 64, 4, 6, 0.0, 1.0, 0.02, 5)
-    _, o = run(cuda(f4), 3.0, np.eye(4) * 0.1 ** 2, 4, 1, 12, "fp32", 0)
-    assert o.tile_w_used == 16                                               # d = 4
+
+    def width(f, sigma, C, **kw):
+        return run(cuda(f), sigma, C, 2, 1, 12, "fp32", 0, **kw)[1].tile_w_used
+
+    f3 = voronoi_image(256, 320, 3, 6, 0.0, 1.0, 0.02, 4)
+    assert width(f3, 3.0, C3) == 32
+    assert width(f3, 2.5, C3) == 16                                    # R = 8
+    assert width(f3, 3.0, C3, spatial="box3+runsum") == 16             # running sums
+    f4 = voronoi_image(256, 320, 4, 6, 0.0, 1.0, 0.02, 5)
+    assert width(f4, 3.0, np.eye(4) * 0.1 ** 2) == 16                  # d = 4
+    f3 = voronoi_image(4096, 20, 3, 6, 0.0, 1.0, 0.02, 3)
+    assert width(f3, 3.0, C3) == 16                                    # W < 32
+    small = voronoi_image(128, 128, 3, 6, 0.0, 1.0, 0.02, 6)
+    assert width(small, 3.0, C3) == 16                                 # 8 x 16 strips
+    assert run(cuda(small), 3.0, C3, 2, 1, 12, "fp32", 32)[1].tile_w_used == 32
 
 
 def test_server_batches_bitwise_equal_to_narrow():
-    say("case strips: serving scheduler (automatic width, one term per round) vs "
-        "bf_vec_ex at 16 columns, three d = 3 requests")
+    say("case strips: serving scheduler (automatic width: 32 columns, one term per round) "
+        "vs bf_vec_ex at 16 columns, three d = 3 requests")
     C = np.eye(3) * 0.12 ** 2
-    imgs = [cuda(voronoi_image(64 + 8 * i, 90 + 20 * i, 3, 8, 0.0, 1.0, 0.02, 70 + i))
+    imgs = [cuda(voronoi_image(256 + 8 * i, 300 + 20 * i, 3, 8, 0.0, 1.0, 0.02, 70 + i))
             for i in range(3)]
+    assert run(imgs[0], 3.0, C, 8, 4, 14, "fp16", 0)[1].tile_w_used == 32
     refs = [run(g, 3.0, C, 8, 4, 14, "fp16", 16)[0] for g in imgs]
     with P.Server(quantum_us=1e-9) as srv:
         subs = [srv.submit(g, 3.0, C, 8, 4, N=14, precision="fp16") for g in imgs]
