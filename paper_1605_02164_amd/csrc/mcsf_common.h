@@ -40,6 +40,16 @@ inline constexpr int stage_width16(int R, int TW = kTW) {
   const int dw = (TW + 2 * R + 4 + 3) / 4 * 2;   // dwords, even (64-bit aligned rows)
   return 2 * (dw % 16 == 0 ? dw + 2 : dw);
 }
+// Staging row width of the matrix-core passes (32-column strips, 16-bit
+// storage): the banded product reads 16 + 16*ceil((16 + 2R)/16) samples per
+// row (two 16-column output blocks, k-blocks of 16; at least the TW + 2R
+// modulated ones), plus 4 so that the row stride is 2 mod 4 dwords: the 16
+// rows one operand read touches then fall on distinct LDS banks.
+inline constexpr int stage_width_mf(int R) { return 16 + 16 * ((16 + 2 * R + 15) / 16) + 4; }
+// Pair-row padding of the 16-bit ring for the matrix-core vertical pass, in
+// dwords: the four 16-lane groups of an operand read sit 2 pair-rows apart,
+// which a stride of 8 mod 32 dwords spreads over all banks.
+constexpr int kRingPadMF = 8;
 constexpr int kSWMax = stage_width(kRMax);
 // 2R rows of look-ahead, in steps of kB rows
 inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
@@ -82,6 +92,7 @@ struct FusedArgs {
   int steps, lag;        // steps per term, and 2R look-ahead in steps
   int vbox;              // variant 3: n of the n-fold box (R = n r); else 0
   int TWc;               // strip width: kTW, or kTWMax for the wide-strip instances
+  int mf;                // 1: 16-bit passes on the matrix cores (32-column strips)
   int p64;               // 1: instance with the FP64 phase path (phase bound unknown or
                          // above kPhaseBound), 0: without it
   float wmax[8];         // max_t |w_tm / 2pi| over the table's FP32 values
@@ -115,7 +126,7 @@ struct FinalizeArgs {
 // prec: the kernel variant (kernel_variant): 0 = FP32 channels, 1 = FP16
 // storage, 2 = BF16 storage (FP32 accumulation), 3 = FP32 with the
 // running-sum vertical pass; TW: strip width
-size_t fused_lds_bytes(int d, int R, int prec, int TW = kTW);
+size_t fused_lds_bytes(int d, int R, int prec, int TW = kTW, int mf = 0);
 // resident workgroups per compute unit for this kernel instance (device query)
 int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW);
 // Strip width for a launch into *TW.  requested: kTW or kTWMax forces it

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
 // Host-side launch helpers
 // ---------------------------------------------------------------------------
 
-size_t fused_lds_bytes(int d, int R, int prec, int TW) {
+size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
   const int NP = d + 1, NC = 2 * NP;
   const bool lp = prec == 1 || prec == 2, vb = prec == 3;
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
@@ -45,8 +45,10 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW) {
   // variant 3 sizes the ring for the largest n (three boxes)
   const int RS = ring_steps(R, vb ? 3 : 0) * kB, CRS = (lag + 2) * kB;
   const size_t fl = (size_t)taps_al + (lp ? 2 * (size_t)tapp_al : 0) +
-                    (size_t)kB * NC * (lp ? stage_width16(R, TW) / 2 : stage_width(R, TW)) +
-                    (size_t)(lp ? RS / 2 : RS) * NC * TW + (size_t)CRS * 2 * TW +
+                    (size_t)kB * NC * (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
+                                          : stage_width(R, TW)) +
+                    (size_t)(lp ? RS / 2 : RS) * (NC * TW + (mf ? kRingPadMF : 0)) +
+                    (size_t)CRS * 2 * TW +
                     (vb ? (size_t)16 * NC * TW : 0);
   return fl * sizeof(float);
 }
@@ -57,10 +59,14 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW) {
 // up, on a SIMD.
 template <int D, int RC, int PREC>
 static int blocks_per_cu_drp(int R, int TW) {
-  const size_t lds = fused_lds_bytes(D, R, PREC, TW);
+  // wide 16-bit strips run the matrix-core instance (fused_geometry)
+  const int mf = (TW == kTWMax && (PREC == 1 || PREC == 2)) ? 1 : 0;
+  const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
   const void* kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>);
   if constexpr (kHasWide<D, RC, PREC>)
     if (TW == kTWMax) kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax>);
+  if constexpr (kHasMF<D, RC, PREC>)
+    if (mf) kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax, true>);
   hipFuncAttributes at{};
   int vgpr = 256;
   if (hipFuncGetAttributes(&at, kern) == hipSuccess && at.numRegs > 0) vgpr = at.numRegs;

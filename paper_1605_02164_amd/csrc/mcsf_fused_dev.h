@@ -142,6 +142,23 @@ __device__ __forceinline__ unsigned pack2(float lo, float hi) {
   else return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
+// 16x16x16 matrix-core product with 16-bit inputs and FP32 accumulation:
+// d += a b, a 16x16 (M x K), b 16x16 (K x N).  Lane l holds a[l%16][4(l/16)+v],
+// b[4(l/16)+v][l%16] (v = 0..3, four 16-bit values in a uint2) and
+// d[4(l/16)+v][l%16].
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+template <int PREC>
+__device__ __forceinline__ f32x4_t mfma16(uint2 a, uint2 b, f32x4_t d) {
+  if constexpr (PREC == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(half4_t, a),
+                                                 __builtin_bit_cast(half4_t, b), d, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, a),
+                                                     __builtin_bit_cast(short4_t, b), d, 0, 0, 0);
+}
+
 // Four outputs (p = 0..3, starting at an even sample) of a 2R+1-tap window
 // over aligned sample pairs x2[j] = (x[2j], x[2j+1]):
 //   out[2q]   = sum_i te[i] . x2[q+i],   te[i] = (w[2i],   w[2i+1])
@@ -342,14 +359,18 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // a.t0 .. a.t1-1 (Algorithm 1's term loop over one strip).
 // RC: window radius fixed at compile time, or -1 for a runtime radius.
 // PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
-template <int D, int RC, int PREC, bool P64, int TW = kTW>
+// MF: both passes of the 16-bit variants on the matrix cores (d = 3,
+// 32-column strips, compile-time radius).
+template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
   static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
+  static_assert(!MF || (D == 3 && TW == 32 && RC >= 0 && (PREC == 1 || PREC == 2)),
+                "matrix-core passes");
   using G = Geo<D, TW>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
   constexpr int B = kB;
-  constexpr int RST = NC * TW;       // ring row stride: [ch][x]
+  constexpr int RST = NC * TW + (MF ? kRingPadMF : 0);   // ring row stride: [ch][x]
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
   constexpr bool VB = PREC == 3;                 // running-sum vertical pass
@@ -359,7 +380,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int R = RC >= 0 ? RC : a.R;
-  const int SW = RC >= 0 ? (LP ? stage_width16(RC, TW) : stage_width(RC, TW)) : a.SW;
+  const int SW =
+      RC >= 0 ? (MF ? stage_width_mf(RC) : LP ? stage_width16(RC, TW) : stage_width(RC, TW)) : a.SW;
   const int MW = RC >= 0 ? TW + 2 * RC : SW;   // modulated columns per staging row
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
@@ -419,6 +441,34 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     asm("v_mov_b32 %0, %1" : "=v"(v) : "v"(v));
     tpo[i] = v;
   }
+  // Matrix-core passes: constant tap operands of the banded products.
+  // Horizontal: out[m][x] = sum_j stage[m][j] w[j - x] over k-blocks of 16
+  // samples (KSH of them cover 16 + 2R); this lane holds the B rows
+  // k = 4(l/16)+v of column x = l%16.  Vertical: out[r][n] = sum_i w[i - r]
+  // ring[i][n] over KSV k-blocks covering B + 2R ring rows; this lane holds the
+  // A row r = l%16 (rows 8-15 zero: a step has 8 output rows).
+  constexpr int KSH = MF ? (16 + 2 * RC + 15) / 16 : 1;
+  constexpr int KSV = MF ? (kB + 2 * RC + 15) / 16 : 1;
+  uint2 hb[KSH], va[KSV];
+  if constexpr (MF) {
+    const int ln = tid & 63;
+    auto tap16 = [&](int u, bool on) -> unsigned {
+      return (unsigned)to16<PREC>(on && u >= 0 && u <= 2 * RC ? s_taps[u] : 0.0f);
+    };
+#pragma unroll
+    for (int s = 0; s < KSH; ++s) {
+      const int u = 16 * s + 4 * (ln >> 4) - (ln & 15);
+      hb[s] = make_uint2(tap16(u, true) | tap16(u + 1, true) << 16,
+                         tap16(u + 2, true) | tap16(u + 3, true) << 16);
+    }
+#pragma unroll
+    for (int s = 0; s < KSV; ++s) {
+      const int u = 16 * s + 4 * (ln >> 4) - (ln & 15);
+      const bool on = (ln & 15) < kB;
+      va[s] = make_uint2(tap16(u, on) | tap16(u + 1, on) << 16,
+                         tap16(u + 2, on) | tap16(u + 3, on) << 16);
+    }
+  }
 
   // ---- per-thread fixed roles -------------------------------------------------
   // pass 1 item: 4-column block xq, channel ch, row rr of the step.  xq varies
@@ -449,7 +499,14 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // accumulators: planar [m][Hp][Wp] padded to whole strips, so every lane
   // owns valid storage; 32-bit element offsets from the (uniform) base
   const int Wp = a.nsx * TW;
-  const unsigned acc_lane = (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
+  // matrix-core vertical pass: wave w filters pair w/2 over columns 16(w%2)
+  // .. +15; lanes 0-31 hold output rows 4(l/16) .. +3 of the step
+  const int mf_m = (tid >> 6) >> 1, mf_x = 16 * ((tid >> 6) & 1) + (tid & 15);
+  const int mf_r0 = 4 * ((tid >> 4) & 1);
+  const bool mf_on = (tid & 63) < 32;
+  const unsigned acc_lane =
+      MF ? (unsigned)(mf_m * a.Hp + y0 + mf_r0) * Wp + x0 + mf_x
+         : (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
   // variant 3: running sums of one (column, channel) per lane of the first
   // 16*NC lanes; sparse-difference weights (-1)^k C(n,k), offsets k(2r+1)
   const int vb_x = tid & 15, vb_ch = tid >> 4;
@@ -489,7 +546,12 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   for (int m = 0; m < D; ++m) cen[m] = a.cen_dev ? ld_const(a.cen_dev, m) : a.cen[m];
   const unsigned frow = (unsigned)a.fpitch * D;  // floats per row of f
   float fA[MI][D], fB[MI][D];
-  float aA[2] = {0.0f, 0.0f}, aB[2] = {0.0f, 0.0f};
+  // accumulators of this lane's output rows: 2 rows, or 4 (lanes 0-31) with
+  // the matrix-core vertical pass
+  constexpr int NACC = MF ? 4 : 2;
+  float aA[NACC], aB[NACC];
+#pragma unroll
+  for (int v = 0; v < NACC; ++v) aA[v] = aB[v] = 0.0f;
   int m_fx[MI];  // clamped column offset of each slot, in floats
 #pragma unroll
   for (int i = 0; i < MI; ++i) m_fx[i] = min(max(m_x[i], 0), Wd - 1) * D;
@@ -504,11 +566,19 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       }
     }
   };
-  auto load_acc = [&](float (&dst)[2], int t, int s) {
+  auto load_acc = [&](float (&dst)[NACC], int t, int s) {
     if (t > 0 && t < t1 && s >= lag) {
-      const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
-      dst[0] = buf_load1(acc_rsrc, 4u * o);
-      dst[1] = buf_load1(acc_rsrc, 4u * (o + Wp));
+      if constexpr (MF) {
+        if (mf_on) {
+          const unsigned o = acc_lane + (unsigned)((s - lag) * B) * Wp;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
+        }
+      } else {
+        const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
+        dst[0] = buf_load1(acc_rsrc, 4u * o);
+        dst[1] = buf_load1(acc_rsrc, 4u * (o + Wp));
+      }
     }
   };
 
@@ -526,7 +596,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
 
   // One pipeline step s of term t; fcur/acur hold this step's prefetched
   // data and are refilled for the step two ahead.
-  auto step = [&](int t, int s, float (&fcur)[MI][D], float (&acur)[2]) {
+  auto step = [&](int t, int s, float (&fcur)[MI][D], float (&acur)[NACC]) {
     // ---- 1. modulation ---------------------------------------------------------
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
@@ -588,7 +658,28 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     __syncthreads();
 
     // ---- 2. horizontal pass ------------------------------------------------------
-    {
+    if constexpr (MF) {
+      // wave w: items m = 16(w%4) .. +15 (m = 8 row + channel), output columns
+      // 16(w/4) .. +15; the lanes' results hold rows 2(w%4) + l/32, channels
+      // 4((l/16)%2) + v, column 16(w/4) + l%16
+      const int ln = tid & 63, mb = (tid >> 6) & 3, nb = tid >> 8;
+      const unsigned short* arow =
+          s_stage16 + ((2 * mb + ((ln & 15) >> 3)) * NC + (ln & 7)) * SW + 16 * nb + 4 * (ln >> 4);
+      f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < KSH; ++k)
+        d = mfma16<PREC>(*reinterpret_cast<const uint2*>(arow + 16 * k), hb[k], d);
+      // rows 2w' (lanes 0-31) and 2w'+1 (lanes 32-63) are the low and high
+      // halves of one pair-row.  Each lane stores its own halves: no lane
+      // exchange, so no hand-written instruction reads the product's registers
+      // (the compiler places the wait states a matrix-core result needs only
+      // before the instructions it generates).
+      unsigned short* dst = s_ring16 +
+                            2 * ((rslot / 2 + mb) * RST + 4 * ((ln >> 4) & 1) * TW + 16 * nb + (ln & 15)) +
+                            ((ln >> 5) & 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[2 * v * TW] = to16<PREC>(d[v]);
+    } else {
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (LP) {
         const unsigned* src =
@@ -673,7 +764,36 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       }
       __syncthreads();
     }
-    if (s >= lag) {
+    if (MF && s >= lag) {
+      if constexpr (MF) {
+        // out[r][n] for the pair's cos and sin channels over this wave's 16
+        // columns; the window's ring rows 4(l/16)+v of each k-block are two
+        // aligned pair-rows (rslot_lag is a multiple of 8)
+        constexpr int RSP = ring_steps(RC, 0) * kB / 2;
+        static_assert((RSP - 4) + 8 * (KSV - 1) + 6 < 2 * RSP, "pair-row wrap");
+        const unsigned* colc = s_ring32 + (2 * mf_m) * TW + mf_x;
+        const int pb = rslot_lag / 2 + 2 * ((tid >> 4) & 3);
+        f32x4_t dc = {0.0f, 0.0f, 0.0f, 0.0f}, ds = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < KSV; ++k) {
+          int p = pb + 8 * k;
+          p = p >= RSP ? p - RSP : p;
+          p = p >= RSP ? p - RSP : p;
+          const unsigned* r0 = colc + p * RST;
+          dc = mfma16<PREC>(va[k], make_uint2(r0[0], r0[RST]), dc);
+          ds = mfma16<PREC>(va[k], make_uint2(r0[TW], r0[RST + TW]), ds);
+        }
+        if (mf_on) {
+          const unsigned o = acc_lane + (unsigned)((s - lag) * B) * Wp;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float* cs = s_cs + wrap(cslot_lag + R + mf_r0 + v, CRS) * CST + mf_x;
+            const float q = fmaf(cs[TW], ds[v], cs[0] * dc[v]);
+            buf_store1(acc_rsrc, 4u * (o + v * Wp), fmaf(tw, q, t > 0 ? acur[v] : 0.0f));
+          }
+        }
+      }
+    } else if (!MF && s >= lag) {
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (VB) {
         // output rows (s - lag)*B .. +7 of the strip: the first lag*B - 2R of
@@ -767,19 +887,19 @@ __device__ __forceinline__ int xcd_order(int bid, int n) {
 // path (its branches cost the common path a few percent, so launches whose
 // phases are bounded below 2^8 turns use the instance without it).  TW: strip
 // width, 16 columns (D+1 waves) or 32 (2(D+1) waves).
-template <int D, int RC, int PREC, bool P64, int TW = kTW>
+template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused(FusedArgs a) {
-  fused_strip<D, RC, PREC, P64, TW>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
+  fused_strip<D, RC, PREC, P64, TW, MF>(a, xcd_order(blockIdx.x, a.nsx * a.nsy));
 }
 
 // Several requests of the same instance in one launch (continuous batching):
 // the workgroup finds its request in the prefix table.
-template <int D, int RC, int PREC, bool P64, int TW = kTW>
+template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused_batch(BatchArgs g) {
   const int bid = xcd_order(blockIdx.x, g.first[g.n]);
   int i = 0;
   while (i + 1 < g.n && bid >= g.first[i + 1]) ++i;
-  fused_strip<D, RC, PREC, P64, TW>(g.req[i], bid - g.first[i]);
+  fused_strip<D, RC, PREC, P64, TW, MF>(g.req[i], bid - g.first[i]);
 }
 
 
@@ -788,24 +908,36 @@ __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused_batch(Bat
 // (choose_strip_width selects them).
 template <int D, int RC, int PREC>
 inline constexpr bool kHasWide = D == 3 && RC >= 0 && PREC <= 2;
+// ... and of those, the 16-bit ones also with matrix-core passes
+template <int D, int RC, int PREC>
+inline constexpr bool kHasMF = kHasWide<D, RC, PREC> && (PREC == 1 || PREC == 2);
 
 template <int D, int RC, int PREC, class A>
 static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
   int nwg, TW = kTW;
   void (*kern)(A);
-  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64 and the strip width
+  int mf = 0;
+  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64 and the strip shape
     const bool p64 = a.req[0].p64;
     for (int k = 1; k < a.n; ++k)
-      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc) return hipErrorInvalidValue;
+      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc || a.req[k].mf != a.req[0].mf)
+        return hipErrorInvalidValue;
     kern = p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
     if constexpr (kHasWide<D, RC, PREC>) {
       if (a.req[0].TWc == kTWMax) {
         kern = p64 ? mcsf_fused_batch<D, RC, PREC, true, kTWMax>
                    : mcsf_fused_batch<D, RC, PREC, false, kTWMax>;
         TW = kTWMax;
+        if constexpr (kHasMF<D, RC, PREC>) {
+          if (a.req[0].mf) {
+            kern = p64 ? mcsf_fused_batch<D, RC, PREC, true, kTWMax, true>
+                       : mcsf_fused_batch<D, RC, PREC, false, kTWMax, true>;
+            mf = 1;
+          }
+        }
       }
     }
-    if (a.req[0].TWc != TW) return hipErrorInvalidValue;   // no instance for this width
+    if (a.req[0].TWc != TW || a.req[0].mf != mf) return hipErrorInvalidValue;   // no such instance
     nwg = a.first[a.n];
   } else {
     kern = a.p64 ? mcsf_fused<D, RC, PREC, true> : mcsf_fused<D, RC, PREC, false>;
@@ -813,12 +945,19 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
       if (a.TWc == kTWMax) {
         kern = a.p64 ? mcsf_fused<D, RC, PREC, true, kTWMax> : mcsf_fused<D, RC, PREC, false, kTWMax>;
         TW = kTWMax;
+        if constexpr (kHasMF<D, RC, PREC>) {
+          if (a.mf) {
+            kern = a.p64 ? mcsf_fused<D, RC, PREC, true, kTWMax, true>
+                         : mcsf_fused<D, RC, PREC, false, kTWMax, true>;
+            mf = 1;
+          }
+        }
       }
     }
-    if (a.TWc != TW) return hipErrorInvalidValue;   // no instance for this width
+    if (a.TWc != TW || a.mf != mf) return hipErrorInvalidValue;   // no instance for this shape
     nwg = a.nsx * a.nsy;
   }
-  const size_t lds = fused_lds_bytes(D, R, PREC, TW);
+  const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
