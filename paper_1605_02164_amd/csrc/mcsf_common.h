@@ -50,6 +50,20 @@ inline constexpr int stage_width_mf(int R) { return 16 + 16 * ((16 + 2 * R + 15)
 // dwords: the four 16-lane groups of an operand read sit 2 pair-rows apart,
 // which a stride of 8 mod 32 dwords spreads over all banks.
 constexpr int kRingPadMF = 8;
+// Matrix-core passes for a launch with strip width TW (the wide instances
+// have them): always with 16-bit storage; for FP32 (horizontal pass only) from
+// R = 12 up -- measured at 4096^2, K = 32: 3-17% faster at R = 12..30, 3-5%
+// slower at R = 6 and 9.
+inline constexpr bool use_mf(int TW, int prec, int R) {
+  return TW == kTWMax && (prec == 1 || prec == 2 || (prec == 0 && R >= 12));
+}
+// FP32 staging row width of the matrix-core horizontal pass: 16 + 4*ceil((16
+// + 2R)/4) samples read per row (k-blocks of 4), rounded to 4 mod 8 floats so
+// that the 16 rows x 4 columns one operand read touches fall on distinct banks.
+inline constexpr int stage_width_mf32(int R) {
+  const int need = 16 + 4 * ((16 + 2 * R + 3) / 4);
+  return need % 8 == 0 ? need + 4 : need;
+}
 constexpr int kSWMax = stage_width(kRMax);
 // 2R rows of look-ahead, in steps of kB rows
 inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }

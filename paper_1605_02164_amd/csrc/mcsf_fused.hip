@@ -46,8 +46,8 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
   const int RS = ring_steps(R, vb ? 3 : 0) * kB, CRS = (lag + 2) * kB;
   const size_t fl = (size_t)taps_al + (lp ? 2 * (size_t)tapp_al : 0) +
                     (size_t)kB * NC * (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
-                                          : stage_width(R, TW)) +
-                    (size_t)(lp ? RS / 2 : RS) * (NC * TW + (mf ? kRingPadMF : 0)) +
+                                          : (mf ? stage_width_mf32(R) : stage_width(R, TW))) +
+                    (size_t)(lp ? RS / 2 : RS) * (NC * TW + (mf && lp ? kRingPadMF : 0)) +
                     (size_t)CRS * 2 * TW +
                     (vb ? (size_t)16 * NC * TW : 0);
   return fl * sizeof(float);
@@ -59,8 +59,7 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
 // up, on a SIMD.
 template <int D, int RC, int PREC>
 static int blocks_per_cu_drp(int R, int TW) {
-  // wide 16-bit strips run the matrix-core instance (fused_geometry)
-  const int mf = (TW == kTWMax && (PREC == 1 || PREC == 2)) ? 1 : 0;
+  const int mf = use_mf(TW, PREC, R) ? 1 : 0;   // as fused_geometry sets it
   const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
   const void* kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>);
   if constexpr (kHasWide<D, RC, PREC>)

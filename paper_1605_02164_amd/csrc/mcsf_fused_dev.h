@@ -149,6 +149,11 @@ __device__ __forceinline__ unsigned pack2(float lo, float hi) {
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+// 16x16x4 FP32 product: lane l holds a[l%16][l/16], b[l/16][l%16] and d as
+// above.
+__device__ __forceinline__ f32x4_t mfma4(float a, float b, f32x4_t d) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+}
 template <int PREC>
 __device__ __forceinline__ f32x4_t mfma16(uint2 a, uint2 b, f32x4_t d) {
   if constexpr (PREC == 1)
@@ -359,18 +364,18 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // a.t0 .. a.t1-1 (Algorithm 1's term loop over one strip).
 // RC: window radius fixed at compile time, or -1 for a runtime radius.
 // PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
-// MF: both passes of the 16-bit variants on the matrix cores (d = 3,
-// 32-column strips, compile-time radius).
+// MF: the horizontal pass on the matrix cores, and with 16-bit storage the
+// vertical pass too (d = 3, 32-column strips, compile-time radius).
 template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
   static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
-  static_assert(!MF || (D == 3 && TW == 32 && RC >= 0 && (PREC == 1 || PREC == 2)),
-                "matrix-core passes");
+  static_assert(!MF || (D == 3 && TW == 32 && RC >= 0 && PREC <= 2), "matrix-core passes");
   using G = Geo<D, TW>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
   constexpr int B = kB;
-  constexpr int RST = NC * TW + (MF ? kRingPadMF : 0);   // ring row stride: [ch][x]
+  constexpr bool MFV = MF && (PREC == 1 || PREC == 2);   // vertical pass on the matrix cores too
+  constexpr int RST = NC * TW + (MFV ? kRingPadMF : 0);   // ring row stride: [ch][x]
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
   constexpr bool VB = PREC == 3;                 // running-sum vertical pass
@@ -380,8 +385,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int R = RC >= 0 ? RC : a.R;
-  const int SW =
-      RC >= 0 ? (MF ? stage_width_mf(RC) : LP ? stage_width16(RC, TW) : stage_width(RC, TW)) : a.SW;
+  const int SW = RC >= 0 ? (MF ? (LP ? stage_width_mf(RC) : stage_width_mf32(RC))
+                               : LP ? stage_width16(RC, TW) : stage_width(RC, TW))
+                          : a.SW;
   const int MW = RC >= 0 ? TW + 2 * RC : SW;   // modulated columns per staging row
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
@@ -447,10 +453,21 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // k = 4(l/16)+v of column x = l%16.  Vertical: out[r][n] = sum_i w[i - r]
   // ring[i][n] over KSV k-blocks covering B + 2R ring rows; this lane holds the
   // A row r = l%16 (rows 8-15 zero: a step has 8 output rows).
-  constexpr int KSH = MF ? (16 + 2 * RC + 15) / 16 : 1;
-  constexpr int KSV = MF ? (kB + 2 * RC + 15) / 16 : 1;
+  constexpr int KSH = MFV ? (16 + 2 * RC + 15) / 16 : 1;
+  constexpr int KSV = MFV ? (kB + 2 * RC + 15) / 16 : 1;
+  // FP32 horizontal pass: k-blocks of 4 samples, one tap per lane and block
+  constexpr int KS4 = (MF && !LP) ? (16 + 2 * RC + 3) / 4 : 1;
   uint2 hb[KSH], va[KSV];
-  if constexpr (MF) {
+  float hb4[KS4];
+  if constexpr (MF && !LP) {
+    const int ln = tid & 63;
+#pragma unroll
+    for (int s = 0; s < KS4; ++s) {
+      const int u = 4 * s + (ln >> 4) - (ln & 15);
+      hb4[s] = u >= 0 && u <= 2 * RC ? s_taps[u] : 0.0f;
+    }
+  }
+  if constexpr (MFV) {
     const int ln = tid & 63;
     auto tap16 = [&](int u, bool on) -> unsigned {
       return (unsigned)to16<PREC>(on && u >= 0 && u <= 2 * RC ? s_taps[u] : 0.0f);
@@ -505,7 +522,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const int mf_r0 = 4 * ((tid >> 4) & 1);
   const bool mf_on = (tid & 63) < 32;
   const unsigned acc_lane =
-      MF ? (unsigned)(mf_m * a.Hp + y0 + mf_r0) * Wp + x0 + mf_x
+      MFV ? (unsigned)(mf_m * a.Hp + y0 + mf_r0) * Wp + x0 + mf_x
          : (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
   // variant 3: running sums of one (column, channel) per lane of the first
   // 16*NC lanes; sparse-difference weights (-1)^k C(n,k), offsets k(2r+1)
@@ -548,7 +565,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   float fA[MI][D], fB[MI][D];
   // accumulators of this lane's output rows: 2 rows, or 4 (lanes 0-31) with
   // the matrix-core vertical pass
-  constexpr int NACC = MF ? 4 : 2;
+  constexpr int NACC = MFV ? 4 : 2;
   float aA[NACC], aB[NACC];
 #pragma unroll
   for (int v = 0; v < NACC; ++v) aA[v] = aB[v] = 0.0f;
@@ -568,7 +585,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   };
   auto load_acc = [&](float (&dst)[NACC], int t, int s) {
     if (t > 0 && t < t1 && s >= lag) {
-      if constexpr (MF) {
+      if constexpr (MFV) {
         if (mf_on) {
           const unsigned o = acc_lane + (unsigned)((s - lag) * B) * Wp;
 #pragma unroll
@@ -658,7 +675,19 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     __syncthreads();
 
     // ---- 2. horizontal pass ------------------------------------------------------
-    if constexpr (MF) {
+    if constexpr (MF && !LP) {
+      // FP32: as below with k-blocks of 4 samples (one per lane group of 16)
+      const int ln = tid & 63, mb = (tid >> 6) & 3, nb = tid >> 8;
+      const float* arow = s_stage + ((2 * mb + ((ln & 15) >> 3)) * NC + (ln & 7)) * SW + 16 * nb + (ln >> 4);
+      f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int k = 0; k < KS4; ++k) d = mfma4(arow[4 * k], hb4[k], d);
+      // rows 2(w%4) + l/32, channels 4((l/16)%2) + v, column 16(w/4) + l%16
+      float* dst = s_ring + (rslot + 2 * mb + ((ln >> 5) & 1)) * RST + 4 * ((ln >> 4) & 1) * TW +
+                   16 * nb + (ln & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[v * TW] = d[v];
+    } else if constexpr (MF) {
       // wave w: items m = 16(w%4) .. +15 (m = 8 row + channel), output columns
       // 16(w/4) .. +15; the lanes' results hold rows 2(w%4) + l/32, channels
       // 4((l/16)%2) + v, column 16(w/4) + l%16
@@ -764,8 +793,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       }
       __syncthreads();
     }
-    if (MF && s >= lag) {
-      if constexpr (MF) {
+    if (MFV && s >= lag) {
+      if constexpr (MFV) {
         // out[r][n] for the pair's cos and sin channels over this wave's 16
         // columns; the window's ring rows 4(l/16)+v of each k-block are two
         // aligned pair-rows (rslot_lag is a multiple of 8)
@@ -793,7 +822,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
           }
         }
       }
-    } else if (!MF && s >= lag) {
+    } else if (!MFV && s >= lag) {
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (VB) {
         // output rows (s - lag)*B .. +7 of the strip: the first lag*B - 2R of
@@ -908,9 +937,9 @@ __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused_batch(Bat
 // (choose_strip_width selects them).
 template <int D, int RC, int PREC>
 inline constexpr bool kHasWide = D == 3 && RC >= 0 && PREC <= 2;
-// ... and of those, the 16-bit ones also with matrix-core passes
+// ... all of which have the matrix-core passes
 template <int D, int RC, int PREC>
-inline constexpr bool kHasMF = kHasWide<D, RC, PREC> && (PREC == 1 || PREC == 2);
+inline constexpr bool kHasMF = kHasWide<D, RC, PREC>;
 
 template <int D, int RC, int PREC, class A>
 static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
