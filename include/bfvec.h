@@ -109,15 +109,15 @@ typedef struct bf_opts {
                       and W >= 32 (else BF_EUNSUPPORTED); automatic picks 32
                       there unless it cuts resident waves per CU below 3/4 or
                       the image is too small to fill the GPU (fewer than two
-                      16-column, 8-row strips per compute unit).  At 32
-                      columns the passes run as banded matrix products on the
-                      matrix cores: both with FP16/BF16 storage, the
-                      horizontal one for FP32 from a radius of 12 up.  They
-                      sum the taps in another order than the 16-column
-                      passes, so results then differ by rounding only; FP32
-                      below radius 12 is bitwise equal at either width.
-                      bf_vec_ex, plans and the server agree bit for bit at
-                      equal width.                                            */
+                      16-column, 8-row strips per compute unit).  At these
+                      radii the passes run as banded matrix products on the
+                      matrix cores: both with FP16/BF16 storage (either
+                      width), and for FP32 the horizontal one of 32-column
+                      strips from a radius of 12 up, which sums the taps in
+                      another order than 16-column strips: FP32 results there
+                      differ between widths by rounding only.  Otherwise the
+                      width changes no output bit.  bf_vec_ex, plans and the
+                      server agree bit for bit at equal width.                */
   int tile_w_used; /* OUT: strip width the fused kernel ran with (16 or 32)   */
 } bf_opts;
 

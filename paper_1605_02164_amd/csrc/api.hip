@@ -202,7 +202,6 @@ void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbo
   a.R = R;
   a.TH = TH;
   a.TWc = TW;
-  a.mf = use_mf(TW, prec, R) ? 1 : 0;   // matrix-core passes
   a.nsx = (W + TW - 1) / TW;
   a.nsy = (H + TH - 1) / TH;
   a.SW = (prec == 1 || prec == 2) ? stage_width16(R, TW) : stage_width(R, TW);

@@ -50,12 +50,12 @@ inline constexpr int stage_width_mf(int R) { return 16 + 16 * ((16 + 2 * R + 15)
 // dwords: the four 16-lane groups of an operand read sit 2 pair-rows apart,
 // which a stride of 8 mod 32 dwords spreads over all banks.
 constexpr int kRingPadMF = 8;
-// Matrix-core passes for a launch with strip width TW (the wide instances
-// have them): always with 16-bit storage; for FP32 (horizontal pass only) from
-// R = 12 up -- measured at 4096^2, K = 32: 3-17% faster at R = 12..30, 3-5%
-// slower at R = 6 and 9.
+// Matrix-core passes for a launch with strip width TW, on the instances that
+// have them (compile-time radius): always with 16-bit storage; for FP32 (the
+// horizontal pass, 32-column strips) from R = 12 up -- measured at 4096^2,
+// K = 32: 3-17% faster at R = 12..30, 3-5% slower at R = 6 and 9.
 inline constexpr bool use_mf(int TW, int prec, int R) {
-  return TW == kTWMax && (prec == 1 || prec == 2 || (prec == 0 && R >= 12));
+  return prec == 1 || prec == 2 || (TW == kTWMax && prec == 0 && R >= 12);
 }
 // FP32 staging row width of the matrix-core horizontal pass: 16 + 4*ceil((16
 // + 2R)/4) samples read per row (k-blocks of 4), rounded to 4 mod 8 floats so
@@ -106,7 +106,6 @@ struct FusedArgs {
   int steps, lag;        // steps per term, and 2R look-ahead in steps
   int vbox;              // variant 3: n of the n-fold box (R = n r); else 0
   int TWc;               // strip width: kTW, or kTWMax for the wide-strip instances
-  int mf;                // 1: 16-bit passes on the matrix cores (32-column strips)
   int p64;               // 1: instance with the FP64 phase path (phase bound unknown or
                          // above kPhaseBound), 0: without it
   float wmax[8];         // max_t |w_tm / 2pi| over the table's FP32 values

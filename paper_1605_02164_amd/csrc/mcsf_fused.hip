@@ -59,13 +59,22 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
 // up, on a SIMD.
 template <int D, int RC, int PREC>
 static int blocks_per_cu_drp(int R, int TW) {
-  const int mf = use_mf(TW, PREC, R) ? 1 : 0;   // as fused_geometry sets it
-  const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
+  // the instance launch_drp picks for this width
+  int mf = 0;
   const void* kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>);
+  if constexpr (kHasMF<D, RC, PREC, kTW>)
+    if (TW == kTW && use_mf(TW, PREC, R)) {
+      kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTW, true>);
+      mf = 1;
+    }
   if constexpr (kHasWide<D, RC, PREC>)
     if (TW == kTWMax) kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax>);
-  if constexpr (kHasMF<D, RC, PREC>)
-    if (mf) kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax, true>);
+  if constexpr (kHasMF<D, RC, PREC, kTWMax>)
+    if (TW == kTWMax && use_mf(TW, PREC, R)) {
+      kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax, true>);
+      mf = 1;
+    }
+  const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
   hipFuncAttributes at{};
   int vgpr = 256;
   if (hipFuncGetAttributes(&at, kern) == hipSuccess && at.numRegs > 0) vgpr = at.numRegs;

@@ -364,13 +364,15 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // a.t0 .. a.t1-1 (Algorithm 1's term loop over one strip).
 // RC: window radius fixed at compile time, or -1 for a runtime radius.
 // PREC: 0 FP32 channels; 1 FP16 / 2 BF16 storage of channels and ring rows.
-// MF: the horizontal pass on the matrix cores, and with 16-bit storage the
-// vertical pass too (d = 3, 32-column strips, compile-time radius).
+// MF: the passes on the matrix cores, at a compile-time radius: both with
+// 16-bit storage (either strip width), the horizontal one for FP32 (32-column
+// strips).
 template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
   static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
-  static_assert(!MF || (D == 3 && TW == 32 && RC >= 0 && PREC <= 2), "matrix-core passes");
+  static_assert(!MF || (RC >= 0 && (TW == 32 ? D == 3 && PREC <= 2 : PREC == 1 || PREC == 2)),
+                "matrix-core passes");
   using G = Geo<D, TW>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
   constexpr int B = kB;
@@ -516,9 +518,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // accumulators: planar [m][Hp][Wp] padded to whole strips, so every lane
   // owns valid storage; 32-bit element offsets from the (uniform) base
   const int Wp = a.nsx * TW;
-  // matrix-core vertical pass: wave w filters pair w/2 over columns 16(w%2)
-  // .. +15; lanes 0-31 hold output rows 4(l/16) .. +3 of the step
-  const int mf_m = (tid >> 6) >> 1, mf_x = 16 * ((tid >> 6) & 1) + (tid & 15);
+  // matrix-core vertical pass: wave w filters pair w/(TW/16) over columns
+  // 16(w%(TW/16)) .. +15; lanes 0-31 hold output rows 4(l/16) .. +3 of the step
+  const int mf_m = (tid >> 6) / (TW / 16), mf_x = 16 * ((tid >> 6) % (TW / 16)) + (tid & 15);
   const int mf_r0 = 4 * ((tid >> 4) & 1);
   const bool mf_on = (tid & 63) < 32;
   const unsigned acc_lane =
@@ -675,39 +677,40 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     __syncthreads();
 
     // ---- 2. horizontal pass ------------------------------------------------------
+    // Matrix-core horizontal pass: the step's staging rows m = NC row +
+    // channel (16 NP of them) form NP blocks of 16; wave w takes block w % NP
+    // and output columns 16(w/NP) .. +15.  Lane l's results are items
+    // m = 16(w%NP) + 4(l/16) + v, column 16(w/NP) + l%16.
     if constexpr (MF && !LP) {
-      // FP32: as below with k-blocks of 4 samples (one per lane group of 16)
-      const int ln = tid & 63, mb = (tid >> 6) & 3, nb = tid >> 8;
-      const float* arow = s_stage + ((2 * mb + ((ln & 15) >> 3)) * NC + (ln & 7)) * SW + 16 * nb + (ln >> 4);
+      // FP32: k-blocks of 4 samples (one per lane group of 16)
+      const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+      const float* arow = s_stage + (16 * mb + (ln & 15)) * SW + 16 * nb + (ln >> 4);
       f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < KS4; ++k) d = mfma4(arow[4 * k], hb4[k], d);
-      // rows 2(w%4) + l/32, channels 4((l/16)%2) + v, column 16(w/4) + l%16
-      float* dst = s_ring + (rslot + 2 * mb + ((ln >> 5) & 1)) * RST + 4 * ((ln >> 4) & 1) * TW +
-                   16 * nb + (ln & 15);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[v * TW] = d[v];
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
+        s_ring[(rslot + row) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)] = d[v];
+      }
     } else if constexpr (MF) {
-      // wave w: items m = 16(w%4) .. +15 (m = 8 row + channel), output columns
-      // 16(w/4) .. +15; the lanes' results hold rows 2(w%4) + l/32, channels
-      // 4((l/16)%2) + v, column 16(w/4) + l%16
-      const int ln = tid & 63, mb = (tid >> 6) & 3, nb = tid >> 8;
-      const unsigned short* arow =
-          s_stage16 + ((2 * mb + ((ln & 15) >> 3)) * NC + (ln & 7)) * SW + 16 * nb + 4 * (ln >> 4);
+      const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+      const unsigned short* arow = s_stage16 + (16 * mb + (ln & 15)) * SW + 16 * nb + 4 * (ln >> 4);
       f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < KSH; ++k)
         d = mfma16<PREC>(*reinterpret_cast<const uint2*>(arow + 16 * k), hb[k], d);
-      // rows 2w' (lanes 0-31) and 2w'+1 (lanes 32-63) are the low and high
-      // halves of one pair-row.  Each lane stores its own halves: no lane
-      // exchange, so no hand-written instruction reads the product's registers
-      // (the compiler places the wait states a matrix-core result needs only
-      // before the instructions it generates).
-      unsigned short* dst = s_ring16 +
-                            2 * ((rslot / 2 + mb) * RST + 4 * ((ln >> 4) & 1) * TW + 16 * nb + (ln & 15)) +
-                            ((ln >> 5) & 1);
+      // row r of the step is the low (even r) or high (odd r) half of pair-row
+      // (rslot + r)/2.  Each lane stores its own halves: no lane exchange, so
+      // no hand-written instruction reads the product's registers (the
+      // compiler places the wait states a matrix-core result needs only before
+      // the instructions it generates).
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[2 * v * TW] = to16<PREC>(d[v]);
+      for (int v = 0; v < 4; ++v) {
+        const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
+        s_ring16[2 * (((rslot + row) >> 1) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)) +
+                 (row & 1)] = to16<PREC>(d[v]);
+      }
     } else {
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (LP) {
@@ -937,28 +940,41 @@ __global__ __launch_bounds__(64 * (D + 1) * (TW / 16)) void mcsf_fused_batch(Bat
 // (choose_strip_width selects them).
 template <int D, int RC, int PREC>
 inline constexpr bool kHasWide = D == 3 && RC >= 0 && PREC <= 2;
-// ... all of which have the matrix-core passes
-template <int D, int RC, int PREC>
-inline constexpr bool kHasMF = kHasWide<D, RC, PREC>;
+// Instances with matrix-core passes (chosen at launch by use_mf): the wide
+// ones, and the 16-column 16-bit ones at a compile-time radius.
+template <int D, int RC, int PREC, int TW>
+inline constexpr bool kHasMF =
+    TW == kTWMax ? kHasWide<D, RC, PREC> : RC >= 0 && (PREC == 1 || PREC == 2);
+
+inline int a_tw(const FusedArgs& a) { return a.TWc; }
+inline int a_tw(const BatchArgs& b) { return b.req[0].TWc; }
 
 template <int D, int RC, int PREC, class A>
 static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
   int nwg, TW = kTW;
   void (*kern)(A);
   int mf = 0;
-  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64 and the strip shape
+  const bool want_mf = use_mf(a_tw(a), PREC, R);
+  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64 and the strip width
     const bool p64 = a.req[0].p64;
     for (int k = 1; k < a.n; ++k)
-      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc || a.req[k].mf != a.req[0].mf)
-        return hipErrorInvalidValue;
+      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc) return hipErrorInvalidValue;
     kern = p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
+    if constexpr (kHasMF<D, RC, PREC, kTW>) {
+      if (want_mf) {
+        kern = p64 ? mcsf_fused_batch<D, RC, PREC, true, kTW, true>
+                   : mcsf_fused_batch<D, RC, PREC, false, kTW, true>;
+        mf = 1;
+      }
+    }
     if constexpr (kHasWide<D, RC, PREC>) {
       if (a.req[0].TWc == kTWMax) {
         kern = p64 ? mcsf_fused_batch<D, RC, PREC, true, kTWMax>
                    : mcsf_fused_batch<D, RC, PREC, false, kTWMax>;
         TW = kTWMax;
-        if constexpr (kHasMF<D, RC, PREC>) {
-          if (a.req[0].mf) {
+        mf = 0;
+        if constexpr (kHasMF<D, RC, PREC, kTWMax>) {
+          if (want_mf) {
             kern = p64 ? mcsf_fused_batch<D, RC, PREC, true, kTWMax, true>
                        : mcsf_fused_batch<D, RC, PREC, false, kTWMax, true>;
             mf = 1;
@@ -966,16 +982,23 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
         }
       }
     }
-    if (a.req[0].TWc != TW || a.req[0].mf != mf) return hipErrorInvalidValue;   // no such instance
+    if (a.req[0].TWc != TW) return hipErrorInvalidValue;   // no instance for this width
     nwg = a.first[a.n];
   } else {
     kern = a.p64 ? mcsf_fused<D, RC, PREC, true> : mcsf_fused<D, RC, PREC, false>;
+    if constexpr (kHasMF<D, RC, PREC, kTW>) {
+      if (want_mf) {
+        kern = a.p64 ? mcsf_fused<D, RC, PREC, true, kTW, true> : mcsf_fused<D, RC, PREC, false, kTW, true>;
+        mf = 1;
+      }
+    }
     if constexpr (kHasWide<D, RC, PREC>) {
       if (a.TWc == kTWMax) {
         kern = a.p64 ? mcsf_fused<D, RC, PREC, true, kTWMax> : mcsf_fused<D, RC, PREC, false, kTWMax>;
         TW = kTWMax;
-        if constexpr (kHasMF<D, RC, PREC>) {
-          if (a.mf) {
+        mf = 0;
+        if constexpr (kHasMF<D, RC, PREC, kTWMax>) {
+          if (want_mf) {
             kern = a.p64 ? mcsf_fused<D, RC, PREC, true, kTWMax, true>
                          : mcsf_fused<D, RC, PREC, false, kTWMax, true>;
             mf = 1;
@@ -983,7 +1006,7 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
         }
       }
     }
-    if (a.TWc != TW || a.mf != mf) return hipErrorInvalidValue;   // no instance for this shape
+    if (a.TWc != TW) return hipErrorInvalidValue;   // no instance for this width
     nwg = a.nsx * a.nsy;
   }
   const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
