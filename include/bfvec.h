@@ -84,7 +84,8 @@ typedef struct bf_opts {
   int center;      /* 1 (default): phase taken on f - c with c the per-channel
                       midpoint (exact in arithmetic: the filter commutes with
                       constant shifts); 0: phase on f itself                   */
-  int tile_h;      /* strip height in rows; 0 = automatic                      */
+  int tile_h;      /* strip height in rows; 0 = automatic.  Rounded up to a
+                      multiple of 8 rows; tile_h_used reports what ran        */
   void* stream;    /* hipStream_t for all device work; NULL = null stream      */
   float* num_out;  /* optional DEVICE H*W*d numerator Re(P), or NULL           */
   float* z_out;    /* optional DEVICE H*W normaliser Re(Z), or NULL            */

@@ -529,13 +529,19 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   (void)TH0;
   int TW = kTW;   // the probes run at the automatic strip width
   if ((rc = choose_strip_width(d, R, precision, H, W, 0, &TW))) return rc;
-  const int model = model_strip_height(d, R, precision, H, W, TW);
+  // every height as the launch runs it (fused_geometry may round it up)
+  auto effective = [&](int th) {
+    FusedArgs g{};
+    fused_geometry(g, H, W, R, precision, th, 0, TW);
+    return g.TH;
+  };
+  const int model = effective(model_strip_height(d, R, precision, H, W, TW));
   // candidate strip counts down the image around the model's
   const int nsy0 = (H + model - 1) / model, nmax = (H + kB - 1) / kB;
   std::vector<int> ths;
   for (int f10 : {3, 5, 7, 10, 13, 15, 20, 30, 40}) {
     const int nsy = std::min(nmax, std::max(1, (nsy0 * f10 + 5) / 10));
-    const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
+    const int th = effective(((H + nsy - 1) / nsy + kB - 1) / kB * kB);
     if (std::find(ths.begin(), ths.end(), th) == ths.end()) ths.push_back(th);
   }
   // probe terms: a few fixed frequencies (the cost does not depend on them)

@@ -378,13 +378,13 @@ def test_autotune_records_height_and_keeps_bits():
     fg = cuda(f)
     C = 0.08 ** 2 * np.eye(3)
     for prec in ("fp32", "fp16"):
-        ref, o0 = P.bf_vec_ex(fg, 5.0, C, 8, 3, precision=prec, tile_h=8, return_opts=True)
+        ref, o0 = P.bf_vec_ex(fg, 5.0, C, 8, 3, precision=prec, tile_h=16, return_opts=True)
         ref = host(ref)
         th, ms = P.bf_autotune(fg, 5.0, precision=prec)
         say(f"  {prec}: tuned strip height {th}, {ms:.4f} ms per term")
         assert th % 8 == 0 and 8 <= th <= 208 and ms > 0
         got, o = P.bf_vec_ex(fg, 5.0, C, 8, 3, precision=prec, return_opts=True)
-        assert o.tile_h_used == th and o0.tile_h_used == 8
+        assert o.tile_h_used == th and o0.tile_h_used == 16
         assert np.array_equal(host(got), ref)
 
 
