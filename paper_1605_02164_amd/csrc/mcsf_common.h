@@ -45,11 +45,11 @@ inline constexpr int stage_width16(int R, int TW = kTW) {
 // row (two 16-column output blocks, k-blocks of 16; at least the TW + 2R
 // modulated ones), plus 4 so that the row stride is 2 mod 4 dwords: the 16
 // rows one operand read touches then fall on distinct LDS banks.
-inline constexpr int stage_width_mf(int R) { return 16 + 16 * ((16 + 2 * R + 15) / 16) + 4; }
+inline constexpr int stage_width_mf(int R) { return 16 + 32 * ((16 + 2 * R + 31) / 32) + 8; }
 // Pair-row padding of the 16-bit ring for the matrix-core vertical pass, in
 // dwords: the four 16-lane groups of an operand read sit 2 pair-rows apart,
 // which a stride of 8 mod 32 dwords spreads over all banks.
-constexpr int kRingPadMF = 8;
+constexpr int kRingPadMF = 4;
 // Matrix-core passes for a launch with strip width TW, on the instances that
 // have them (compile-time radius): always with 16-bit storage; for FP32 (the
 // horizontal pass, 32-column strips) from R = 12 up -- measured at 4096^2,

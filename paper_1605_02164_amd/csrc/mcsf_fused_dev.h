@@ -154,6 +154,19 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f32x4_t mfma4(float a, float b, f32x4_t d) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
 }
+// 16x16x32 form (gfx950): eight 16-bit values per lane, a[l%16][8(l/16)+v],
+// b[8(l/16)+v][l%16]; d as above.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+template <int PREC>
+__device__ __forceinline__ f32x4_t mfma32(uint4 a, uint4 b, f32x4_t d) {
+  if constexpr (PREC == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a),
+                                                  __builtin_bit_cast(half8_t, b), d, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                   __builtin_bit_cast(bf16x8_t, b), d, 0, 0, 0);
+}
 template <int PREC>
 __device__ __forceinline__ f32x4_t mfma16(uint2 a, uint2 b, f32x4_t d) {
   if constexpr (PREC == 1)
@@ -455,11 +468,11 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // k = 4(l/16)+v of column x = l%16.  Vertical: out[r][n] = sum_i w[i - r]
   // ring[i][n] over KSV k-blocks covering B + 2R ring rows; this lane holds the
   // A row r = l%16 (rows 8-15 zero: a step has 8 output rows).
-  constexpr int KSH = MFV ? (16 + 2 * RC + 15) / 16 : 1;
-  constexpr int KSV = MFV ? (kB + 2 * RC + 15) / 16 : 1;
+  constexpr int KSH = MFV ? (16 + 2 * RC + 31) / 32 : 1;
+  constexpr int KSV = MFV ? (kB + 2 * RC + 31) / 32 : 1;
   // FP32 horizontal pass: k-blocks of 4 samples, one tap per lane and block
   constexpr int KS4 = (MF && !LP) ? (16 + 2 * RC + 3) / 4 : 1;
-  uint2 hb[KSH], va[KSV];
+  uint4 hb[KSH], va[KSV];
   float hb4[KS4];
   if constexpr (MF && !LP) {
     const int ln = tid & 63;
@@ -476,16 +489,20 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     };
 #pragma unroll
     for (int s = 0; s < KSH; ++s) {
-      const int u = 16 * s + 4 * (ln >> 4) - (ln & 15);
-      hb[s] = make_uint2(tap16(u, true) | tap16(u + 1, true) << 16,
-                         tap16(u + 2, true) | tap16(u + 3, true) << 16);
+      const int u = 32 * s + 8 * (ln >> 4) - (ln & 15);
+      hb[s] = make_uint4(tap16(u, true) | tap16(u + 1, true) << 16,
+                         tap16(u + 2, true) | tap16(u + 3, true) << 16,
+                         tap16(u + 4, true) | tap16(u + 5, true) << 16,
+                         tap16(u + 6, true) | tap16(u + 7, true) << 16);
     }
 #pragma unroll
     for (int s = 0; s < KSV; ++s) {
-      const int u = 16 * s + 4 * (ln >> 4) - (ln & 15);
+      const int u = 32 * s + 8 * (ln >> 4) - (ln & 15);
       const bool on = (ln & 15) < kB;
-      va[s] = make_uint2(tap16(u, on) | tap16(u + 1, on) << 16,
-                         tap16(u + 2, on) | tap16(u + 3, on) << 16);
+      va[s] = make_uint4(tap16(u, on) | tap16(u + 1, on) << 16,
+                         tap16(u + 2, on) | tap16(u + 3, on) << 16,
+                         tap16(u + 4, on) | tap16(u + 5, on) << 16,
+                         tap16(u + 6, on) | tap16(u + 7, on) << 16);
     }
   }
 
@@ -695,11 +712,11 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       }
     } else if constexpr (MF) {
       const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
-      const unsigned short* arow = s_stage16 + (16 * mb + (ln & 15)) * SW + 16 * nb + 4 * (ln >> 4);
+      const unsigned short* arow = s_stage16 + (16 * mb + (ln & 15)) * SW + 16 * nb + 8 * (ln >> 4);
       f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < KSH; ++k)
-        d = mfma16<PREC>(*reinterpret_cast<const uint2*>(arow + 16 * k), hb[k], d);
+        d = mfma32<PREC>(*reinterpret_cast<const uint4*>(arow + 32 * k), hb[k], d);
       // row r of the step is the low (even r) or high (odd r) half of pair-row
       // (rslot + r)/2.  Each lane stores its own halves: no lane exchange, so
       // no hand-written instruction reads the product's registers (the
@@ -799,21 +816,23 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     if (MFV && s >= lag) {
       if constexpr (MFV) {
         // out[r][n] for the pair's cos and sin channels over this wave's 16
-        // columns; the window's ring rows 4(l/16)+v of each k-block are two
-        // aligned pair-rows (rslot_lag is a multiple of 8)
+        // columns; the window's ring rows 8(l/16)+v of each k-block are four
+        // aligned pair-rows (rslot_lag is a multiple of 8, the ring a
+        // multiple of 4 pair-rows).  Rows past the window (taps zero) wrap
+        // around the ring and read finite values.
         constexpr int RSP = ring_steps(RC, 0) * kB / 2;
-        static_assert((RSP - 4) + 8 * (KSV - 1) + 6 < 2 * RSP, "pair-row wrap");
+        static_assert(RSP % 4 == 0 && (RSP - 4) + 16 * (KSV - 1) + 12 < 3 * RSP, "pair-row wrap");
         const unsigned* colc = s_ring32 + (2 * mf_m) * TW + mf_x;
-        const int pb = rslot_lag / 2 + 2 * ((tid >> 4) & 3);
+        const int pb = rslot_lag / 2 + 4 * ((tid >> 4) & 3);
         f32x4_t dc = {0.0f, 0.0f, 0.0f, 0.0f}, ds = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int k = 0; k < KSV; ++k) {
-          int p = pb + 8 * k;
+          int p = pb + 16 * k;
           p = p >= RSP ? p - RSP : p;
           p = p >= RSP ? p - RSP : p;
           const unsigned* r0 = colc + p * RST;
-          dc = mfma16<PREC>(va[k], make_uint2(r0[0], r0[RST]), dc);
-          ds = mfma16<PREC>(va[k], make_uint2(r0[TW], r0[RST + TW]), ds);
+          dc = mfma32<PREC>(va[k], make_uint4(r0[0], r0[RST], r0[2 * RST], r0[3 * RST]), dc);
+          ds = mfma32<PREC>(va[k], make_uint4(r0[TW], r0[RST + TW], r0[2 * RST + TW], r0[3 * RST + TW]), ds);
         }
         if (mf_on) {
           const unsigned o = acc_lane + (unsigned)((s - lag) * B) * Wp;
