@@ -35,17 +35,17 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "4ed529447efcc6e6dd8257bef28119cce6850e8006815d5838f735d4dbdbd843",
-    "fp32": {"fetch_kib": 88837994, "write_kib": 67108864,
+    "sha256": "f5afd7cb666f05eb1216fe0a57498ce6de3d72739a8a461b674807e627407305",
+    "fp32": {"fetch_kib": 87993694, "write_kib": 67108864,
              # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
              # + SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 (matrix-core flops)
              "executed_flops": 70476914688 * 64 + 10838081536 * 512},
-    "fp16": {"fetch_kib": 100497703, "write_kib": 67108393,
+    "fp16": {"fetch_kib": 100525833, "write_kib": 67108282,
              # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
              # + SQ_INSTS_VALU_MFMA_MOPS_F16 x 512
              "executed_flops": (2717908992 + 5175820288) * 64
-                               + 33554432000 * 512},
-    "fetch_factor": 1048576 / 524306.8125,
+                               + 40265318400 * 512},
+    "fetch_factor": 1048576 / 524306.5625,
     "write_factor": 1048576 / 1048576.0,
 }
 
