@@ -173,17 +173,18 @@ def test_automatic_width():
     assert run(cuda(small), 3.0, C3, 2, 1, 12, "fp32", 32)[1].tile_w_used == 32
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
-def test_server_batches_with_wide_strips(precision):
+@pytest.mark.parametrize("precision,sigma", [("fp32", 3.0), ("fp32", 5.0), ("fp16", 3.0),
+                                             ("bf16", 5.0)])
+def test_server_batches_with_wide_strips(precision, sigma):
     say(f"case strips: serving scheduler (32 columns, one term per round) vs bf_vec_ex, "
-        f"three d = 3 requests, {precision}")
+        f"three d = 3 requests, {precision}, sigma_s={sigma} (R={O.window_radius(sigma)})")
     C = np.eye(3) * 0.12 ** 2
     imgs = [cuda(voronoi_image(256 + 8 * i, 300 + 20 * i, 3, 8, 0.0, 1.0, 0.02, 70 + i))
             for i in range(3)]
-    assert run(imgs[0], 3.0, C, 8, 4, 14, precision, 0)[1].tile_w_used == 32
-    refs = [run(g, 3.0, C, 8, 4, 14, precision, 0)[0] for g in imgs]
+    assert run(imgs[0], sigma, C, 8, 4, 14, precision, 0)[1].tile_w_used == 32
+    refs = [run(g, sigma, C, 8, 4, 14, precision, 0)[0] for g in imgs]
     with P.Server(quantum_us=1e-9) as srv:
-        subs = [srv.submit(g, 3.0, C, 8, 4, N=14, precision=precision) for g in imgs]
+        subs = [srv.submit(g, sigma, C, 8, 4, N=14, precision=precision) for g in imgs]
         for (t, out), ref in zip(subs, refs):
             st = srv.wait(t, 60.0)
             assert st["state"] == "done", st
