@@ -120,6 +120,12 @@ typedef struct bf_opts {
                       width changes no output bit.  bf_vec_ex, plans and the
                       server agree bit for bit at equal width.                */
   int tile_w_used; /* OUT: strip width the fused kernel ran with (16 or 32)   */
+  int valu_only;   /* 1: run both separable passes on the vector ALUs (FMA /
+                      v_dot2 sliding windows), never on the matrix cores; 0
+                      (default): matrix-core passes where tile_w describes
+                      them.  16-bit results are the same bits either way only
+                      up to rounding of the pass sums                       */
+  int mfma_used;   /* OUT: 1 if a pass ran on the matrix cores, else 0        */
 } bf_opts;
 
 /* Fill *o with the defaults (N auto, FP32, centring on, automatic tiles,
@@ -168,16 +174,25 @@ int bf_whiten_mode(int d, const double* C, int mode, double* W);
  * key (seed lo32, seed hi32) and counters (t, m, q, 0), q = 0, 1, ...; word
  * 4q + l of the stream is output lane l of counter q; bit i of the stream is
  * bit (i mod 32) of word (i div 32).  Y = N - 2X (eq. (finalApproxY));
- * w[t] = W^T Y[t] / sqrt(N) with W from bf_whiten.  Y (K x d int32) and w
- * (K x d float64) are host arrays; either may be NULL. */
-int bf_sample_terms(int d, const double* C, int N, int K, uint64_t seed,
+ * w[t] = W^T Y[t] / sqrt(N) with W = bf_whiten_mode(C, whiten), so these are
+ * exactly the terms bf_vec_ex draws with the same seed, N and opts.whiten.
+ * Y (K x d int32) and w (K x d float64) are host arrays; either may be NULL.
+ * BF_EINVAL for N or K outside [1, 65536] or an unknown whitening mode;
+ * BF_ENOTSPD as bf_whiten. */
+int bf_sample_terms(int d, const double* C, int N, int K, uint64_t seed, int whiten,
                     int32_t* Y, double* w);
 
-/* Order rule, host only: with spans s_m = hi[m] - lo[m] and T = max_k
- * sum_m |W_km| s_m (the largest whitened difference in the image), N is the
- * smallest integer with pi*sqrt(N) >= T + 4, and at least 10.  lo/hi are host
- * arrays of d floats.  BF_EUNSUPPORTED if that N exceeds 65536. */
-int bf_choose_N(int d, const double* W, const float* lo, const float* hi, int* N);
+/* Order rule, host only.  The raised cosine cos(z/sqrt(N))^N of eq. (approx)
+ * approximates exp(-z^2/2) (Proposition 1) only for |z| < pi sqrt(N): at
+ * z = pi sqrt(N) it aliases back to magnitude one.  With W =
+ * bf_whiten_mode(C, whiten), spans s_m = hi[m] - lo[m] and T = max_k sum_m
+ * |W_km| s_m (the largest whitened difference between two pixels of the
+ * image), N is the smallest integer with pi*sqrt(N) >= T + 4 (the alias lobe
+ * stays below exp(-8) over the data range), and at least 10, the paper's
+ * order.  lo/hi: host arrays of d floats (finite, lo <= hi), as bf_minmax
+ * returns them.  BF_EINVAL for bad arguments, BF_ENOTSPD as bf_whiten,
+ * BF_EUNSUPPORTED if that N exceeds 65536. */
+int bf_choose_N(int d, const double* C, const float* lo, const float* hi, int whiten, int* N);
 
 /* Per-channel minimum and maximum of a device HWC image, written to host
  * arrays lo/hi (d floats each).  Synchronous on `stream` (NULL = null

@@ -83,6 +83,8 @@ class bf_opts(ctypes.Structure):
         ("whiten", ctypes.c_int),
         ("tile_w", ctypes.c_int),
         ("tile_w_used", ctypes.c_int),
+        ("valu_only", ctypes.c_int),
+        ("mfma_used", ctypes.c_int),
     ]
 
 
@@ -171,8 +173,8 @@ def lib():
     L.bf_vec_terms.argtypes = [P, I, I, I, D, P, P, I, P, ctypes.POINTER(bf_opts)]
     L.bf_whiten.argtypes = [I, P, P]
     L.bf_whiten_mode.argtypes = [I, P, I, P]
-    L.bf_sample_terms.argtypes = [I, P, I, I, U64, P, P]
-    L.bf_choose_N.argtypes = [I, P, P, P, ctypes.POINTER(I)]
+    L.bf_sample_terms.argtypes = [I, P, I, I, U64, I, P, P]
+    L.bf_choose_N.argtypes = [I, P, P, P, I, ctypes.POINTER(I)]
     L.bf_minmax.argtypes = [P, I, I, I, P, P, P]
     L.bf_direct.argtypes = [P, I, I, I, D, P, P]
     L.bf_autotune.argtypes = [P, I, I, I, D, I, P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float)]
@@ -238,7 +240,7 @@ def _check_image(f, out):
 
 def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
               num_out=None, z_out=None, time_kernel=False, dedup=False, spatial="gauss",
-              whiten="eig", tile_w=0):
+              whiten="eig", tile_w=0, valu_only=False):
     o = bf_opts()
     lib().bf_opts_init(ctypes.byref(o))
     o.N = int(N)
@@ -253,6 +255,7 @@ def make_opts(N=0, precision="fp32", center=True, tile_h=0, stream=None,
     o.spatial = _spatial(spatial)
     o.whiten = _whiten_mode(whiten)
     o.tile_w = int(tile_w)
+    o.valu_only = 1 if valu_only else 0
     return o
 
 
@@ -275,26 +278,29 @@ def bf_vec(f, sigma_s, C, K, seed, out=None):
 
 def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
               tile_h=0, stream=None, num_out=None, z_out=None, time_kernel=False,
-              return_opts=False, dedup=False, spatial="gauss", whiten="eig", tile_w=0):
+              return_opts=False, dedup=False, spatial="gauss", whiten="eig", tile_w=0,
+              valu_only=False):
     """The filter with options, queued on ``stream`` (torch stream; default:
     current stream).  Returns (out, N_used), or (out, opts) with
     ``return_opts`` (opts.kernel_ms holds the fused-kernel time when
     ``time_kernel`` is set; opts.K_used the number of kernel terms, fewer than
     K with ``dedup``; opts.tile_h_used / tile_w_used the strip shape).
     ``spatial``: "gauss" (default), "box", "hat", "box3"; ``whiten``: "eig"
-    (default), "chol", "sym"; ``tile_w``: strip width 0 (auto), 16 or 32."""
+    (default), "chol", "sym"; ``tile_w``: strip width 0 (auto), 16 or 32;
+    ``valu_only``: both passes on the vector ALUs (no matrix cores)."""
     out = _check_image(f, out)
     H, W, d = f.shape
     Ch = _host_f64(C, (d, d))
     o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  time_kernel, dedup, spatial, whiten, tile_w)
+                  time_kernel, dedup, spatial, whiten, tile_w, valu_only)
     _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
     return (out, o) if return_opts else (out, o.N_used)
 
 
 def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center=True,
-                 tile_h=0, stream=None, num_out=None, z_out=None, spatial="gauss", tile_w=0):
+                 tile_h=0, stream=None, num_out=None, z_out=None, spatial="gauss", tile_w=0,
+                 valu_only=False):
     """The filter with an explicit (K, d) float64 term table and optional
     weights.  Returns out."""
     out = _check_image(f, out)
@@ -305,7 +311,7 @@ def bf_vec_terms(f, sigma_s, w, weights=None, out=None, precision="fp32", center
     K = wh.shape[0]
     wt = None if weights is None else _host_f64(weights, (K,))
     o = make_opts(0, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
-                  spatial=spatial, tile_w=tile_w)
+                  spatial=spatial, tile_w=tile_w, valu_only=valu_only)
     _check(lib().bf_vec_terms(f.data_ptr(), H, W, d, float(sigma_s), _ptr(wh),
                               None if wt is None else _ptr(wt), K, out.data_ptr(),
                               ctypes.byref(o)))
@@ -322,25 +328,29 @@ def bf_whiten(C, mode="eig"):
     return W
 
 
-def bf_sample_terms(C, N, K, seed):
-    """Host draws: returns (Y int32 (K, d), w float64 (K, d))."""
+def bf_sample_terms(C, N, K, seed, whiten="eig"):
+    """Host draws with the given whitening: returns (Y int32 (K, d),
+    w float64 (K, d))."""
     Ch = _host_f64(C)
     d = Ch.shape[0]
     Y = np.empty((K, d), dtype=np.int32)
     w = np.empty((K, d))
     _check(lib().bf_sample_terms(d, _ptr(Ch), int(N), int(K),
-                                 int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(Y), _ptr(w)))
+                                 int(seed) & 0xFFFFFFFFFFFFFFFF, _whiten_mode(whiten),
+                                 _ptr(Y), _ptr(w)))
     return Y, w
 
 
-def bf_choose_N(W, lo, hi):
-    """Host order rule from the whitening and per-channel extrema."""
-    Wh = _host_f64(W)
-    d = Wh.shape[0]
-    lo32 = np.ascontiguousarray(np.asarray(lo, dtype=np.float32))
-    hi32 = np.ascontiguousarray(np.asarray(hi, dtype=np.float32))
+def bf_choose_N(C, lo, hi, whiten="eig"):
+    """Host order rule from the covariance, the whitening mode and the
+    per-channel extrema."""
+    Ch = _host_f64(C)
+    d = Ch.shape[0]
+    lo32 = np.ascontiguousarray(np.asarray(lo, dtype=np.float32).reshape(d))
+    hi32 = np.ascontiguousarray(np.asarray(hi, dtype=np.float32).reshape(d))
     N = ctypes.c_int(0)
-    _check(lib().bf_choose_N(d, _ptr(Wh), _ptr(lo32), _ptr(hi32), ctypes.byref(N)))
+    _check(lib().bf_choose_N(d, _ptr(Ch), _ptr(lo32), _ptr(hi32), _whiten_mode(whiten),
+                             ctypes.byref(N)))
     return N.value
 
 
@@ -383,10 +393,11 @@ class Plan:
     HIP graph launch per image.  ``N`` must be explicit."""
 
     def __init__(self, H, W, d, sigma_s, C, K, seed, N, precision="fp32", center=True,
-                 tile_h=0, dedup=False, spatial="gauss", whiten="eig", tile_w=0):
+                 tile_h=0, dedup=False, spatial="gauss", whiten="eig", tile_w=0,
+                 valu_only=False):
         Ch = _host_f64(C, (d, d))
         o = make_opts(N, precision, center, tile_h, None, None, None, False, dedup, spatial,
-                      whiten, tile_w)
+                      whiten, tile_w, valu_only)
         h = ctypes.c_void_p()
         _check(lib().bf_plan_create(int(H), int(W), int(d), float(sigma_s), _ptr(Ch), int(K),
                                     int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(o),
@@ -395,6 +406,7 @@ class Plan:
         self.shape = (int(H), int(W), int(d))
         self.N_used, self.K_used, self.tile_h_used = o.N_used, o.K_used, o.tile_h_used
         self.tile_w_used = o.tile_w_used
+        self.mfma_used = o.mfma_used
 
     def __call__(self, f, out=None, stream=None):
         """Queue the filter of f into out on ``stream`` (default: current

@@ -154,6 +154,7 @@ int check_opts(const bf_opts* o) {
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
   if (o->whiten < BF_WHITEN_EIG || o->whiten > BF_WHITEN_SYM)
     return fail(BF_EINVAL, "opts.whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
+  if (o->valu_only != 0 && o->valu_only != 1) return fail(BF_EINVAL, "opts.valu_only must be 0 or 1");
   return check_spatial(o->spatial, o->precision);
 }
 
@@ -216,6 +217,15 @@ void fused_geometry(FusedArgs& a, int H, int W, int R, int prec, int TH, int vbo
 size_t fused_acc_floats(const FusedArgs& a, int d) {
   return (size_t)(d + 1) * a.Hp * a.nsx * a.TWc;
 }
+
+int check_acc_size(const FusedArgs& a, int d) {
+  // the kernels form accumulator offsets as 32-bit byte offsets
+  if ((double)(d + 1) * (double)a.Hp * (double)a.nsx * (double)a.TWc >= 1073741824.0 - 65536.0)
+    return fail(BF_EUNSUPPORTED,
+                "accumulators too large: (d+1) x padded rows x padded columns must stay below 2^30");
+  return BF_OK;
+}
+
 
 std::vector<float> term_table(int d, int K, const double* w, const double* weights,
                               double sigma_s, size_t* off_weights, size_t* off_taps, int spatial) {
@@ -295,7 +305,10 @@ int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH, i
   if (rc) return rc;
   const int v = kernel_variant(o->precision, o->spatial);
   if ((rc = choose_strip_width(d, R, v, H, W, o->tile_w, TW))) return rc;
-  return choose_strip_height(d, R, v, H, W, o->tile_h, TH, *TW);
+  if ((rc = choose_strip_height(d, R, v, H, W, o->tile_h, TH, *TW, o->valu_only))) return rc;
+  FusedArgs g{};   // the padded accumulators of this geometry must fit 32-bit offsets
+  fused_geometry(g, H, W, R, v, *TH, v == 3 ? spatial_boxes(o->spatial) : 0, *TW);
+  return check_acc_size(g, d);
 }
 
 // Launch the fused filter for a host FP64 term table (radians per unit).
@@ -320,8 +333,16 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = K;
+  a.valu = o->valu_only;
+  int rc = check_acc_size(a, d);
+  if (rc) return rc;
+  if (o->precision == BF_FP16) {
+    if (!lo) return fail(BF_EINVAL, "FP16 storage needs the image range (internal)");
+    if ((rc = check_fp16_range(d, sigma_s, spatial_boxes(o->spatial), lo, hi, a.cen))) return rc;
+  }
   o->tile_h_used = a.TH;
   o->tile_w_used = a.TWc;
+  o->mfma_used = fused_uses_mf(d, R, variant, a.TWc, a.valu);
 
   // one stream-ordered allocation: accumulators | terms | weights | taps
   const size_t n_acc = fused_acc_floats(a, d);
@@ -453,7 +474,8 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   int TH = 0, TW = 0;
   if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
   float lo[8] = {0}, hi[8] = {0};
-  const bool have_range = o->N == 0 || o->center;
+  // the order rule, centring and the FP16 range check need the extrema
+  const bool have_range = o->N == 0 || o->center || o->precision == BF_FP16;
   if (have_range) {
     if ((rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   }
@@ -507,11 +529,12 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const doub
   int TH = 0, TW = 0;
   if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
   float lo[8] = {0}, hi[8] = {0};
-  if (o->center && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
+  const bool have_range = o->center || o->precision == BF_FP16;
+  if (have_range && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   o->N_used = o->N;
   o->K_used = K;
-  return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, o->center ? lo : nullptr,
-                   o->center ? hi : nullptr, TH, TW);
+  return run_terms(f, H, W, d, sigma_s, w, weights, K, out, o, have_range ? lo : nullptr,
+                   have_range ? hi : nullptr, TH, TW);
 }
 
 int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precision, void* stream,
@@ -539,10 +562,20 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   // candidate strip counts down the image around the model's
   const int nsy0 = (H + model - 1) / model, nmax = (H + kB - 1) / kB;
   std::vector<int> ths;
+  auto acc_fits = [&](int th) {   // check_acc_size's rule, without setting an error
+    FusedArgs g{};
+    fused_geometry(g, H, W, R, precision, th, 0, TW);
+    return (double)fused_acc_floats(g, d) < 1073741824.0 - 65536.0;
+  };
+  if (!acc_fits(model)) {
+    FusedArgs g{};
+    fused_geometry(g, H, W, R, precision, model, 0, TW);
+    return check_acc_size(g, d);
+  }
   for (int f10 : {3, 5, 7, 10, 13, 15, 20, 30, 40}) {
     const int nsy = std::min(nmax, std::max(1, (nsy0 * f10 + 5) / 10));
     const int th = effective(((H + nsy - 1) / nsy + kB - 1) / kB * kB);
-    if (std::find(ths.begin(), ths.end(), th) == ths.end()) ths.push_back(th);
+    if (acc_fits(th) && std::find(ths.begin(), ths.end(), th) == ths.end()) ths.push_back(th);
   }
   // probe terms: a few fixed frequencies (the cost does not depend on them)
   constexpr int KP = 4;

@@ -253,6 +253,23 @@ int choose_order(int d, const double* W, const float* lo, const float* hi, int* 
   return BF_OK;
 }
 
+int check_fp16_range(int d, double sigma_s, int spatial, const float* lo, const float* hi,
+                     const float* cen) {
+  // FP16 storage holds c (f - c_m), s (f - c_m), cos, sin and their
+  // horizontal-pass sums: |value| <= max(1, max_m |f_m - c_m|) * sum_u omega_1(u)
+  const std::vector<double> taps = spatial_taps(sigma_s, spatial);
+  double sw = 0.0;
+  for (double t : taps) sw += t;
+  double dev = 1.0;
+  for (int m = 0; m < d; ++m)
+    dev = std::max(dev, std::max((double)hi[m] - (double)cen[m], (double)cen[m] - (double)lo[m]));
+  if (dev * sw > kFP16Limit)
+    return fail(BF_EUNSUPPORTED,
+                "image range too wide for FP16 storage: max |f - c| x sum(omega_1) = " +
+                    std::to_string(dev * sw) + " exceeds 32768; use BF_BF16 or BF_FP32");
+  return BF_OK;
+}
+
 int check_common(const void* f, int H, int W, int d, double sigma_s, const void* out) {
   if (!f || !out) return fail(BF_EINVAL, "f and out must be non-null device pointers");
   if (H < 1 || W < 1 || H > 65536 || W > 65536)
@@ -299,13 +316,15 @@ int bf_whiten_mode(int d, const double* C, int mode, double* W) {
   return bfvec::whiten(d, C, W, mode);
 }
 
-int bf_sample_terms(int d, const double* C, int N, int K, uint64_t seed, int32_t* Y,
+int bf_sample_terms(int d, const double* C, int N, int K, uint64_t seed, int whiten, int32_t* Y,
                     double* w) {
   bfvec::clear_error();
   if (N < 1 || N > 65536) return bfvec::fail(BF_EINVAL, "N must be in [1, 65536]");
   if (K < 1 || K > 65536) return bfvec::fail(BF_EINVAL, "K must be in [1, 65536]");
+  if (whiten < BF_WHITEN_EIG || whiten > BF_WHITEN_SYM)
+    return bfvec::fail(BF_EINVAL, "whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
   double Wm[64];
-  int st = bfvec::whiten(d, C, Wm);
+  int st = bfvec::whiten(d, C, Wm, whiten);
   if (st) return st;
   const double sqn = std::sqrt((double)N);
   for (int t = 0; t < K; ++t) {
@@ -323,11 +342,19 @@ int bf_sample_terms(int d, const double* C, int N, int K, uint64_t seed, int32_t
   return BF_OK;
 }
 
-int bf_choose_N(int d, const double* W, const float* lo, const float* hi, int* N) {
+int bf_choose_N(int d, const double* C, const float* lo, const float* hi, int whiten, int* N) {
   bfvec::clear_error();
   if (d < 1 || d > 8) return bfvec::fail(BF_EINVAL, "d must be in [1, 8]");
-  if (!W || !lo || !hi || !N) return bfvec::fail(BF_EINVAL, "null argument");
-  return bfvec::choose_order(d, W, lo, hi, N);
+  if (!C || !lo || !hi || !N) return bfvec::fail(BF_EINVAL, "null argument");
+  if (whiten < BF_WHITEN_EIG || whiten > BF_WHITEN_SYM)
+    return bfvec::fail(BF_EINVAL, "whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
+  for (int m = 0; m < d; ++m)
+    if (!std::isfinite(lo[m]) || !std::isfinite(hi[m]) || hi[m] < lo[m])
+      return bfvec::fail(BF_EINVAL, "lo/hi must be finite with lo <= hi");
+  double Wm[64];
+  int st = bfvec::whiten(d, C, Wm, whiten);
+  if (st) return st;
+  return bfvec::choose_order(d, Wm, lo, hi, N);
 }
 
 }  // extern "C"

@@ -42,6 +42,16 @@ int binomial_draw(uint64_t seed, int t, int m, int N);
 // Order rule; see bf_choose_N.
 int choose_order(int d, const double* W, const float* lo, const float* hi, int* N);
 
+// FP16 storage range: the stored channels c (f_m - c_m), s (f_m - c_m), cos,
+// sin and their horizontal-pass sums are bounded by
+// max(1, max_m |f_m - c_m|) * sum_u omega_1(u) (|cos|, |sin| <= 1; the taps
+// are positive).  Above kFP16Limit (half the FP16 maximum, 65504) a launch
+// is refused: BF_EUNSUPPORTED with the message set.  lo/hi: the image's
+// per-channel extrema; cen: the centre subtracted before the phase.
+constexpr double kFP16Limit = 32768.0;
+int check_fp16_range(int d, double sigma_s, int spatial, const float* lo, const float* hi,
+                     const float* cen);
+
 // Argument validation shared by the entry points.
 int check_common(const void* f, int H, int W, int d, double sigma_s, const void* out);
 

@@ -40,11 +40,12 @@ inline constexpr int stage_width16(int R, int TW = kTW) {
   const int dw = (TW + 2 * R + 4 + 3) / 4 * 2;   // dwords, even (64-bit aligned rows)
   return 2 * (dw % 16 == 0 ? dw + 2 : dw);
 }
-// Staging row width of the matrix-core passes (32-column strips, 16-bit
-// storage): the banded product reads 16 + 16*ceil((16 + 2R)/16) samples per
-// row (two 16-column output blocks, k-blocks of 16; at least the TW + 2R
-// modulated ones), plus 4 so that the row stride is 2 mod 4 dwords: the 16
-// rows one operand read touches then fall on distinct LDS banks.
+// Staging row width of the matrix-core passes (16-bit storage, either
+// strip width): the banded product reads 16 + 32*ceil((16 + 2R)/32) samples
+// per row (16-column output blocks, k-blocks of 32 samples; at least the
+// TW + 2R modulated ones), plus 8 elements so that the row stride is 4 mod 8
+// dwords: the 16 rows one 128-bit operand read touches then spread over the
+// LDS banks.
 inline constexpr int stage_width_mf(int R) { return 16 + 32 * ((16 + 2 * R + 31) / 32) + 8; }
 // Pair-row padding of the 16-bit ring for the matrix-core vertical pass, in
 // dwords: the four 16-lane groups of an operand read sit 2 pair-rows apart,
@@ -109,6 +110,7 @@ struct FusedArgs {
   int p64;               // 1: instance with the FP64 phase path (phase bound unknown or
                          // above kPhaseBound), 0: without it
   float wmax[8];         // max_t |w_tm / 2pi| over the table's FP32 values
+  int valu;              // 1: no matrix-core passes (the VALU instance of this width)
 };
 
 // Host side of the FP64-phase decision: 1 unless the per-channel ranges
@@ -140,8 +142,11 @@ struct FinalizeArgs {
 // storage, 2 = BF16 storage (FP32 accumulation), 3 = FP32 with the
 // running-sum vertical pass; TW: strip width
 size_t fused_lds_bytes(int d, int R, int prec, int TW = kTW, int mf = 0);
-// resident workgroups per compute unit for this kernel instance (device query)
-int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW);
+// resident workgroups per compute unit for this kernel instance (device query);
+// valu = 1: the instance without matrix-core passes
+int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW, int valu = 0);
+// 1 if a launch of this (d, R, variant, width) runs a pass on the matrix cores
+int fused_uses_mf(int d, int R, int prec, int TW, int valu);
 // Strip width for a launch into *TW.  requested: kTW or kTWMax forces it
 // (kTWMax needs a wide-strip instance: d = 3, a specialised radius, variants
 // 0-2, W >= kTWMax; else BF_EUNSUPPORTED); 0 picks kTWMax where such an
@@ -172,10 +177,15 @@ hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* 
 int check_fused_size(int H, int W, int pitch, int d, int R);
 // Strip height: requested > 0 forces it; otherwise a height measured by
 // bf_autotune for this device and shape, else the occupancy model.
+// The height is at most the image height rounded up to kB rows (one strip).
 int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH,
-                        int TW = kTW);
+                        int TW = kTW, int valu = 0);
 // The occupancy model alone: minimises (waves of workgroups) x (rows + halo).
-int model_strip_height(int d, int R, int prec, int H, int W, int TW = kTW);
+int model_strip_height(int d, int R, int prec, int H, int W, int TW = kTW, int valu = 0);
+// BF_EUNSUPPORTED (message set) if the planned accumulators of a (after
+// fused_geometry) need 32-bit element offsets of 2^30 or more.
+int check_acc_size(const FusedArgs& a, int d);
+
 // Process-wide table of measured strip heights, keyed by the current device,
 // d, R, precision, the image shape and the strip width.
 void record_tuned_height(int d, int R, int prec, int H, int W, int TH, int TW = kTW);

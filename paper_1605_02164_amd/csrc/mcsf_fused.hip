@@ -58,19 +58,19 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
 // each); a workgroup of (D+1)*TW/16 waves puts a quarter of them, rounded
 // up, on a SIMD.
 template <int D, int RC, int PREC>
-static int blocks_per_cu_drp(int R, int TW) {
+static int blocks_per_cu_drp(int R, int TW, int valu) {
   // the instance launch_drp picks for this width
   int mf = 0;
   const void* kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false>);
   if constexpr (kHasMF<D, RC, PREC, kTW>)
-    if (TW == kTW && use_mf(TW, PREC, R)) {
+    if (TW == kTW && use_mf(TW, PREC, R) && !valu) {
       kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTW, true>);
       mf = 1;
     }
   if constexpr (kHasWide<D, RC, PREC>)
     if (TW == kTWMax) kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax>);
   if constexpr (kHasMF<D, RC, PREC, kTWMax>)
-    if (TW == kTWMax && use_mf(TW, PREC, R)) {
+    if (TW == kTWMax && use_mf(TW, PREC, R) && !valu) {
       kern = reinterpret_cast<const void*>(mcsf_fused<D, RC, PREC, false, kTWMax, true>);
       mf = 1;
     }
@@ -86,31 +86,31 @@ static int blocks_per_cu_drp(int R, int TW) {
 }
 
 template <int D, int PREC>
-static int bpc_dp(int R, int TW) {
+static int bpc_dp(int R, int TW, int valu) {
   switch (R) {
-    case 6: return blocks_per_cu_drp<D, 6, PREC>(R, TW);
-    case 9: return blocks_per_cu_drp<D, 9, PREC>(R, TW);
-    case 12: return blocks_per_cu_drp<D, 12, PREC>(R, TW);
-    case 15: return blocks_per_cu_drp<D, 15, PREC>(R, TW);
-    case 18: return blocks_per_cu_drp<D, 18, PREC>(R, TW);
-    case 21: return blocks_per_cu_drp<D, 21, PREC>(R, TW);
-    case 24: return blocks_per_cu_drp<D, 24, PREC>(R, TW);
-    case 30: return blocks_per_cu_drp<D, 30, PREC>(R, TW);
-    default: return blocks_per_cu_drp<D, -1, PREC>(R, TW);
+    case 6: return blocks_per_cu_drp<D, 6, PREC>(R, TW, valu);
+    case 9: return blocks_per_cu_drp<D, 9, PREC>(R, TW, valu);
+    case 12: return blocks_per_cu_drp<D, 12, PREC>(R, TW, valu);
+    case 15: return blocks_per_cu_drp<D, 15, PREC>(R, TW, valu);
+    case 18: return blocks_per_cu_drp<D, 18, PREC>(R, TW, valu);
+    case 21: return blocks_per_cu_drp<D, 21, PREC>(R, TW, valu);
+    case 24: return blocks_per_cu_drp<D, 24, PREC>(R, TW, valu);
+    case 30: return blocks_per_cu_drp<D, 30, PREC>(R, TW, valu);
+    default: return blocks_per_cu_drp<D, -1, PREC>(R, TW, valu);
   }
 }
 
 template <int PREC>
-static int bpc_p(int d, int R, int TW) {
+static int bpc_p(int d, int R, int TW, int valu) {
   switch (d) {
-    case 1: return blocks_per_cu_drp<1, -1, PREC>(R, TW);
-    case 2: return blocks_per_cu_drp<2, -1, PREC>(R, TW);
-    case 3: return bpc_dp<3, PREC>(R, TW);
-    case 4: return blocks_per_cu_drp<4, -1, PREC>(R, TW);
-    case 5: return blocks_per_cu_drp<5, -1, PREC>(R, TW);
-    case 6: return bpc_dp<6, PREC>(R, TW);
-    case 7: return blocks_per_cu_drp<7, -1, PREC>(R, TW);
-    default: return blocks_per_cu_drp<8, -1, PREC>(R, TW);
+    case 1: return blocks_per_cu_drp<1, -1, PREC>(R, TW, valu);
+    case 2: return blocks_per_cu_drp<2, -1, PREC>(R, TW, valu);
+    case 3: return bpc_dp<3, PREC>(R, TW, valu);
+    case 4: return blocks_per_cu_drp<4, -1, PREC>(R, TW, valu);
+    case 5: return blocks_per_cu_drp<5, -1, PREC>(R, TW, valu);
+    case 6: return bpc_dp<6, PREC>(R, TW, valu);
+    case 7: return blocks_per_cu_drp<7, -1, PREC>(R, TW, valu);
+    default: return blocks_per_cu_drp<8, -1, PREC>(R, TW, valu);
   }
 }
 
@@ -122,13 +122,19 @@ static bool specialised_radius(int R) {
   }
 }
 
-int fused_blocks_per_cu(int d, int R, int prec, int TW) {
+int fused_blocks_per_cu(int d, int R, int prec, int TW, int valu) {
   switch (prec) {
-    case 0: return bpc_p<0>(d, R, TW);
-    case 1: return bpc_p<1>(d, R, TW);
-    case 2: return bpc_p<2>(d, R, TW);
-    default: return bpc_p<3>(d, R, TW);
+    case 0: return bpc_p<0>(d, R, TW, valu);
+    case 1: return bpc_p<1>(d, R, TW, valu);
+    case 2: return bpc_p<2>(d, R, TW, valu);
+    default: return bpc_p<3>(d, R, TW, valu);
   }
+}
+
+int fused_uses_mf(int d, int R, int prec, int TW, int valu) {
+  if (valu || !specialised_radius(R) || (d != 3 && d != 6) || prec > 2) return 0;
+  const bool inst = TW == kTWMax ? d == 3 : (prec == 1 || prec == 2);
+  return inst && use_mf(TW, prec, R) ? 1 : 0;
 }
 
 int choose_strip_width(int d, int R, int prec, int H, int W, int requested, int* TW) {
@@ -193,25 +199,29 @@ int tuned_height(int d, int R, int prec, int H, int W, int TW) {
   return it == g_tuned.end() ? 0 : it->second;
 }
 
-int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH, int TW) {
+int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH, int TW,
+                        int valu) {
   if (fused_lds_bytes(d, R, prec, TW) > 160 * 1024)
     return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
+  // one strip covers the image: taller strips only add padded rows (and
+  // would push accumulator offsets past 32 bits for huge requests)
+  const int one = (H + kB - 1) / kB * kB;
   if (requested > 0) {
-    *TH = (requested + kB - 1) / kB * kB;
+    *TH = (int)std::min<long>(((long)requested + kB - 1) / kB * kB, one);
     return BF_OK;
   }
-  if ((*TH = tuned_height(d, R, prec, H, W, TW)) > 0) return BF_OK;
-  *TH = model_strip_height(d, R, prec, H, W, TW);
+  if (!valu && (*TH = tuned_height(d, R, prec, H, W, TW)) > 0) return BF_OK;
+  *TH = std::min(model_strip_height(d, R, prec, H, W, TW, valu), one);
   return BF_OK;
 }
 
-int model_strip_height(int d, int R, int prec, int H, int W, int TW) {
+int model_strip_height(int d, int R, int prec, int H, int W, int TW, int valu) {
   const int nsx = (W + TW - 1) / TW;
   // resident workgroups on the GPU
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int slots = fused_blocks_per_cu(d, R, prec, TW) * std::max(ncu, 1);
+  const int slots = fused_blocks_per_cu(d, R, prec, TW, valu) * std::max(ncu, 1);
   const int halo = lag_steps(R) * kB;
   // The accumulators of the resident workgroups are read and written once
   // per term.  On the 4096^2 workload, strips half as tall (two waves of

@@ -22,16 +22,18 @@
 //      adding into planar accumulators in device memory (Algorithm 1, P and Z).
 // A separate finalize kernel divides (Algorithm 1, last step).
 //
-// Work per output pixel and term: 2(d+1)(2R+1) FMAs per pass.  Both passes
-// are register-blocked sliding windows over LDS (4 outputs per item).  With
-// R fixed at compile time the window loops unroll completely and the taps
-// live in registers; a runtime-R variant serves every other radius.  No
-// MFMA: the passes are stencils.  LDS stays near 70 KB so two workgroups
-// share a compute unit.
+// Work per output pixel and term: 2(d+1)(2R+1) FMAs per pass.  On the VALU
+// both passes are register-blocked sliding windows over LDS (4 outputs per
+// item).  With R fixed at compile time the window loops unroll completely
+// and the taps live in registers; a runtime-R variant serves every other
+// radius.  At the compile-time radii the passes can also run as banded
+// (Toeplitz) matrix products on the matrix cores (MF instances, below): both
+// passes with 16-bit storage, the horizontal pass of 32-column FP32 strips.
+// A VALU instance of every width stays available (bf_opts.valu_only).
 //
 // Low-precision variants (PREC 1 = FP16, 2 = BF16) store the modulated
-// channels and the horizontal-pass rows as 16-bit pairs and run both passes
-// with v_dot2_f32_{f16,bf16}: two taps times two adjacent samples added into
+// channels and the horizontal-pass rows as 16-bit pairs; their VALU passes
+// use v_dot2_f32_{f16,bf16}: two taps times two adjacent samples added into
 // an FP32 accumulator.  With the taps split by parity, output 2q takes
 // (w[2i], w[2i+1]) against samples (2q+2i, 2q+2i+1) and output 2q+1 takes
 // (w[2i-1], w[2i]) against the same aligned pair, so every window read is an
@@ -142,12 +144,6 @@ __device__ __forceinline__ unsigned pack2(float lo, float hi) {
   else return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
-// 16x16x16 matrix-core product with 16-bit inputs and FP32 accumulation:
-// d += a b, a 16x16 (M x K), b 16x16 (K x N).  Lane l holds a[l%16][4(l/16)+v],
-// b[4(l/16)+v][l%16] (v = 0..3, four 16-bit values in a uint2) and
-// d[4(l/16)+v][l%16].
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 // 16x16x4 FP32 product: lane l holds a[l%16][l/16], b[l/16][l%16] and d as
 // above.
@@ -167,16 +163,6 @@ __device__ __forceinline__ f32x4_t mfma32(uint4 a, uint4 b, f32x4_t d) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
                                                    __builtin_bit_cast(bf16x8_t, b), d, 0, 0, 0);
 }
-template <int PREC>
-__device__ __forceinline__ f32x4_t mfma16(uint2 a, uint2 b, f32x4_t d) {
-  if constexpr (PREC == 1)
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(half4_t, a),
-                                                 __builtin_bit_cast(half4_t, b), d, 0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, a),
-                                                     __builtin_bit_cast(short4_t, b), d, 0, 0, 0);
-}
-
 // Four outputs (p = 0..3, starting at an even sample) of a 2R+1-tap window
 // over aligned sample pairs x2[j] = (x[2j], x[2j+1]):
 //   out[2q]   = sum_i te[i] . x2[q+i],   te[i] = (w[2i],   w[2i+1])
@@ -463,11 +449,12 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     tpo[i] = v;
   }
   // Matrix-core passes: constant tap operands of the banded products.
-  // Horizontal: out[m][x] = sum_j stage[m][j] w[j - x] over k-blocks of 16
+  // Horizontal: out[m][x] = sum_j stage[m][j] w[j - x] over k-blocks of 32
   // samples (KSH of them cover 16 + 2R); this lane holds the B rows
-  // k = 4(l/16)+v of column x = l%16.  Vertical: out[r][n] = sum_i w[i - r]
-  // ring[i][n] over KSV k-blocks covering B + 2R ring rows; this lane holds the
-  // A row r = l%16 (rows 8-15 zero: a step has 8 output rows).
+  // k = 8(l/16)+v (v = 0..7) of column x = l%16.  Vertical: out[r][n] =
+  // sum_i w[i - r] ring[i][n] over KSV k-blocks of 32 covering B + 2R ring
+  // rows; this lane holds the A row r = l%16 (rows 8-15 zero: a step has 8
+  // output rows).  FP32 horizontal pass: k-blocks of 4 samples.
   constexpr int KSH = MFV ? (16 + 2 * RC + 31) / 32 : 1;
   constexpr int KSV = MFV ? (kB + 2 * RC + 31) / 32 : 1;
   // FP32 horizontal pass: k-blocks of 4 samples, one tap per lane and block
@@ -973,11 +960,14 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
   int nwg, TW = kTW;
   void (*kern)(A);
   int mf = 0;
-  const bool want_mf = use_mf(a_tw(a), PREC, R);
-  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64 and the strip width
+  bool want_mf = use_mf(a_tw(a), PREC, R);
+  if constexpr (std::is_same_v<A, BatchArgs>) {   // the batch shares p64, valu and the width
     const bool p64 = a.req[0].p64;
     for (int k = 1; k < a.n; ++k)
-      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc) return hipErrorInvalidValue;
+      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != a.req[0].TWc ||
+          a.req[k].valu != a.req[0].valu)
+        return hipErrorInvalidValue;
+    want_mf = want_mf && !a.req[0].valu;
     kern = p64 ? mcsf_fused_batch<D, RC, PREC, true> : mcsf_fused_batch<D, RC, PREC, false>;
     if constexpr (kHasMF<D, RC, PREC, kTW>) {
       if (want_mf) {
@@ -1004,6 +994,7 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
     if (a.req[0].TWc != TW) return hipErrorInvalidValue;   // no instance for this width
     nwg = a.first[a.n];
   } else {
+    want_mf = want_mf && !a.valu;
     kern = a.p64 ? mcsf_fused<D, RC, PREC, true> : mcsf_fused<D, RC, PREC, false>;
     if constexpr (kHasMF<D, RC, PREC, kTW>) {
       if (want_mf) {

@@ -139,6 +139,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
     return fail(BF_EINVAL, "opts.whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
   if (o->num_out || o->z_out || o->time_kernel)
     return fail(BF_EINVAL, "plans take no num_out, z_out or time_kernel");
+  if (o->valu_only != 0 && o->valu_only != 1) return fail(BF_EINVAL, "opts.valu_only must be 0 or 1");
   double Wm[64];
   if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
@@ -146,7 +147,12 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;
   int TH = 0, TW = 0;
   if ((rc = choose_strip_width(d, R, variant, H, W, o->tile_w, &TW))) return rc;
-  if ((rc = choose_strip_height(d, R, variant, H, W, o->tile_h, &TH, TW))) return rc;
+  if ((rc = choose_strip_height(d, R, variant, H, W, o->tile_h, &TH, TW, o->valu_only))) return rc;
+  {
+    FusedArgs g{};
+    fused_geometry(g, H, W, R, variant, TH, variant == 3 ? spatial_boxes(o->spatial) : 0, TW);
+    if ((rc = check_acc_size(g, d))) return rc;
+  }
 
   // the terms, exactly as bf_vec_ex draws them
   const int N = o->N;
@@ -175,6 +181,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   a.fpitch = W;
   a.t0 = 0;
   a.t1 = Kr;
+  a.valu = o->valu_only;
   const size_t n_acc = fused_acc_floats(a, d);
   p->nparts = minmax_parts((size_t)H * W);
   const size_t n_mm = o->center ? (size_t)p->nparts * 17 + kMMResult : 0;
@@ -204,6 +211,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   o->K_used = Kr;
   o->tile_h_used = a.TH;
   o->tile_w_used = a.TWc;
+  o->mfma_used = fused_uses_mf(d, R, variant, a.TWc, a.valu);
   *plan = p;
   return BF_OK;
 }

@@ -198,7 +198,12 @@ struct Server {
                                               spatial_boxes(r->in.spatial));
     for (int m = 0; m < 8; ++m)
       r->a.cen[m] = (r->in.center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
-    // the extrema are known when the min/max ran (order rule or centring)
+    if (r->in.precision == BF_FP16 &&
+        check_fp16_range(d, r->in.sigma_s, spatial_boxes(r->in.spatial), lo, hi, r->a.cen) != BF_OK) {
+      finish(r, BF_REQ_FAILED, BF_EUNSUPPORTED, bf_last_error());
+      return false;
+    }
+    // the extrema are known when the min/max ran (order rule, centring, FP16)
     table_wmax(d, K, tab.data(), r->a.wmax);
     r->a.p64 = phase64_flag(d, r->a.wmax, r->a.cen, r->need_minmax ? lo : nullptr,
                             r->need_minmax ? hi : nullptr);
@@ -613,13 +618,14 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   }
   fused_geometry(r->a, in.H, in.W, r->R, r->kvar, TH,
                  r->kvar == 3 ? spatial_boxes(in.spatial) : 0, TW);
+  if ((rc = check_acc_size(r->a, in.d))) return rc;
   r->a.f = in.f;
   r->a.fpitch = in.pitch;
   r->n_acc = fused_acc_floats(r->a, in.d);
   // term table at most K rows of d+1 floats, K weights (merged draws), 2R+1 taps
   // hi and lo term rows, weights, taps (term_table's layout)
   r->n_tab = (size_t)in.K * (2 * in.d + 3) + (size_t)(2 * r->R + 1);
-  r->need_minmax = in.N == 0 || in.center;
+  r->need_minmax = in.N == 0 || in.center || in.precision == BF_FP16;
   r->nparts = minmax_parts((size_t)in.H * in.W);
   const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMResult : 0;
   r->dev_bytes = Arena::round_up((r->n_acc + r->n_tab) * sizeof(float), kAlign) +

@@ -74,7 +74,8 @@ int main() {
       const int K = 33;
       std::vector<int32_t> Y(K * d);
       std::vector<double> w(K * d), W(d * d);
-      check(bf_sample_terms(d, C.data(), N, K, 12345u + d, Y.data(), w.data()) == BF_OK,
+      check(bf_sample_terms(d, C.data(), N, K, 12345u + d, BF_WHITEN_EIG, Y.data(), w.data()) ==
+                BF_OK,
             "sample status");
       check(bf_whiten(d, C.data(), W.data()) == BF_OK, "whiten");
       for (int t = 0; t < K; ++t)
@@ -88,17 +89,23 @@ int main() {
         }
     }
   }
-  check(bf_sample_terms(3, nullptr, 10, 4, 1, nullptr, nullptr) == BF_EINVAL ||
-            bf_sample_terms(3, nullptr, 10, 4, 1, nullptr, nullptr) == BF_ENOTSPD,
+  check(bf_sample_terms(3, nullptr, 10, 4, 1, BF_WHITEN_EIG, nullptr, nullptr) == BF_EINVAL ||
+            bf_sample_terms(3, nullptr, 10, 4, 1, BF_WHITEN_EIG, nullptr, nullptr) == BF_ENOTSPD,
         "null C rejected by the sampler");
+  {
+    const double C[4] = {1.0, 0.3, 0.3, 2.0};
+    check(bf_sample_terms(2, C, 10, 4, 1, 3, nullptr, nullptr) == BF_EINVAL,
+          "unknown whitening mode rejected by the sampler");
+  }
   std::printf("PASS draws\n");
 
   // order rule: pi sqrt(N) >= T + 4 with N minimal and at least 10
   {
-    const double W[9] = {10, 0, 0, 0, 10, 0, 0, 0, 10};
+    // C = 0.01 I: W = 10 I in every whitening mode
+    const double C[9] = {0.01, 0, 0, 0, 0.01, 0, 0, 0, 0.01};
     const float lo[3] = {0, 0, 0}, hi[3] = {1, 0.5f, 0.25f};
     int N = 0;
-    check(bf_choose_N(3, W, lo, hi, &N) == BF_OK, "choose_N status");
+    check(bf_choose_N(3, C, lo, hi, BF_WHITEN_EIG, &N) == BF_OK, "choose_N status");
     const double T = 10.0;   // max_k sum_m |W_km| (hi - lo)_m
     check(M_PI * std::sqrt((double)N) >= T + 4 && (N == 10 || M_PI * std::sqrt(N - 1.0) < T + 4),
           "order rule");
@@ -121,5 +128,28 @@ int main() {
           "gaussian taps");
   }
   std::printf("PASS taps\n");
+
+  // FP16 storage range: max(1, max_m |f_m - c_m|) * sum(omega_1) <= 32768
+  {
+    double sw = 0.0;   // sigma_s = 10: sum of the 61 Gaussian taps, about 25.07
+    for (double v : bfvec::spatial_taps(10.0)) sw += v;
+    const float lo[3] = {0.0f, -5.0f, 0.0f}, hi[3] = {1.0f, 5.0f, 0.0f};
+    const float mid[3] = {0.5f, 0.0f, 0.0f}, zero[3] = {0.0f, 0.0f, 0.0f};
+    check(bfvec::check_fp16_range(3, 10.0, 0, lo, hi, mid) == BF_OK, "fp16 range: unit data");
+    const float big_lo[1] = {0.0f}, big_hi[1] = {2000.0f};
+    const float c1000[1] = {1000.0f};
+    check(1000.0 * sw < bfvec::kFP16Limit && 2000.0 * sw > bfvec::kFP16Limit, "fp16 range: setup");
+    check(bfvec::check_fp16_range(1, 10.0, 0, big_lo, big_hi, c1000) == BF_OK,
+          "fp16 range: centred 2000-wide channel fits");
+    check(bfvec::check_fp16_range(1, 10.0, 0, big_lo, big_hi, zero) == BF_EUNSUPPORTED,
+          "fp16 range: the same channel uncentred is refused");
+    const float wide_hi[1] = {3000.0f}, c1500[1] = {1500.0f};
+    check(bfvec::check_fp16_range(1, 10.0, 0, big_lo, wide_hi, c1500) == BF_EUNSUPPORTED,
+          "fp16 range: a 3000-wide channel is refused at sigma_s = 10");
+    // sigma_s = 0: one tap of weight 1, so |f - c| up to 32768 fits
+    const float h2[1] = {60000.0f}, c2[1] = {30000.0f};
+    check(bfvec::check_fp16_range(1, 0.0, 0, big_lo, h2, c2) == BF_OK, "fp16 range: identity");
+  }
+  std::printf("PASS fp16 range\n");
   return failures ? 1 : 0;
 }

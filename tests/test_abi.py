@@ -72,21 +72,48 @@ def test_draws_match_oracle(d, N, K, seed):
     assert np.max(np.abs(w - wo)) <= 1e-13 * max(1.0, np.max(np.abs(wo)))
 
 
-def test_order_rule_matches_oracle():
+@pytest.mark.parametrize("mode,omode", [("eig", O.WHITEN_EIG), ("chol", O.WHITEN_CHOL),
+                                        ("sym", O.WHITEN_SYM)])
+def test_order_rule_matches_oracle(mode, omode):
     rng = np.random.default_rng(5)
     for d in (1, 3, 6):
         C = random_spd(d, -3, -1, d) if d > 1 else np.array([[0.01]])
-        W = O.whiten(C)
+        W = O.whiten(C, omode)
         f = rng.uniform(-0.3, 1.2, size=(5, 7, d)).astype(np.float32)
         lo, hi = f.reshape(-1, d).min(0), f.reshape(-1, d).max(0)
-        assert P.bf_choose_N(W, lo, hi) == O.choose_order(f, W)
+        assert P.bf_choose_N(C, lo, hi, whiten=mode) == O.choose_order(f, W)
 
 
-def test_order_rule_limit():
-    W = np.eye(1) / 1e-3
+def test_order_rule_limit_and_arguments():
+    C = np.eye(1) * 1e-6
     with pytest.raises(P.BfError) as e:
-        P.bf_choose_N(W, [0.0], [1.0])
+        P.bf_choose_N(C, [0.0], [1.0])
     assert e.value.code == B.BF_EUNSUPPORTED
+    with pytest.raises(P.BfError) as e:          # lo above hi
+        P.bf_choose_N(np.eye(2), [0.0, 1.0], [1.0, 0.5])
+    assert e.value.code == B.BF_EINVAL
+    with pytest.raises(P.BfError) as e:          # not SPD
+        P.bf_choose_N(np.array([[1.0, 2.0], [2.0, 1.0]]), [0.0, 0.0], [1.0, 1.0])
+    assert e.value.code == B.BF_ENOTSPD
+    with pytest.raises(P.BfError) as e:          # unknown whitening mode
+        P.bf_choose_N(np.eye(2), [0.0, 0.0], [1.0, 1.0], whiten=5)
+    assert e.value.code == B.BF_EINVAL
+
+
+@pytest.mark.parametrize("mode,omode", [("chol", O.WHITEN_CHOL), ("sym", O.WHITEN_SYM)])
+@pytest.mark.parametrize("d,N,K,seed", [(3, 309, 128, 2002), (6, 40, 64, 2004)])
+def test_draws_match_oracle_every_whitening(mode, omode, d, N, K, seed):
+    # the C ABI reproduces the draws bf_vec_ex runs with opts.whiten: the same
+    # Y (whitening does not enter the bits) and w = W^T Y / sqrt(N) with the
+    # mode's W
+    C = (np.array([[100.0, 0, 0], [0, 25, 12.5], [0, 12.5, 25]]) if d == 3
+         else random_spd(d, -3, -1, d + 10))
+    Y, w = P.bf_sample_terms(C, N, K, seed, whiten=mode)
+    Yo, wo = O.sample_terms(C, N, K, seed, W=O.whiten(C, omode))
+    assert np.array_equal(Y, Yo)
+    assert np.max(np.abs(w - wo)) <= 1e-13 * max(1.0, np.max(np.abs(wo)))
+    _, we = P.bf_sample_terms(C, N, K, seed)       # non-diagonal C: the modes differ
+    assert np.max(np.abs(we - w)) > 1e-6
 
 
 def _call_vec(f=0x1000, H=8, W=8, d=3, sigma=1.0, C=None, K=4, out=0x100000):
@@ -251,3 +278,35 @@ def test_whitening_mode_validation():
     rc = L.bf_vec_ex(0x1000, 8, 8, 3, 1.0, C.ctypes.data_as(ctypes.c_void_p), 4, 1, 0x100000,
                      ctypes.byref(o))
     assert rc == B.BF_EINVAL
+
+
+def test_strip_height_bounded_by_accumulator_offsets():
+    # A requested strip height is clamped to one strip (the image height), so
+    # a huge value cannot inflate the padded accumulators; a height that
+    # splits the image into two tall strips whose padding pushes
+    # (d+1) x padded rows x padded columns past 2^30 floats is refused before
+    # any device work (32-bit byte offsets in the kernels).
+    H = W = 16000
+    d = 3
+    out = 0x1000 + H * W * d * 4 + 4096
+    Ch = np.ascontiguousarray(np.eye(d) * 0.01)
+    for tile_h in (8400, 12000):
+        o = B.make_opts(tile_h=tile_h)
+        rc = B.lib().bf_vec_ex(0x1000, H, W, d, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                               out, ctypes.byref(o))
+        assert rc == B.BF_EUNSUPPORTED, B.lib().bf_last_error().decode()
+        assert "accumulators too large" in B.lib().bf_last_error().decode()
+        o = B.make_opts(tile_h=tile_h, N=20)
+        h = ctypes.c_void_p()
+        rc = B.lib().bf_plan_create(H, W, d, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                                    ctypes.byref(o), ctypes.byref(h))
+        assert rc == B.BF_EUNSUPPORTED and not h.value
+
+
+def test_valu_only_option_validated():
+    o = B.make_opts()
+    o.valu_only = 2
+    Ch = np.eye(3) * 0.01
+    rc = B.lib().bf_vec_ex(0x1000, 8, 8, 3, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                           0x100000, ctypes.byref(o))
+    assert rc == B.BF_EINVAL and "valu_only" in B.lib().bf_last_error().decode()

@@ -186,3 +186,16 @@ def test_sampled_filter_converges_to_exact():
     assert -1.4 < slope < -0.6, slope
     # the order-N kernel itself is close to the Gaussian
     assert O.mse(rc, exact) < 1e-6
+
+
+def test_mse_hand_values():
+    # eq. (MSE): the mean over pixels and channels of the squared difference.
+    # a - b = [[1, -2], [3, -4]] (a 2 x 1 x 2 image): (1 + 4 + 9 + 16) / 4 = 7.5
+    a = np.array([[[1.0, 0.0]], [[5.0, 2.0]]])
+    b = np.array([[[0.0, 2.0]], [[2.0, 6.0]]])
+    assert O.mse(a, b) == 7.5
+    assert O.mse(a, a) == 0.0
+    # in dB on a 255 scale: 10 log10(7.5 * 255^2) = 10 log10(487687.5)
+    assert abs(O.mse_db(a, b, scale=255.0) - 56.8814162) < 1e-6
+    # 10 log10(100) = 20 dB exactly: a constant offset of 10
+    assert abs(O.mse_db(np.full((3, 4, 3), 10.0), np.zeros((3, 4, 3))) - 20.0) < 1e-12

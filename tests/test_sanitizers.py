@@ -1,6 +1,6 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only):
 the library's host-only C entry points (host.cpp: whitening, draws, order
-rule, spatial taps) driven by tests/host_check.cpp, and the serving
+rule, spatial taps, FP16 range rule) driven by tests/host_check.cpp, and the serving
 scheduler's arena and round planner driven by tests/sched_check.cpp, both
 built with g++ (no device code involved)."""
 
@@ -33,7 +33,7 @@ def test_host_entry_points_under_sanitizers(tmp_path):
                      [f"{ROOT}/tests/host_check.cpp", f"{CSRC}/host.cpp"])
     assert out.returncode == 0, out.stdout + out.stderr
     assert "runtime error" not in out.stderr and "ERROR: AddressSanitizer" not in out.stderr
-    assert sum(l.startswith("PASS") for l in out.stdout.splitlines()) == 4, out.stdout
+    assert sum(l.startswith("PASS") for l in out.stdout.splitlines()) == 5, out.stdout
 
 
 def test_scheduler_under_sanitizers(tmp_path):
