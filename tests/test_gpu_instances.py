@@ -12,9 +12,19 @@ filter (O3, Algorithm 1 in FP64) over a whole image of several strips in both
 directions with ragged edges:
 
 * bf_vec_ex at the instance's strip width, with and without the matrix-core
-  passes (bf_opts.valu_only), against O3: FP32 within 1e-4 of each channel's
-  range (1e-5/z where the normaliser z is small, as in test_gpu_parity), FP16
-  and BF16 within the storage-rounding bound of test_gpu_parity;
+  passes (bf_opts.valu_only), against O3.  The accumulated numerator and
+  normaliser (eqs. (numerator), (denom); the num_out / z_out outputs) are
+  linear in the filtered channels, so their error does not depend on the
+  conditioning of the ratio: every pixel within 1e-5 (FP32) or 4u (16-bit
+  storage, u the unit roundoff, two roundings of each stored value) of their
+  scale K sum(omega) (times max |f| for the numerator).  The output num/Z:
+  FP32 within 1e-4 of each channel's range where z = Z / (K sum omega) >=
+  0.1 and within 1e-5/z for 0.01 <= z < 0.1 (test_gpu_parity's bound for
+  ill-conditioned pixels, continued up to where it meets 1e-4: with a few
+  terms z comes close to zero at some pixels, and the ratio amplifies the
+  FP32 rounding of num, Z and the term table by 1/z; below z = 0.01 the
+  num and Z checks stand alone), FP16 and BF16 within the storage-rounding
+  bound 4u/z of test_gpu_parity (z >= 0.01);
 * a plan with the same options runs the instance with the FP64 phase path
   (a plan's graph is captured before the image range is known) and must
   equal the bf_vec_ex result bit for bit (lanes below 2^8 turns run the same
@@ -27,7 +37,8 @@ import pytest
 import paper_1605_02164_amd as P
 from oracle import mcsf as O
 from synth import voronoi_image, random_spd
-from tests.test_gpu_parity import assert_close, lp_errors, LP_BOUND, cuda, host, say
+from tests.helpers import rel_err_per_channel
+from tests.test_gpu_parity import lp_errors, LP_UNIT, cuda, host, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -64,6 +75,13 @@ def _cases():
 CASES = _cases()
 
 
+def _span(f):
+    f2 = np.asarray(f, np.float64).reshape(-1, f.shape[-1])
+    s = f2.max(0) - f2.min(0)
+    s[s == 0] = 1.0
+    return s
+
+
 def _image(d, R, TW):
     # several strips across (ragged last strip) and down (tile_h = 24), and
     # an image narrower / shorter than the window at the larger radii
@@ -82,11 +100,13 @@ def test_instance_against_oracle(d, R, prec, TW, valu):
     f, C = _image(d, R, TW)
     sigma = R / 3.0
     assert O.window_radius(sigma) == R
-    K, seed, TH = 3, 1000 + R, 24
+    K, seed, TH = 4, 1000 + R, 24
     fg = cuda(f)
+    num = torch.empty_like(fg)
+    zo = torch.empty(fg.shape[:2], device="cuda", dtype=torch.float32)
     got, o = P.bf_vec_ex(fg, sigma, C, K, seed, precision=prec, tile_h=TH, tile_w=TW,
-                         valu_only=bool(valu), return_opts=True)
-    got = host(got)
+                         valu_only=bool(valu), num_out=num, z_out=zo, return_opts=True)
+    got, num, zo = host(got), host(num), host(zo)
     assert o.tile_w_used == TW and o.tile_h_used == TH
     assert o.mfma_used == _mf_expected(prec, R, TW, valu)
     f64 = f.astype(np.float64)
@@ -94,14 +114,28 @@ def test_instance_against_oracle(d, R, prec, TW, valu):
     N = O.choose_order(f64, W_)
     assert o.N_used == N
     _, w = O.sample_terms(C, N, K, seed, W=W_)
-    ref, _, Z = O.mcsf_separable(f64, sigma, w)
-    z = Z / (K * O.spatial_taps(sigma).sum() ** 2)
+    ref, rnum, rZ = O.mcsf_separable(f64, sigma, w)
+    scale = K * O.spatial_taps(sigma).sum() ** 2
+    z = rZ / scale
+    eps = 1e-5 if prec == "fp32" else 4.0 * LP_UNIT[prec]
+    ez = np.max(np.abs(zo - rZ)) / scale
+    en = np.max(np.abs(num - rnum)) / (scale * np.abs(f64).max())
+    say(f"  N={N} Z err {ez:.3e}, num err {en:.3e} (of their scale; bound {eps:.1e});"
+        f" min z {z.min():.3f}")
+    assert ez <= eps and en <= eps
     if prec == "fp32":
-        assert_close(got, ref, f, z)
+        good = z >= 0.1
+        err = rel_err_per_channel(got[good], ref[good], f)
+        say(f"  output rel_err={err} (z >= 0.1), {int((~good).sum())} pixels below")
+        assert np.all(err <= 1e-4), err
+        mid = ~good & (z >= 0.01)
+        if mid.any():
+            e = np.abs(got[mid] - ref[mid]) / _span(f)
+            assert np.all(e * z[mid][:, None] <= 1e-5)
     else:
-        mx, mean, sc = lp_errors(got, ref, f, z)
-        say(f"  {prec}: max err {mx:.3e} mean err {mean:.3e} conditioning-scaled {sc:.3e}")
-        assert sc <= LP_BOUND[prec]
+        mx, mean, rb = lp_errors(got, ref, f, z, prec)
+        say(f"  {prec}: max err {mx:.3e} mean err {mean:.3e}, {rb:.3f} of the bound")
+        assert rb <= 1.0
     # the FP64-phase-path instance (plans) gives the same bits
     with P.Plan(*f.shape, sigma, C, K, seed, N=N, precision=prec, tile_h=TH, tile_w=TW,
                 valu_only=bool(valu)) as plan:
