@@ -146,6 +146,30 @@ int bf_vec(const float* f, int H, int W, int d, double sigma_s,
 int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s,
               const double* C, int K, uint64_t seed, float* out, bf_opts* o);
 
+/* Size of the device scratch array of bf_vec_static (per GPU, held for the
+ * life of the process). */
+#define BF_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* bf_vec_ex without any device allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, options, results (the
+ * same bits as bf_vec_ex) and errors, except:
+ *   - the min/max partials, the term table and the accumulators live in one
+ *     library-owned static device array of BF_STATIC_SCRATCH_BYTES per GPU;
+ *     a call whose accumulators ((d+1) x padded rows x padded columns floats)
+ *     plus term table exceed it returns BF_EUNSUPPORTED before any kernel
+ *     runs (2^24 floats: about 4 million padded pixels at d = 3, 2.3 million
+ *     at d = 6; strips pad the image to whole strips of 16 or 32 columns);
+ *   - every call on one GPU shares that GPU's array: calls that overlap on
+ *     the device (different streams, or threads without ordering) race and
+ *     give undefined results.  Calls queued on one stream are ordered and
+ *     safe.  The array keeps the last call's contents; nothing in it needs
+ *     to start at zero (the kernels write before they read);
+ *   - o->time_kernel must be 0 (BF_EINVAL).
+ * The caller still provides f and out (and num_out / z_out if wanted). */
+int bf_vec_static(const float* f, int H, int W, int d, double sigma_s,
+                  const double* C, int K, uint64_t seed, float* out, bf_opts* o);
+
 /* The filter with an explicit term table instead of drawn terms:
  * w: HOST K x d float64 frequency vectors (radians per unit of f), so term t
  * modulates by exp(i <w_t, f(i)>) (eqs. (Ht), (bigExp)); weights: HOST K

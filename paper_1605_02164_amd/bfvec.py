@@ -52,8 +52,9 @@ EXPORTS = [
     "bf_server_config_init", "bf_request_init", "bf_server_create", "bf_server_submit",
     "bf_server_poll", "bf_server_wait", "bf_server_drain", "bf_server_forget",
     "bf_server_get_stats", "bf_server_clock", "bf_server_destroy",
-    "bf_plan_create", "bf_plan_execute", "bf_plan_destroy",
+    "bf_plan_create", "bf_plan_execute", "bf_plan_destroy", "bf_vec_static",
 ]
+BF_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class BfError(RuntimeError):
@@ -171,6 +172,7 @@ def lib():
     L.bf_vec.argtypes = [P, I, I, I, D, P, I, U64, P]
     L.bf_vec_ex.argtypes = [P, I, I, I, D, P, I, U64, P, ctypes.POINTER(bf_opts)]
     L.bf_vec_terms.argtypes = [P, I, I, I, D, P, P, I, P, ctypes.POINTER(bf_opts)]
+    L.bf_vec_static.argtypes = [P, I, I, I, D, P, I, U64, P, ctypes.POINTER(bf_opts)]
     L.bf_whiten.argtypes = [I, P, P]
     L.bf_whiten_mode.argtypes = [I, P, I, P]
     L.bf_sample_terms.argtypes = [I, P, I, I, U64, I, P, P]
@@ -198,7 +200,8 @@ def lib():
     L.bf_plan_create.argtypes = [I, I, I, D, P, I, U64, ctypes.POINTER(bf_opts), ctypes.POINTER(P)]
     L.bf_plan_execute.argtypes = [P, P, P, P]
     L.bf_plan_destroy.argtypes = [P]
-    for name in ("bf_vec", "bf_vec_ex", "bf_vec_terms", "bf_whiten", "bf_whiten_mode",
+    for name in ("bf_vec", "bf_vec_ex", "bf_vec_static", "bf_vec_terms", "bf_whiten",
+                 "bf_whiten_mode",
                  "bf_sample_terms",
                  "bf_choose_N", "bf_minmax", "bf_direct", "bf_autotune", "bf_version",
                  "bf_server_create",
@@ -295,6 +298,22 @@ def bf_vec_ex(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=Tr
                   time_kernel, dedup, spatial, whiten, tile_w, valu_only)
     _check(lib().bf_vec_ex(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
                            int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
+    return (out, o) if return_opts else (out, o.N_used)
+
+
+def bf_vec_static(f, sigma_s, C, K, seed, out=None, N=0, precision="fp32", center=True,
+                  tile_h=0, stream=None, num_out=None, z_out=None, return_opts=False,
+                  dedup=False, spatial="gauss", whiten="eig", tile_w=0, valu_only=False):
+    """bf_vec_ex through the allocation-free entry point (library-owned static
+    device scratch of BF_STATIC_SCRATCH_BYTES per GPU; calls that overlap on
+    the device race).  Returns (out, N_used), or (out, opts)."""
+    out = _check_image(f, out)
+    H, W, d = f.shape
+    Ch = _host_f64(C, (d, d))
+    o = make_opts(N, precision, center, tile_h, _stream_handle(stream), num_out, z_out,
+                  False, dedup, spatial, whiten, tile_w, valu_only)
+    _check(lib().bf_vec_static(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), int(K),
+                               int(seed) & 0xFFFFFFFFFFFFFFFF, out.data_ptr(), ctypes.byref(o)))
     return (out, o) if return_opts else (out, o.N_used)
 
 

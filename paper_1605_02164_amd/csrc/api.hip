@@ -8,6 +8,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -118,17 +119,23 @@ hipError_t launch_minmax(const float* f, int H, int W, int pitch, int d, float* 
 
 namespace {
 
-int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStream_t st) {
+// Per-channel extrema on the host.  work: device buffer of at least
+// minmax_floats(H*W) floats, or null to allocate one in stream order.
+int run_minmax(const float* f, int H, int W, int d, float* lo, float* hi, hipStream_t st,
+               float* work = nullptr) {
   const int nparts = minmax_parts((size_t)H * W);
-  float* dbuf = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&dbuf, ((size_t)nparts * 17 + kMMResult) * sizeof(float), st),
-          "hipMallocAsync(minmax)");
+  float* dbuf = work;
+  if (!work)
+    HIP_TRY(hipMallocAsync((void**)&dbuf, ((size_t)nparts * 17 + kMMResult) * sizeof(float), st),
+            "hipMallocAsync(minmax)");
   float* res = dbuf + (size_t)nparts * 17;
   hipError_t e = launch_minmax(f, H, W, W, d, dbuf, nparts, res, st);
   float h[17];
   if (e == hipSuccess) e = hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st);
-  hipError_t e2 = hipFreeAsync(dbuf, st);
-  if (e == hipSuccess) e = e2;
+  if (!work) {
+    hipError_t e2 = hipFreeAsync(dbuf, st);
+    if (e == hipSuccess) e = e2;
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "min/max reduction");
   if (h[16] != 0.0f) return fail(BF_EINVAL, "f contains NaN or infinity");
@@ -313,9 +320,12 @@ int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH, i
 
 // Launch the fused filter for a host FP64 term table (radians per unit).
 // lo/hi: per-channel extrema when known (min/max ran), else null.
+// work: device buffer of work_floats floats for the accumulators and the
+// term table (the call fails with BF_EUNSUPPORTED if they do not fit), or
+// null to allocate them in stream order.
 int run_terms(const float* f, int H, int W, int d, double sigma_s, const double* w,
               const double* weights, int K, float* out, bf_opts* o, const float* lo,
-              const float* hi, int TH, int TW) {
+              const float* hi, int TH, int TW, float* work = nullptr, size_t work_floats = 0) {
   hipStream_t st = (hipStream_t)o->stream;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   const int variant = kernel_variant(o->precision, o->spatial);
@@ -344,11 +354,18 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   o->tile_w_used = a.TWc;
   o->mfma_used = fused_uses_mf(d, R, variant, a.TWc, a.valu);
 
-  // one stream-ordered allocation: accumulators | terms | weights | taps
+  // one buffer: accumulators | terms | weights | taps
   const size_t n_acc = fused_acc_floats(a, d);
-  float* dbuf = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&dbuf, (n_acc + hbuf.size()) * sizeof(float), st),
-          "hipMallocAsync(accumulators)");
+  float* dbuf = work;
+  if (work && n_acc + hbuf.size() > work_floats)
+    return fail(BF_EUNSUPPORTED,
+                "accumulators and term table need " +
+                    std::to_string((n_acc + hbuf.size()) * sizeof(float)) +
+                    " bytes, above the static scratch of " +
+                    std::to_string(work_floats * sizeof(float)) + " bytes");
+  if (!work)
+    HIP_TRY(hipMallocAsync((void**)&dbuf, (n_acc + hbuf.size()) * sizeof(float), st),
+            "hipMallocAsync(accumulators)");
   a.acc = dbuf;
   float* dterms = dbuf + n_acc;
   hipError_t e = hipMemcpyAsync(dterms, hbuf.data(), hbuf.size() * sizeof(float),
@@ -386,8 +403,10 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   }
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
-  hipError_t e2 = hipFreeAsync(dbuf, st);
-  if (e == hipSuccess) e = e2;
+  if (!work) {
+    hipError_t e2 = hipFreeAsync(dbuf, st);
+    if (e == hipSuccess) e = e2;
+  }
   if (e != hipSuccess) return hip_fail(e, "fused MCSF launch");
   return BF_OK;
 }
@@ -449,12 +468,87 @@ hipError_t launch_direct(const DirectArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free variant (bf_vec_static): every device buffer the call needs
+// (min/max partials, term table, accumulators) lives in one file-scope device
+// array per GPU.  Host code must not use the array's name as a device
+// address: its per-device address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchFloats = (size_t)BF_STATIC_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (resolved on the first call there).
+int scratch_for_current_device(float** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(BF_EDEVICE, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(BF_EDEVICE, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *ptr = g_scratch_ptr[dev];
+  return BF_OK;
+}
+
 }  // namespace
 }  // namespace bfvec
 
 using namespace bfvec;
 
 extern "C" {
+
+int bf_vec_static(const float* f, int H, int W, int d, double sigma_s, const double* C, int K,
+                  uint64_t seed, float* out, bf_opts* o) {
+  clear_error();
+  bf_opts def;
+  if (!o) {
+    bf_opts_init(&def);
+    o = &def;
+  }
+  int rc = check_common(f, H, W, d, sigma_s, out);
+  if (rc) return rc;
+  if (K < 1 || K > 65536) return fail(BF_EINVAL, "K must be in [1, 65536]");
+  if (!C) return fail(BF_EINVAL, "C must be non-null");
+  if ((rc = check_opts(o))) return rc;
+  if (o->time_kernel) return fail(BF_EINVAL, "bf_vec_static takes no time_kernel (events)");
+  double Wm[64];
+  if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
+  int TH = 0, TW = 0;
+  if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
+  // the min/max partials fit the scratch at any size (at most 1024 x 17 +
+  // kMMResult floats); the accumulators and the table are checked by run_terms
+  float* work = nullptr;
+  if ((rc = scratch_for_current_device(&work))) return rc;
+  float lo[8] = {0}, hi[8] = {0};
+  const bool have_range = o->N == 0 || o->center || o->precision == BF_FP16;
+  if (have_range && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream, work))) return rc;
+  int N = o->N;
+  if (N == 0 && (rc = choose_order(d, Wm, lo, hi, &N))) return rc;
+  o->N_used = N;
+  std::vector<double> w, weight;
+  if (o->dedup) {
+    distinct_terms(d, Wm, N, K, seed, &w, &weight);
+    o->K_used = (int)weight.size();
+  } else {
+    w.resize((size_t)K * d);
+    frequency_table(d, Wm, N, K, seed, w.data());
+    o->K_used = K;
+  }
+  return run_terms(f, H, W, d, sigma_s, w.data(), o->dedup ? weight.data() : nullptr, o->K_used,
+                   out, o, have_range ? lo : nullptr, have_range ? hi : nullptr, TH, TW, work,
+                   kScratchFloats);
+}
 
 int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double* C, int K,
               uint64_t seed, float* out, bf_opts* o) {
