@@ -35,19 +35,11 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "f5afd7cb666f05eb1216fe0a57498ce6de3d72739a8a461b674807e627407305",
-    "fp32": {"fetch_kib": 87993694, "write_kib": 67108864,
-             # SQ_INSTS_VALU_FLOPS_FP32 x 64 lanes (executed FP32 VALU flops)
-             # + SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 (matrix-core flops)
-             "executed_flops": 70476914688 * 64 + 10838081536 * 512},
-    "fp16": {"fetch_kib": 100525833, "write_kib": 67108282,
-             # SQ_INSTS_VALU_FLOPS_FP16 + SQ_INSTS_VALU_FLOPS_FP32, x 64 lanes
-             # + SQ_INSTS_VALU_MFMA_MOPS_F16 x 512
-             "executed_flops": (2717908992 + 5175820288) * 64
-                               + 40265318400 * 512},
+    "sha256": "pending: counters not yet taken on these kernel sources",
     "fetch_factor": 1048576 / 524306.5625,
     "write_factor": 1048576 / 1048576.0,
 }
+COUNTERS_PROFILE = "profiles/mcsf_fused_voronoi4096_d3_s10_K256.md"
 
 
 def _counters(prec):
@@ -69,11 +61,10 @@ def measured_traffic(prec):
     return (t["fetch_kib"] * TRAFFIC["fetch_factor"] + t["write_kib"] * TRAFFIC["write_factor"]) * 1024
 
 
-def executed_flops(prec):
-    """Executed VALU flops per launch (rocprofv3 counters) for the current
-    kernel sources, or None."""
-    t = _counters(prec)
-    return None if t is None else t["executed_flops"]
+def kernel_name(d, R, prec, tile_w, mf):
+    """The fused-kernel instance a launch ran: mcsf_fused<d, R, storage,
+    FP64-phase path, strip width, matrix-core passes>."""
+    return f"mcsf_fused<{d}, {R}, {prec}, p64=0, TW={tile_w}, MF={int(bool(mf))}>"
 
 
 def log(*a):
@@ -86,24 +77,114 @@ def algorithmic_flops_per_pixel(d, R, K):
     return K * (4 * d + 8 * (d + 1) * (2 * R + 1) + 4 * (d + 1))
 
 
-def cpu_baseline(f, C, sigma_s, K, seed, N, crop=512, k_sample=64):
-    """The oracle's separable MCSF (FP64 numpy, single thread) on a centred
-    crop with the first k_sample of the same terms; rate scaled to K terms."""
+def _cpu_info():
+    """(CPU model, logical CPUs of the machine, CPUs this process may use)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=None, crop=1024, direct_crop=192,
+                 n_acc_pixels=1024):
+    """The FP64 oracle on the host cores (CPU baseline leg).
+
+    1. O3, the separable MCSF of Algorithm 1 (the oracle as it stands), on a
+       centred crop: the K terms are split over the worker threads (numpy
+       releases the GIL inside its array operations; each worker's BLAS is
+       limited to one thread), each worker filters the crop with its share of
+       the terms, and the numerators and normalisers are summed (both are
+       sums over terms).  A bounded sample of the terms is run (six per
+       worker, about 10-20 s) and the rate scaled to all K.
+    2. O1, the direct filter of eqs. (BF)/(normal) with the exact Gaussian
+       range kernel (the paper's comparison method), on a smaller centred
+       crop, pixels split over the workers.
+    3. The GPU outputs (gpu_outs: mode -> (H, W, d) tensor) against O2,
+       the direct filter with the same sampled kernel, at seeded pixels:
+       max and mean error as a fraction of each channel's range.
+    """
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     from threadpoolctl import threadpool_limits
     from oracle import mcsf as O
+    model, nproc, usable = _cpu_info()
+    workers = max(1, min(16, usable))   # the box's CPU share for one GPU
     H, W, d = f.shape
+    f64 = f.astype(np.float64)
+    Wm = O.whiten(C)
+    _, w = O.sample_terms(C, N, K, seed, W=Wm)
     y0, x0 = (H - crop) // 2, (W - crop) // 2
-    sub = f[y0:y0 + crop, x0:x0 + crop].astype(np.float64)
-    _, w = O.sample_terms(C, N, k_sample, seed)
-    with threadpool_limits(limits=1):
+    sub = f64[y0:y0 + crop, x0:x0 + crop]
+    k_run = min(K, 6 * workers)
+    shares = [s for s in np.array_split(np.arange(k_run), workers) if len(s)]
+
+    def o3_share(idx):
+        _, num, Z = O.mcsf_separable(sub, sigma_s, w[idx])
+        return num, Z
+
+    with threadpool_limits(limits=1), ThreadPoolExecutor(workers) as ex:
         t0 = time.perf_counter()
-        O.mcsf_separable(sub, sigma_s, w)
+        parts = list(ex.map(o3_share, shares))
+        num = sum(p[0] for p in parts)
+        Z = sum(p[1] for p in parts)
+        _ = num / Z[..., None]
         dt = time.perf_counter() - t0
-    rate = crop * crop * (k_sample / K) / dt / 1e6
-    return {"value": rate, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": f"{crop}x{crop} centre crop, first {k_sample} of the {K} terms "
-                      f"(rate scaled to {K} terms), separable FP64 oracle, {dt:.1f} s"}
+    rate = crop * crop * (k_run / K) / dt / 1e6
+    rec = {"value": rate, "unit": "Mpix/s", "cores": len(shares), "kind": "oracle",
+           "sample": f"separable FP64 oracle (Algorithm 1) on the {crop}x{crop} centre crop, "
+                     f"the first {k_run} of the {K} terms split over {len(shares)} threads "
+                     f"({dt:.1f} s), rate scaled to {K} terms",
+           "cpu_model": model, "nproc": nproc, "usable_cpus": usable}
+    # O1 on a smaller crop
+    yd, xd = (H - direct_crop) // 2, (W - direct_crop) // 2
+    dsub = f64[yd:yd + direct_crop, xd:xd + direct_crop]
+    pix = np.stack(np.meshgrid(np.arange(direct_crop), np.arange(direct_crop), indexing="ij"),
+                   axis=-1).reshape(-1, 2)
+    with threadpool_limits(limits=1), ThreadPoolExecutor(workers) as ex:
+        t0 = time.perf_counter()
+        list(ex.map(lambda c: O.direct_exact(dsub, sigma_s, C, pixels=c),
+                    np.array_split(pix, 8 * workers)))
+        dt1 = time.perf_counter() - t0
+    rec["direct_o1"] = {"value": direct_crop ** 2 / dt1 / 1e6, "unit": "Mpix/s",
+                        "cores": workers,
+                        "sample": f"direct FP64 filter, exact Gaussian range kernel, "
+                                  f"{direct_crop}x{direct_crop} centre crop, pixels split over "
+                                  f"{workers} threads ({dt1:.1f} s)"}
+    if gpu_outs:
+        rng = np.random.default_rng(17)
+        n = n_acc_pixels
+        pts = np.stack([rng.integers(0, H, n), rng.integers(0, W, n)], axis=1)
+        corners = np.array([[0, 0], [0, W - 1], [H - 1, 0], [H - 1, W - 1]])
+        pts = np.unique(np.concatenate([pts, corners]), axis=0)
+        with threadpool_limits(limits=1), ThreadPoolExecutor(workers) as ex:
+            t0 = time.perf_counter()
+            res = list(ex.map(lambda c: O.direct_sampled(f64, sigma_s, w, pixels=c),
+                              np.array_split(pts, 8 * workers)))
+            dt2 = time.perf_counter() - t0
+        ref = np.concatenate([r[0] for r in res])
+        span = f64.reshape(-1, d).max(0) - f64.reshape(-1, d).min(0)
+        span[span == 0] = 1.0
+        acc = {}
+        for mode, out in gpu_outs.items():
+            # out: a device tensor of the GPU run; only the sampled pixels come back
+            g = out[pts[:, 0], pts[:, 1]].double().cpu().numpy()
+            e = np.abs(g - ref) / span
+            acc[mode] = {"max_err": float(e.max()), "mean_err": float(e.mean())}
+        rec["accuracy_vs_oracle"] = {
+            "reference": "O2: direct filter with the same K sampled terms (FP64)",
+            "pixels": int(len(pts)), "unit": "fraction of each channel's range",
+            "oracle_s": dt2, "modes": acc}
+    return rec
 
 
 def serving_run(args, P, torch, log_fn):
@@ -525,28 +606,29 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def step(prec, dst, dedup, spatial="gauss"):
+    def step(prec, dst, dedup, spatial="gauss", valu=False):
         _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=dst, precision=prec,
                            stream=stream, time_kernel=True, return_opts=True, dedup=dedup,
-                           spatial=spatial)
-        return o.N_used, o.kernel_ms, o.K_used, o.tile_h_used
+                           spatial=spatial, valu_only=valu)
+        return o.N_used, o.kernel_ms, o.K_used, o.tile_h_used, o.tile_w_used, o.mfma_used
 
     tuned = {}
 
     def run(mode, dst):
         prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
         spatial = "box3" if mode.endswith("_box3") else "gauss"
+        valu = mode.endswith("_valu")
         if not args.no_autotune and prec not in tuned:
             # one-off, untimed: measured strip height for this shape
             tuned[prec] = P.bf_autotune(fg, sigma_s, precision=prec, stream=stream)
             log(f"{prec}: autotuned strip height {tuned[prec][0]}")
         for _ in range(args.warmup):
-            step(prec, dst, dedup, spatial)
+            step(prec, dst, dedup, spatial, valu)
         torch.cuda.synchronize()
         kms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            N, ms, K_used, tile_h = step(prec, dst, dedup, spatial)
+            N, ms, K_used, tile_h, tile_w, mf = step(prec, dst, dedup, spatial, valu)
             kms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -557,7 +639,10 @@ def main():
         tf = None if spatial != "gauss" else flops_run / (kernel_ms * 1e-3) / 1e12
         rec = {"value": H * W * args.steps / dt / 1e6, "ms_per_step": 1e3 * dt / args.steps,
                "kernel_ms": kernel_ms, "achieved_tflops": tf,
-               "N": N, "K_used": K_used, "tile_h": tile_h, "spatial": spatial}
+               "frac_of_fp32_peak": None if tf is None else tf / PEAK_FP32_VALU,
+               "N": N, "K_used": K_used, "tile_h": tile_h, "tile_w": tile_w,
+               "matrix_core_passes": bool(mf), "spatial": spatial,
+               "kernel": kernel_name(d, R, prec, tile_w, mf)}
         log(f"{mode}: N={N} K_used={K_used} step {rec['ms_per_step']:.2f} ms, kernel "
             f"{kernel_ms:.2f} ms, " + ("" if tf is None else f"{tf:.2f} TFLOP/s algorithmic, ")
             + f"{rec['value']:.2f} Mpix/s")
@@ -566,7 +651,7 @@ def main():
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
         [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + \
-        ["fp32_dedup", "fp16_dedup", "fp32_box3"]
+        ["fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3"]
     results, outs = {}, {}
     for prec in precs:
         outs[prec] = torch.empty_like(fg)
@@ -615,9 +700,18 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
-        cpu = cpu_baseline(f, C, sigma_s, K, seed, N)
-        log(f"cpu baseline {cpu['value']:.4g} Mpix/s ({cpu['sample']})")
+        gauss = {m: outs[m] for m in results if results[m]["spatial"] == "gauss"}
+        cpu = cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=gauss)
+        log(f"cpu baseline {cpu['value']:.4g} Mpix/s ({cpu['sample']}); direct O1 "
+            f"{cpu['direct_o1']['value']:.4g} Mpix/s")
+        for m, e in cpu["accuracy_vs_oracle"]["modes"].items():
+            results[m]["max_err_vs_oracle"] = e["max_err"]
+            results[m]["mean_err_vs_oracle"] = e["mean_err"]
+            log(f"{m}: error vs the FP64 oracle max {e['max_err']:.3g}, mean {e['mean_err']:.3g}")
 
+    cnt = _counters(args.precision)
+    ex_valu = None if cnt is None else cnt["valu_flops"] / (kernel_ms * 1e-3) / 1e12
+    ex_mfma = None if cnt is None else cnt["mfma_flops"] / (kernel_ms * 1e-3) / 1e12
     rec = {
         "metric": METRIC,
         "value": value,
@@ -637,26 +731,34 @@ def main():
                    "window": 2 * R + 1, "K": K, "N": N, "C": "0.08^2 I" if d == 3 else "SPD",
                    "precision": args.precision},
         "roofline": {
+            # FP32: the vertical pass, modulation and demodulation run on the
+            # VALU, the horizontal pass (32-column strips, R >= 12) on the
+            # FP32 matrix cores; both units peak at 157.3 TFLOP/s
             "bound": "alu",
-            "kernel": f"mcsf_fused<{d}, {R}, {args.precision}>",
+            "kernel": main_rec["kernel"],
+            "units": ("VALU + FP32 matrix cores" if main_rec["matrix_core_passes"] and
+                      args.precision == "fp32" else
+                      "VALU + 16-bit matrix cores" if main_rec["matrix_core_passes"] else "VALU"),
             "achieved": achieved,
             "peak": PEAK_FP32_VALU,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU,
             "frac_vs_nonpacked_fma": achieved / PEAK_FP32_NONPACKED,
+            "algorithmic_flops_per_launch": flops,
+            "kernel_ms": kernel_ms,
             "traffic": measured_traffic(args.precision),
             "traffic_unit": "bytes per launch",
             "hbm_tb_s": (None if measured_traffic(args.precision) is None else
                          measured_traffic(args.precision) / (kernel_ms * 1e-3) / 1e12),
-            "flops_per_launch": flops,
-            "kernel_ms": kernel_ms,
-            # executed (not algorithmic) VALU flops from the rocprofv3 counters of
-            # the same kernel build, over this run's launch time
-            "executed_tflops": (None if executed_flops(args.precision) is None else
-                                executed_flops(args.precision) / (kernel_ms * 1e-3) / 1e12),
-            "executed_frac": (None if executed_flops(args.precision) is None else
-                              executed_flops(args.precision) / (kernel_ms * 1e-3) / 1e12
-                              / PEAK_FP32_VALU),
+            # The fields below come from rocprofv3 --pmc counter runs of this
+            # kernel build (COUNTERS_PROFILE), not from this run: executed
+            # (not algorithmic) flops per launch, over this run's launch time.
+            "counters_source": None if cnt is None else COUNTERS_PROFILE,
+            "executed_valu_tflops": ex_valu,
+            "executed_valu_frac_of_157_3": None if ex_valu is None else ex_valu / PEAK_FP32_VALU,
+            "executed_valu_frac_of_nonpacked_78_6": (None if ex_valu is None else
+                                                     ex_valu / PEAK_FP32_NONPACKED),
+            "executed_matrix_core_tflops": ex_mfma,
         },
         "cpu_baseline": cpu,
         "direct_comparator": direct,
