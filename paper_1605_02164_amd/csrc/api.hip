@@ -666,9 +666,10 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
     fused_geometry(g, H, W, R, precision, model, 0, TW);
     return check_acc_size(g, d);
   }
+  const int mult = strip_row_multiple(d, R, precision, TW, 0);
   for (int f10 : {3, 5, 7, 10, 13, 15, 20, 30, 40}) {
     const int nsy = std::min(nmax, std::max(1, (nsy0 * f10 + 5) / 10));
-    const int th = effective(((H + nsy - 1) / nsy + kB - 1) / kB * kB);
+    const int th = effective(((H + nsy - 1) / nsy + mult - 1) / mult * mult);
     if (acc_fits(th) && std::find(ths.begin(), ths.end(), th) == ths.end()) ths.push_back(th);
   }
   // probe terms: a few fixed frequencies (the cost does not depend on them)

@@ -58,6 +58,15 @@ constexpr int kRingPadMF = 4;
 inline constexpr bool use_mf(int TW, int prec, int R) {
   return prec == 1 || prec == 2 || (TW == kTWMax && prec == 0 && R >= 12);
 }
+// FP32 matrix-core instances from R = 21 run both passes on the matrix cores
+// in a one-barrier pipeline (two staging buffers, two more ring steps): there
+// one workgroup fills a CU's LDS with or without it, and the pipeline
+// overlaps the products with the modulation on the VALU.  Below R = 21 the
+// extra LDS would halve the resident workgroups.
+inline constexpr bool use_pipe(int prec, int R, bool mf) { return mf && prec == 0 && R >= 21; }
+// Ring row padding of those instances, in floats (16 mod 32: conflict-free
+// reads of 4 rows x 16 columns).
+constexpr int kRingPadPipe = 16;
 // FP32 staging row width of the matrix-core horizontal pass: 16 + 4*ceil((16
 // + 2R)/4) samples read per row (k-blocks of 4), rounded to 4 mod 8 floats so
 // that the 16 rows x 4 columns one operand read touches fall on distinct banks.
@@ -147,6 +156,10 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW = kTW, int mf = 0);
 int fused_blocks_per_cu(int d, int R, int prec, int TW = kTW, int valu = 0);
 // 1 if a launch of this (d, R, variant, width) runs a pass on the matrix cores
 int fused_uses_mf(int d, int R, int prec, int TW, int valu);
+// Strip heights of this instance are multiples of this many rows: 16 for the
+// pipelined FP32 matrix-core instances (their vertical pass takes pairs of
+// 8-row steps), else kB.
+int strip_row_multiple(int d, int R, int prec, int TW, int valu);
 // Strip width for a launch into *TW.  requested: kTW or kTWMax forces it
 // (kTWMax needs a wide-strip instance: d = 3, a specialised radius, variants
 // 0-2, W >= kTWMax; else BF_EUNSUPPORTED); 0 picks kTWMax where such an

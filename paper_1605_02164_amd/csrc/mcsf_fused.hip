@@ -42,12 +42,17 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
   const int taps_al = (ntap4 + 7) / 8 * 8;
   const int tapp_al = (R + 1 + 3) / 4 * 4;
   const int lag = lag_steps(R);
+  // FP32 matrix-core instances from R = 21 run the one-barrier pipeline:
+  // two staging buffers and two more ring steps
+  const bool pipe = use_pipe(prec, R, mf != 0);
   // variant 3 sizes the ring for the largest n (three boxes)
-  const int RS = ring_steps(R, vb ? 3 : 0) * kB, CRS = (lag + 2) * kB;
+  const int RS = (ring_steps(R, vb ? 3 : 0) + (pipe ? 2 : 0)) * kB, CRS = (lag + 2) * kB;
   const size_t fl = (size_t)taps_al + (lp ? 2 * (size_t)tapp_al : 0) +
-                    (size_t)kB * NC * (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
-                                          : (mf ? stage_width_mf32(R) : stage_width(R, TW))) +
-                    (size_t)(lp ? RS / 2 : RS) * (NC * TW + (mf && lp ? kRingPadMF : 0)) +
+                    (size_t)kB * NC * (pipe ? 2 : 1) *
+                        (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
+                            : (mf ? stage_width_mf32(R) : stage_width(R, TW))) +
+                    (size_t)(lp ? RS / 2 : RS) *
+                        (NC * TW + (mf && lp ? kRingPadMF : 0) + (pipe ? kRingPadPipe : 0)) +
                     (size_t)CRS * 2 * TW +
                     (vb ? (size_t)16 * NC * TW : 0);
   return fl * sizeof(float);
@@ -137,6 +142,10 @@ int fused_uses_mf(int d, int R, int prec, int TW, int valu) {
   return inst && use_mf(TW, prec, R) ? 1 : 0;
 }
 
+int strip_row_multiple(int d, int R, int prec, int TW, int valu) {
+  return fused_uses_mf(d, R, prec, TW, valu) && use_pipe(prec, R, true) ? 2 * kB : kB;
+}
+
 int choose_strip_width(int d, int R, int prec, int H, int W, int requested, int* TW) {
   const bool wide_ok = d == 3 && prec <= 2 && W >= kTWMax && specialised_radius(R) &&
                        fused_lds_bytes(d, R, prec, kTWMax) <= 160 * 1024;
@@ -205,9 +214,10 @@ int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int
     return fail(BF_EUNSUPPORTED, "window too large for the fused kernel's LDS budget");
   // one strip covers the image: taller strips only add padded rows (and
   // would push accumulator offsets past 32 bits for huge requests)
-  const int one = (H + kB - 1) / kB * kB;
+  const int mult = strip_row_multiple(d, R, prec, TW, valu);
+  const int one = (H + mult - 1) / mult * mult;
   if (requested > 0) {
-    *TH = (int)std::min<long>(((long)requested + kB - 1) / kB * kB, one);
+    *TH = (int)std::min<long>(((long)requested + mult - 1) / mult * mult, one);
     return BF_OK;
   }
   if (!valu && (*TH = tuned_height(d, R, prec, H, W, TW)) > 0) return BF_OK;
@@ -231,8 +241,9 @@ int model_strip_height(int d, int R, int prec, int H, int W, int TW, int valu) {
   constexpr double kCacheShare = 0.6 * 256.0 * 1024 * 1024;
   double best = -1.0;
   int best_th = kB;
-  for (int nsy = 1; nsy <= (H + kB - 1) / kB; ++nsy) {
-    const int th = ((H + nsy - 1) / nsy + kB - 1) / kB * kB;
+  const int mult = strip_row_multiple(d, R, prec, TW, valu);
+  for (int nsy = 1; nsy <= (H + mult - 1) / mult; ++nsy) {
+    const int th = ((H + nsy - 1) / nsy + mult - 1) / mult * mult;
     const long nwg = (long)nsx * ((H + th - 1) / th);
     const long waves = (nwg + slots - 1) / slots;
     const double resident = (double)std::min<long>(nwg, slots) * th * TW * (d + 1) * 4.0;

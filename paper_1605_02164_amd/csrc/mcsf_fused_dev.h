@@ -376,7 +376,15 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
   constexpr int B = kB;
   constexpr bool MFV = MF && (PREC == 1 || PREC == 2);   // vertical pass on the matrix cores too
-  constexpr int RST = NC * TW + (MFV ? kRingPadMF : 0);   // ring row stride: [ch][x]
+  // PIPE (FP32 matrix-core instances, R >= 21): both passes on the matrix
+  // cores, the vertical one over pairs of steps (16 output rows), and one
+  // barrier per step (the loop below).  That needs two staging buffers and
+  // two more ring steps: step g is written while the pair's window, steps
+  // g - 2 - lag .. g - 1, is read.  Its ring rows are padded by 16 floats:
+  // an operand read of the vertical pass touches 4 consecutive rows x 16
+  // columns, which a stride of 16 mod 32 floats spreads over the LDS banks.
+  constexpr bool PIPE = use_pipe(PREC, RC, MF);
+  constexpr int RST = NC * TW + (MFV ? kRingPadMF : 0) + (PIPE ? kRingPadPipe : 0);   // ring row stride: [ch][x]
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
   constexpr bool VB = PREC == 3;                 // running-sum vertical pass
@@ -393,15 +401,17 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
   const int tapp_al = (R + 1 + 3) / 4 * 4;
-  const int RS = a.RSB * B, CRS = a.CRB * B;
-  // LDS carve-up: FP32 taps | packed tap pairs (16-bit modes) | staging |
-  // ring | cos/sin ring.  16-bit modes store the ring as row pairs.
+  const int RS = (a.RSB + (PIPE ? 2 : 0)) * B, CRS = a.CRB * B;
+  // LDS carve-up: FP32 taps | packed tap pairs (16-bit modes) | staging (two
+  // buffers with PIPE) | ring | cos/sin ring.  16-bit modes store the ring as
+  // row pairs.
+  const int stage_floats = LP ? B * NC * SW / 2 : B * NC * SW;
   float* s_taps = lds;
   unsigned* s_te = reinterpret_cast<unsigned*>(s_taps + taps_al);
   unsigned* s_to = s_te + (LP ? tapp_al : 0);
   float* s_stage = reinterpret_cast<float*>(s_to + (LP ? tapp_al : 0));
   unsigned short* s_stage16 = reinterpret_cast<unsigned short*>(s_stage);
-  float* s_ring = s_stage + (LP ? B * NC * SW / 2 : B * NC * SW);
+  float* s_ring = s_stage + stage_floats * (PIPE ? 2 : 1);
   unsigned* s_ring32 = reinterpret_cast<unsigned*>(s_ring);
   unsigned short* s_ring16 = reinterpret_cast<unsigned short*>(s_ring);
   float* s_cs = s_ring + (LP ? RS / 2 : RS) * RST;
@@ -414,8 +424,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
 
   for (int i = tid; i < taps_al; i += NT) s_taps[i] = i < 2 * R + 1 ? a.taps[i] : 0.0f;
   for (int i = tid; i < (LP ? RS / 2 : RS) * RST; i += NT) s_ring[i] = 0.0f;
-  for (int i = tid; i < B * NC * (SW - MW); i += NT) {   // staging padding columns
-    const int row = i / (SW - MW), col = MW + i % (SW - MW);
+  for (int i = tid; i < (PIPE ? 2 : 1) * B * NC * (SW - MW); i += NT) {   // staging padding columns
+    const int row = i / (SW - MW), col = MW + i % (SW - MW);   // rows of both buffers (PIPE)
     if constexpr (LP) s_stage16[row * SW + col] = 0;
     else s_stage[row * SW + col] = 0.0f;
   }
@@ -607,20 +617,26 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
 
   // ring positions of the current step (rows written) and of the step lag
   // behind it (rows the vertical pass starts from), advanced by B per step
+  const int RSBk = RS / B;
   int rslot = 0, cslot = 0;
-  int rslot_lag = (a.RSB - lag % a.RSB) % a.RSB * B, cslot_lag = (a.CRB - lag % a.CRB) % a.CRB * B;
-  float wr[D];
-  float tw = 1.0f;
-  auto load_term = [&](int t) {
+  int rslot_lag = (RSBk - lag % RSBk) % RSBk * B, cslot_lag = (a.CRB - lag % a.CRB) % a.CRB * B;
+  float wr[D];       // frequencies of the term being modulated
+  float tw = 1.0f;   // weight of the term being demodulated
+  auto load_wr = [&](int t) {
 #pragma unroll
     for (int m = 0; m < D; ++m) wr[m] = ld_const(a.terms, t * NP + m);
-    tw = a.weights ? ld_const(a.weights, t) : 1.0f;
+  };
+  auto load_tw = [&](int t) { tw = a.weights ? ld_const(a.weights, t) : 1.0f; };
+  auto load_term = [&](int t) {
+    load_wr(t);
+    load_tw(t);
   };
 
-  // One pipeline step s of term t; fcur/acur hold this step's prefetched
-  // data and are refilled for the step two ahead.
-  auto step = [&](int t, int s, float (&fcur)[MI][D], float (&acur)[NACC]) {
-    // ---- 1. modulation ---------------------------------------------------------
+  // ---- 1. modulation of step s of term t from the prefetched f values
+  // fcur into the staging buffer stg (16-bit modes: its 16-bit view) and
+  // the cos/sin ring rows at cs0 ------------------------------------------------
+  auto modulate = [&](int t, int s, const float (&fcur)[MI][D], float* stg, int cs0) {
+    unsigned short* stg16 = reinterpret_cast<unsigned short*>(stg);
 #pragma unroll
     for (int i = 0; i < MI; ++i) {
       if (i * NT < nmod && tid + i * NT < nmod) {
@@ -648,7 +664,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         c = in ? c : 0.0f;
         sn = in ? sn : 0.0f;
         if constexpr (LP) {
-          unsigned short* st = s_stage16 + m_off[i];
+          unsigned short* st = stg16 + m_off[i];
 #pragma unroll
           for (int m = 0; m < D; ++m) {
             st[(2 * m) * SW] = to16<PREC>(c * fv[m]);
@@ -657,7 +673,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
           st[(2 * D) * SW] = to16<PREC>(c);
           st[(2 * D + 1) * SW] = to16<PREC>(sn);
         } else {
-          float* st = s_stage + m_off[i];
+          float* st = stg + m_off[i];
 #pragma unroll
           for (int m = 0; m < D; ++m) {
             st[(2 * m) * SW] = c * fv[m];
@@ -668,38 +684,91 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         }
         const int xc = m_x[i] - x0;
         if (xc >= 0 && xc < TW) {
-          s_cs[(cslot + m_rr[i]) * CST + xc] = c;
-          s_cs[(cslot + m_rr[i]) * CST + TW + xc] = sn;
+          s_cs[(cs0 + m_rr[i]) * CST + xc] = c;
+          s_cs[(cs0 + m_rr[i]) * CST + TW + xc] = sn;
         }
       }
     }
-    // the step two ahead, possibly in the next term(s)
-    int s2 = s + 2, t2 = t;
-    if (s2 >= steps) { s2 -= steps; ++t2; }
-    if (s2 >= steps) { s2 -= steps; ++t2; }
-    load_f(fcur, s2);
-    __syncthreads();
+  };
 
-    // ---- 2. horizontal pass ------------------------------------------------------
+  // FP32 matrix-core horizontal pass in two parts, so that the pipelined
+  // schedule can place the vertical pass's ring loads between the products
+  // and the ring stores: the banded product of the staging buffer stg, then
+  // the store of its results into ring rows r0.
+  auto hmf = [&](const float* stg) {
+    const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+    const float* arow = stg + (16 * mb + (ln & 15)) * SW + 16 * nb + (ln >> 4);
+    f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < KS4; ++k) d = mfma4(arow[4 * k], hb4[k], d);
+    return d;
+  };
+  auto hmf_store = [&](const f32x4_t& d, int r0) {
+    const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
+      s_ring[(r0 + row) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)] = d[v];
+    }
+  };
+
+  // ---- FP32 matrix-core vertical pass of a pair of steps (PIPE instances) --
+  // out[r][n] = sum_k w[k - r] ring[k][n] over the pair's 16 output rows r
+  // and 16 + 2R window rows k (k-blocks of 4: KS4 of them, the horizontal
+  // pass's count): the tap operand is the horizontal pass's register hb4
+  // (lane l holds w[4kb + l/16 - l%16], here as A[r = l%16][k = l/16]); the
+  // ring operand is one value per lane, B[k = l/16][n = l%16].  Wave w takes
+  // pair m = w % NP (its cos and sin channels, two product chains) and
+  // columns 16(w/NP) .. +15; lane l then holds output rows 4(l/16) .. +3 of
+  // column l%16, demodulates them with the cos/sin of the output pixels and
+  // updates four accumulator rows.  pr: strip row of the pair's first output
+  // row; rl / cl: ring / cos-sin rows of its first window row; ap: this
+  // lane's accumulators of the pair (prefetched; unused for t = 0).
+  auto load_accp = [&](float (&dst)[4], int t, int pr) {
+    if (t > 0 && t < t1) {
+      const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+      const unsigned o =
+          (unsigned)(m * a.Hp + y0 + pr + 4 * (ln >> 4)) * Wp + x0 + 16 * nb + (ln & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
+    }
+  };
+  auto vpair = [&](int t, int pr, const float (&ap)[4], int rl, int cl) {
+    const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+    const int col = 16 * nb + (ln & 15);
+    // ring rows rl + 4k + l/16: k-blocks of 4 rows start at multiples of 4
+    // (rl is a multiple of 8, the ring of 8), so only the uniform part wraps
+    const float* cc = s_ring + ((ln >> 4) * RST + (2 * m) * TW + col);
+    f32x4_t dc = {0.0f, 0.0f, 0.0f, 0.0f}, ds = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < KS4; ++k) {
+      const int row = wrap(rl + 4 * k, RS);
+      dc = mfma4(hb4[k], cc[row * RST], dc);
+      ds = mfma4(hb4[k], cc[row * RST + TW], ds);
+    }
+    const unsigned o = (unsigned)(m * a.Hp + y0 + pr + 4 * (ln >> 4)) * Wp + x0 + col;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float* cs = s_cs + wrap(cl + R + 4 * (ln >> 4) + v, CRS) * CST + col;
+      const float q = fmaf(cs[TW], ds[v], cs[0] * dc[v]);
+      buf_store1(acc_rsrc, 4u * (o + v * Wp), fmaf(tw, q, t > 0 ? ap[v] : 0.0f));
+    }
+  };
+
+  // ---- 2. horizontal pass of the staging buffer stg into ring rows r0 -------
+  auto hpass_step = [&](const float* stg, int r0) {
+    const unsigned short* stg16 = reinterpret_cast<const unsigned short*>(stg);
+    const int rslot = r0;
     // Matrix-core horizontal pass: the step's staging rows m = NC row +
     // channel (16 NP of them) form NP blocks of 16; wave w takes block w % NP
     // and output columns 16(w/NP) .. +15.  Lane l's results are items
     // m = 16(w%NP) + 4(l/16) + v, column 16(w/NP) + l%16.
     if constexpr (MF && !LP) {
       // FP32: k-blocks of 4 samples (one per lane group of 16)
-      const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
-      const float* arow = s_stage + (16 * mb + (ln & 15)) * SW + 16 * nb + (ln >> 4);
-      f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int k = 0; k < KS4; ++k) d = mfma4(arow[4 * k], hb4[k], d);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
-        s_ring[(rslot + row) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)] = d[v];
-      }
+      hmf_store(hmf(stg), rslot);
     } else if constexpr (MF) {
       const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
-      const unsigned short* arow = s_stage16 + (16 * mb + (ln & 15)) * SW + 16 * nb + 8 * (ln >> 4);
+      const unsigned short* arow = stg16 + (16 * mb + (ln & 15)) * SW + 16 * nb + 8 * (ln >> 4);
       f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < KSH; ++k)
@@ -719,7 +788,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (LP) {
         const unsigned* src =
-            reinterpret_cast<const unsigned*>(s_stage16 + (p1_rr * NC + p1_ch) * SW) + p1_xq * 2;
+            reinterpret_cast<const unsigned*>(stg16 + (p1_rr * NC + p1_ch) * SW) + p1_xq * 2;
         hpass_lp<PREC, RC>(src, tpe, tpo, s_te, s_to, R, acc);
         // row r goes to the low (even r) or high (odd r) half of pair-row r/2
         const int r = rslot + p1_rr;
@@ -742,64 +811,18 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
           for (int p = 0; p < 4; ++p) dst[2 * p] = to16<PREC>(acc[p]);
         }
       } else {
-        hpass<RC>(s_stage + (p1_rr * NC + p1_ch) * SW + p1_xq * 4, tapr, s_taps, ntap4, acc);
+        hpass<RC>(stg + (p1_rr * NC + p1_ch) * SW + p1_xq * 4, tapr, s_taps, ntap4, acc);
         *reinterpret_cast<float4*>(s_ring + (rslot + p1_rr) * RST + p1_ch * TW + p1_xq * 4) =
             make_float4(acc[0], acc[1], acc[2], acc[3]);
       }
     }
-    __syncthreads();
+  };
 
-    // ---- 3. vertical pass, demodulation, accumulation -------------------------------
-    if constexpr (VB) {
-      // input row i = s*B + j of the term (strip row i - R) completes the box
-      // sum of output row i - 2R; rows before the term's first (i < k w) are
-      // the previous term's and read as zero
-      if (vb_on) {
-        if (s == 0) vI1 = vI2 = vI3 = 0.0;
-        const float* col = s_ring + vb_ch * TW + vb_x;
-        // all ring reads of the step first (no branch between them): row i
-        // and rows i - k w, k <= n; a lag that is not part of the sum (k > n,
-        // or a row before the term's first) reads an in-ring slot and gets
-        // weight zero (ring values are finite)
-        const int o1 = vw, o2 = vn >= 2 ? 2 * vw : 0, o3 = vn >= 3 ? 3 * vw : 0;
-        float u[B][4];
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-          const int sl = wrap(rslot + j, RS);
-          const int s1 = sl - o1, s2 = sl - o2, s3 = sl - o3;
-          u[j][0] = col[sl * RST];
-          u[j][1] = col[(s1 < 0 ? s1 + RS : s1) * RST];
-          u[j][2] = col[(s2 < 0 ? s2 + RS : s2) * RST];
-          u[j][3] = col[(s3 < 0 ? s3 + RS : s3) * RST];
-        }
-        // rows before the term's first only occur in its first steps: one
-        // uniform test per step, then a loop without per-row conditions
-        auto rows = [&](auto head) {
-          constexpr bool HEAD = decltype(head)::value;
-#pragma unroll
-          for (int j = 0; j < B; ++j) {
-            const int i = s * B + j;
-            const double c1 = !HEAD || i >= o1 ? vc1 : 0.0;
-            const double c2 = !HEAD || i >= o2 ? vc2 : 0.0;
-            const double c3 = !HEAD || i >= o3 ? vc3 : 0.0;
-            double v = (double)u[j][0];
-            v = fma(c1, (double)u[j][1], v);
-            v = fma(c2, (double)u[j][2], v);
-            v = fma(c3, (double)u[j][3], v);
-            vI1 += v;
-            vI2 += vI1;
-            vI3 += vI2;
-            // output row i - 2R; rows outside 0..TH-1 land in ring slots that
-            // are rewritten before the demodulation reads them
-            s_vr[((i - 2 * R) & 15) * RST + vb_ch * TW + vb_x] =
-                (float)fma(ve3, vI3, fma(ve2, vI2, ve1 * vI1));
-          }
-        };
-        if (s * B >= vn * vw) rows(std::false_type{});
-        else rows(std::true_type{});
-      }
-      __syncthreads();
-    }
+  // ---- 3. vertical pass of step s of term t (weight tw), demodulation and
+  // accumulation: ring rows from rl, cos/sin rows from cl; acur holds this
+  // step's prefetched accumulators -------------------------------------------
+  auto vpass_step = [&](int t, int s, const float (&acur)[NACC], int rl, int cl) {
+    const int rslot_lag = rl, cslot_lag = cl;
     if (MFV && s >= lag) {
       if constexpr (MFV) {
         // out[r][n] for the pair's cos and sin channels over this wave's 16
@@ -875,6 +898,73 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         buf_store1(acc_rsrc, 4u * (o + Wp), fmaf(tw, v1, t > 0 ? acur[1] : 0.0f));
       }
     }
+  };
+
+  // One pipeline step s of term t (two barriers; every instance but PIPE);
+  // fcur/acur hold this step's prefetched data and are refilled for the step
+  // two ahead.
+  auto step = [&](int t, int s, float (&fcur)[MI][D], float (&acur)[NACC]) {
+    modulate(t, s, fcur, s_stage, cslot);
+    // the step two ahead, possibly in the next term(s)
+    int s2 = s + 2, t2 = t;
+    if (s2 >= steps) { s2 -= steps; ++t2; }
+    if (s2 >= steps) { s2 -= steps; ++t2; }
+    load_f(fcur, s2);
+    __syncthreads();
+    hpass_step(s_stage, rslot);
+    __syncthreads();
+    // variant 3: running sums of the rows just written
+    if constexpr (VB) {
+      // input row i = s*B + j of the term (strip row i - R) completes the box
+      // sum of output row i - 2R; rows before the term's first (i < k w) are
+      // the previous term's and read as zero
+      if (vb_on) {
+        if (s == 0) vI1 = vI2 = vI3 = 0.0;
+        const float* col = s_ring + vb_ch * TW + vb_x;
+        // all ring reads of the step first (no branch between them): row i
+        // and rows i - k w, k <= n; a lag that is not part of the sum (k > n,
+        // or a row before the term's first) reads an in-ring slot and gets
+        // weight zero (ring values are finite)
+        const int o1 = vw, o2 = vn >= 2 ? 2 * vw : 0, o3 = vn >= 3 ? 3 * vw : 0;
+        float u[B][4];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const int sl = wrap(rslot + j, RS);
+          const int s1 = sl - o1, s2 = sl - o2, s3 = sl - o3;
+          u[j][0] = col[sl * RST];
+          u[j][1] = col[(s1 < 0 ? s1 + RS : s1) * RST];
+          u[j][2] = col[(s2 < 0 ? s2 + RS : s2) * RST];
+          u[j][3] = col[(s3 < 0 ? s3 + RS : s3) * RST];
+        }
+        // rows before the term's first only occur in its first steps: one
+        // uniform test per step, then a loop without per-row conditions
+        auto rows = [&](auto head) {
+          constexpr bool HEAD = decltype(head)::value;
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            const int i = s * B + j;
+            const double c1 = !HEAD || i >= o1 ? vc1 : 0.0;
+            const double c2 = !HEAD || i >= o2 ? vc2 : 0.0;
+            const double c3 = !HEAD || i >= o3 ? vc3 : 0.0;
+            double v = (double)u[j][0];
+            v = fma(c1, (double)u[j][1], v);
+            v = fma(c2, (double)u[j][2], v);
+            v = fma(c3, (double)u[j][3], v);
+            vI1 += v;
+            vI2 += vI1;
+            vI3 += vI2;
+            // output row i - 2R; rows outside 0..TH-1 land in ring slots that
+            // are rewritten before the demodulation reads them
+            s_vr[((i - 2 * R) & 15) * RST + vb_ch * TW + vb_x] =
+                (float)fma(ve3, vI3, fma(ve2, vI2, ve1 * vI1));
+          }
+        };
+        if (s * B >= vn * vw) rows(std::false_type{});
+        else rows(std::true_type{});
+      }
+      __syncthreads();
+    }
+    vpass_step(t, s, acur, rslot_lag, cslot_lag);
     load_acc(acur, t2, s2);
     rslot = wrap(rslot + B, RS);
     cslot = wrap(cslot + B, CRS);
@@ -897,6 +987,74 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   else load_acc(aB, t0 + 1, 0);
   load_term(t0);
   const int total = (t1 - t0) * steps;
+  if constexpr (PIPE) {
+    // Software pipeline, one barrier per step: iteration g runs the
+    // horizontal pass of global step g, the modulation of step g + 1 and,
+    // when step g - 1 completes a pair of output steps (s - lag odd), the
+    // pair's vertical pass: matrix-core products of both passes overlap the
+    // modulation on the VALU.  Staging and f are double-buffered by step
+    // parity (f: fA even steps, fB odd); a strip has an even number of
+    // output steps (TH a multiple of 16, checked at launch).
+    float* const stg0 = s_stage;
+    float* const stg1 = s_stage + stage_floats;
+    float ap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    load_accp(ap, t0, 0);
+    modulate(t0, 0, fA, stg0, 0);
+    load_f(fA, 2 % steps);             // step 2 (the next term's first when steps = 2)
+    __syncthreads();
+    int tv = t0, sv = 0;               // step g - 1 (advanced from g = 1 on)
+    int tm = t0, sm = 1;               // step modulated in iteration g (g + 1)
+    if (sm == steps) { sm = 0; ++tm; }
+    if (tm < t1) load_wr(tm);
+    // ring rows of step g (horizontal pass) and of step g - 2 - lag (the
+    // window of the pair ending at step g - 1); cos/sin rows of step g + 1
+    // (modulation) and of step g - 2 - lag
+    int rh = 0;
+    int rl = (RSBk - (lag + 2) % RSBk) % RSBk * B;
+    int cm = B % CRS;
+    int cl = (a.CRB - (lag + 2) % a.CRB) % a.CRB * B;
+    auto iter = [&](int g, const float* stg_h, float* stg_m, float (&fm)[MI][D]) {
+      if (g >= 1 && sv > lag && ((sv - lag) & 1)) {
+        // the pair (sv - 1, sv) of term tv and the horizontal pass of step
+        // g in one block; the ring stores after the pair's ring loads
+        const f32x4_t hd = hmf(stg_h);
+        vpair(tv, (sv - 1 - lag) * B, ap, rl, cl);
+        hmf_store(hd, rh);
+        int ps = sv + 1, pt = tv;      // the next pair's accumulators
+        if (ps >= steps) { ps = lag; ++pt; }
+        load_accp(ap, pt, (ps - lag) * B);
+      } else {
+        hpass_step(stg_h, rh);
+      }
+      if (g >= 1 && ++sv == steps) {
+        sv = 0;
+        if (++tv < t1) load_tw(tv);
+      }
+      rl = wrap(rl + B, RS);
+      cl = wrap(cl + B, CRS);
+      if (g + 1 < total) {
+        modulate(tm, sm, fm, stg_m, cm);
+        int s3 = sm + 2;               // f rows of step g + 3
+        if (s3 >= steps) s3 -= steps;
+        if (s3 >= steps) s3 -= steps;
+        load_f(fm, s3);
+        if (++sm == steps) {
+          sm = 0;
+          if (++tm < t1) load_wr(tm);
+        }
+        cm = wrap(cm + B, CRS);
+      }
+      __syncthreads();
+      rh = wrap(rh + B, RS);
+    };
+    for (int g = 0; g < total; g += 2) {
+      iter(g, stg0, stg1, fB);
+      if (g + 1 < total) iter(g + 1, stg1, stg0, fA);
+    }
+    // the last pair (its second step is the launch's last)
+    vpair(tv, (sv - 1 - lag) * B, ap, rl, cl);
+    return;
+  }
   int t = t0, s = 0;
   for (int gs = 0; gs < total; gs += 2) {
     step(t, s, fA, aA);
@@ -1018,6 +1176,15 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
     }
     if (a.TWc != TW) return hipErrorInvalidValue;   // no instance for this width
     nwg = a.nsx * a.nsy;
+  }
+  // the pipelined instances take pairs of output steps: whole pairs per strip
+  if (mf && use_pipe(PREC, R, true)) {
+    if constexpr (std::is_same_v<A, BatchArgs>) {
+      for (int k = 0; k < a.n; ++k)
+        if (a.req[k].TH % (2 * kB)) return hipErrorInvalidValue;
+    } else if (a.TH % (2 * kB)) {
+      return hipErrorInvalidValue;
+    }
   }
   const size_t lds = fused_lds_bytes(D, R, PREC, TW, mf);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

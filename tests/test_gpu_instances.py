@@ -107,7 +107,10 @@ def test_instance_against_oracle(d, R, prec, TW, valu):
     got, o = P.bf_vec_ex(fg, sigma, C, K, seed, precision=prec, tile_h=TH, tile_w=TW,
                          valu_only=bool(valu), num_out=num, z_out=zo, return_opts=True)
     got, num, zo = host(got), host(num), host(zo)
-    assert o.tile_w_used == TW and o.tile_h_used == TH
+    # the pipelined FP32 matrix-core instances (R >= 21) take pairs of 8-row
+    # steps: strip heights are rounded up to 16 rows there
+    pipe = prec == "fp32" and _mf_expected(prec, R, TW, valu) and R >= 21
+    assert o.tile_w_used == TW and o.tile_h_used == (32 if pipe else TH)
     assert o.mfma_used == _mf_expected(prec, R, TW, valu)
     f64 = f.astype(np.float64)
     W_ = O.whiten(C)

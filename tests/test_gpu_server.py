@@ -85,8 +85,9 @@ def test_mix_matches_standalone_bitwise(pools):
 
 
 def test_batched_launches_share_requests(pools):
-    # many small requests of one instance arriving together: with N given and
-    # centring off no reduction is needed, so all 40 are ready at admission
+    # many small requests of one instance arriving together: with N given,
+    # centring off and BF16 storage no reduction is needed (FP16 storage needs
+    # the image range for its range check), so all 40 are ready at admission
     # and the first round packs them into 16 + 16 + 8 (whole K in one chunk)
     f = pools[0]
     C = 0.05 ** 2 * np.eye(3)
@@ -96,7 +97,7 @@ def test_batched_launches_share_requests(pools):
         tickets = []
         for (y0, x0, H, W) in specs:
             t, out = srv.submit(f[y0:y0 + H, x0:x0 + W], 2.0, C, 6, seed=9, N=16, center=False,
-                                arrival=start)
+                                arrival=start, precision="bf16")
             tickets.append((t, out))
         srv.drain(timeout=60.0)
         stats = srv.stats()
@@ -104,7 +105,7 @@ def test_batched_launches_share_requests(pools):
         assert stats["rounds"] == 1 and stats["launches"] == 3, stats
         for (y0, x0, H, W), (t, out) in list(zip(specs, tickets))[::7]:
             ref, _ = P.bf_vec_ex(f[y0:y0 + H, x0:x0 + W].contiguous(), 2.0, C, 6, seed=9, N=16,
-                                 center=False, precision="fp16")
+                                 center=False, precision="bf16")
             torch.cuda.synchronize()
             assert torch.equal(out, ref)
             st = srv.poll(t)
