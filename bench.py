@@ -527,6 +527,26 @@ def study_lab(P, torch, log_fn):
             "round_trip_max_abs": float(np.abs(rt - rgb).max())}
 
 
+def write_study(path, rec):
+    """A study's record as a short markdown file: command, table, raw JSON."""
+    rows = rec.get("rows")
+    lines = [f"# {rec['study']}", "", f"Command: `{rec['command']}`", ""]
+    meta = {k: v for k, v in rec.items() if k not in ("rows", "study", "command")}
+    lines += [f"Settings: {json.dumps(meta)}", ""]
+    if isinstance(rows, list) and rows:
+        keys = list(rows[0].keys())
+        lines += ["| " + " | ".join(keys) + " |", "|" + "---|" * len(keys)]
+        for r in rows:
+            lines.append("| " + " | ".join(f"{r[k]:.4g}" if isinstance(r[k], float) else str(r[k])
+                                           for k in keys) + " |")
+    elif isinstance(rows, dict):
+        for k, v in rows.items():
+            lines.append(f"- {k}: {json.dumps(v)}")
+    lines += ["", "```json", json.dumps(rec), "```", ""]
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -558,6 +578,8 @@ def main():
                     help="run one of the paper-study analogues instead of the benchmark and "
                          "print its JSON")
     ap.add_argument("--realizations", type=int, default=400)
+    ap.add_argument("--out", help="with --study: also write the result (and the command line) "
+                                  "to this markdown file")
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters against known traffic) and exit")
@@ -578,7 +600,10 @@ def main():
                else study_lab(P, torch, log) if args.study == "lab"
                else study_spatial(P, torch, log) if args.study == "spatial"
                else study_mse(P, torch, log, args.realizations))
+        rec["command"] = "python bench.py " + " ".join(sys.argv[1:])
         print(json.dumps(rec), flush=True)
+        if args.out:
+            write_study(args.out, rec)
         return
 
     if args.serve_only:
