@@ -187,19 +187,28 @@ def cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=None, crop=1024, direct_cro
     return rec
 
 
-def serving_run(args, P, torch, log_fn):
+def serving_run(args, P, torch, log_fn, policy="share", graph_rounds=False, autotune=False,
+                host_io=False, n=None, rate=None):
     """Serving workload: requests with square sides log-uniform in
     [256, 2048], d in {3, 6}, sigma_s in {2..8}, C = sigma_r^2 I with sigma_r
     ~ U[0.05, 0.2], K in {64, 128, 256}, FP16 storage.  Images are crops (at
     request-seeded offsets, row pitch 2048) of two resident 2048^2 images:
-    Voronoi colour (d = 3) and colour plus correlated channels (d = 6)."""
+    Voronoi colour (d = 3) and colour plus correlated channels (d = 6).  With
+    host_io the pools and the results are in pinned host memory and the
+    server uploads each crop and downloads each result (inside the latency).
+    policy / graph_rounds / autotune: the server's round policy, graph-captured
+    rounds, and strip heights measured per size class (warm-up covers every
+    class, so no measurement falls in the timed runs).  rate: Poisson arrival
+    rate in requests/s (default: args.serve_load x this run's capacity)."""
     import numpy as np
     from synth import serving_requests, voronoi_image, feature_image
     dev = torch.device("cuda:0")
-    n = args.serve_requests
-    log_fn("serving: generating the 2048^2 image pools")
-    pool = {3: torch.from_numpy(voronoi_image(2048, 2048, 3, 64, 0.0, 1.0, 0.02, seed=3003)).to(dev),
-            6: torch.from_numpy(feature_image(2048, 2048, 64, seed=3004, smooth_sigma=32.0)).to(dev)}
+    n = n or args.serve_requests
+    log_fn(f"serving ({policy}, graph_rounds={graph_rounds}, autotune={autotune}, "
+           f"host_io={host_io}): generating the 2048^2 image pools")
+    pool = {3: torch.from_numpy(voronoi_image(2048, 2048, 3, 64, 0.0, 1.0, 0.02, seed=3003)),
+            6: torch.from_numpy(feature_image(2048, 2048, 64, seed=3004, smooth_sigma=32.0))}
+    pool = {k: (v.pin_memory() if host_io else v.to(dev)) for k, v in pool.items()}
     reqs = serving_requests(n, seed=5, rate_hz=1.0)
     crops, total_px, outs = [], 0, []
     for q in reqs:
@@ -208,16 +217,25 @@ def serving_run(args, P, torch, log_fn):
         oy, ox = (int(v) for v in rng.integers(0, 2048 - s + 1, size=2))
         crops.append(pool[q["d"]][oy:oy + s, ox:ox + s])
         total_px += s * s
-    flat = torch.empty(sum(q["H"] * q["W"] * q["d"] for q in reqs), dtype=torch.float32, device=dev)
-    o = 0
-    for q in reqs:
-        m = q["H"] * q["W"] * q["d"]
-        outs.append(flat[o:o + m].view(q["H"], q["W"], q["d"]))
-        o += m
+    if host_io:
+        # results: a ring of pinned buffers of the largest size (requests far
+        # apart in the stream share one; only the timing is used here)
+        bufs = [torch.empty(2048 * 2048 * 6, dtype=torch.float32).pin_memory() for _ in range(32)]
+        for i, q in enumerate(reqs):
+            outs.append(bufs[i % len(bufs)][:q["H"] * q["W"] * q["d"]].view(q["H"], q["W"], q["d"]))
+    else:
+        flat = torch.empty(sum(q["H"] * q["W"] * q["d"] for q in reqs), dtype=torch.float32,
+                           device=dev)
+        o = 0
+        for q in reqs:
+            m = q["H"] * q["W"] * q["d"]
+            outs.append(flat[o:o + m].view(q["H"], q["W"], q["d"]))
+            o += m
     torch.cuda.synchronize()
     srv = P.Server(arena_bytes=args.serve_arena_gib << 30, max_active=args.serve_max_active,
                    quantum_us=args.serve_quantum_us, depth=args.serve_depth,
-                   streams=args.serve_streams)
+                   streams=args.serve_streams, policy=policy, graph_rounds=graph_rounds,
+                   autotune=autotune)
     dedup = not args.serve_no_dedup
 
     def submit_all(arrivals):
@@ -238,14 +256,19 @@ def serving_run(args, P, torch, log_fn):
             srv.forget(t)
         return sts
 
-    # warm-up: one small request of every kernel instance in the stream
+    # warm-up: one small request of every kernel instance in the stream; with
+    # autotune also one request of every (d, sigma_s, size class) present
     seen = {}
     for i, q in enumerate(reqs):
         seen.setdefault((q["d"], q["sigma_s"]), i)
+        if autotune:
+            seen.setdefault((q["d"], q["sigma_s"], int(np.floor(2 * np.log2(q["H"]) + 0.5))), i)
     warm = []
-    for (d, sig), i in seen.items():
+    for key, i in seen.items():
+        d, sig = key[0], key[1]
         C = (reqs[i]["sigma_r"] ** 2) * np.eye(d)
-        t, _ = srv.submit(pool[d][:96, :96], sig, C, 8, seed=1)
+        f = pool[d][:96, :96] if len(key) == 2 else crops[i]
+        t, _ = srv.submit(f, sig, C, 8, seed=1)
         warm.append(t)
     srv.drain(600.0)
     collect(warm)
@@ -262,8 +285,8 @@ def serving_run(args, P, torch, log_fn):
            "p50_ms": 1e3 * float(np.percentile([s["done"] - s["arrival"] for s in sts], 50))}
     log_fn(f"serving: capacity {capacity:.1f} req/s, {sat['mpix_s']:.1f} Mpix/s")
 
-    # 2. latency: Poisson arrivals at args.serve_load x capacity
-    rate = args.serve_load * capacity
+    # 2. latency: Poisson arrivals at args.serve_load x capacity (or the rate given)
+    rate = rate or args.serve_load * capacity
     arr = [q["arrival"] / rate for q in reqs]   # the generator's unit-rate arrival times
     log_fn(f"serving: {n} Poisson arrivals at {rate:.1f} req/s")
     t0 = srv.clock() + 0.5
@@ -274,18 +297,29 @@ def serving_run(args, P, torch, log_fn):
     span = max(s["done"] for s in sts) - t0
     stats = srv.stats()
     srv.close()
+    # slowdown: latency over the request's modelled size (pixels x terms),
+    # normalised by the median; shows how the policy treats small and large jobs
+    size = np.array([q["H"] * q["W"] * q["K"] for q in reqs], dtype=np.float64)
     # spot check: a few requests equal the same filter run alone, bit for bit
-    same = True
-    for i in (0, n // 2, n - 1):
-        q = reqs[i]
-        ref, _ = P.bf_vec_ex(crops[i].contiguous(), q["sigma_s"], (q["sigma_r"] ** 2) * np.eye(q["d"]),
-                             q["K"], seed=q["term_seed"], precision="fp16", dedup=dedup)
-        torch.cuda.synchronize()
-        same = same and bool(torch.equal(ref, outs[i]))
+    same = None
+    if not host_io:
+        same = True
+        for i in (0, n // 2, n - 1):
+            q = reqs[i]
+            ref, _ = P.bf_vec_ex(crops[i].contiguous(), q["sigma_s"],
+                                 (q["sigma_r"] ** 2) * np.eye(q["d"]), q["K"],
+                                 seed=q["term_seed"], precision="fp16", dedup=dedup)
+            torch.cuda.synchronize()
+            same = same and bool(torch.equal(ref, outs[i]))
+    small = size <= np.percentile(size, 50)
     rec = {
         "requests": n, "precision": "fp16", "load": args.serve_load, "rate_rps": rate,
+        "policy": policy, "graph_rounds": graph_rounds, "autotune": autotune,
+        "host_io": host_io,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
+        "p99_small_half_ms": float(np.percentile(lat[small], 99)),
+        "p99_large_half_ms": float(np.percentile(lat[~small], 99)),
         "mpix_s": total_px / span / 1e6, "total_mpix": total_px / 1e6,
         "saturated": sat, "quantum_us": args.serve_quantum_us, "depth": args.serve_depth,
         "streams": args.serve_streams, "dedup": dedup,
@@ -293,9 +327,23 @@ def serving_run(args, P, torch, log_fn):
         "launches": stats["launches"], "arena_peak_gib": stats["arena_peak"] / 2**30,
         "spot_check_bitwise_equal_alone": same,
     }
-    log_fn(f"serving: p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms, "
-           f"{rec['mpix_s']:.1f} Mpix/s")
+    log_fn(f"serving: p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms "
+           f"(small half {rec['p99_small_half_ms']:.1f}, large half "
+           f"{rec['p99_large_half_ms']:.1f}), {rec['mpix_s']:.1f} Mpix/s")
     return rec
+
+
+def serving_variants(args, P, torch, log_fn, rate):
+    """The serving run under each scheduler option, one at a time against the
+    default (processor sharing, direct launches, occupancy-model strips,
+    device-resident images), and with host-resident images and results; the
+    Poisson phase of every variant runs at the same arrival rate (the
+    default's), so the latencies compare like for like."""
+    out = []
+    for kw in (dict(policy="shortest"), dict(graph_rounds=True), dict(autotune=True),
+               dict(host_io=True, n=min(args.serve_requests, 1000))):
+        out.append(serving_run(args, P, torch, log_fn, rate=rate, **kw))
+    return out
 
 
 def plan_run(P, torch, log_fn, reps=200):
@@ -574,6 +622,9 @@ def main():
                     help="run every drawn term (default: merge equal +-Y draws, exact)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving run (no headline modes, CPU baseline or comparator)")
+    ap.add_argument("--serve-variants", action="store_true",
+                    help="also run the serving workload under each scheduler option "
+                         "(shortest-first, graph rounds, autotune, host I/O)")
     ap.add_argument("--study", choices=["table1", "mse", "lab", "spatial"],
                     help="run one of the paper-study analogues instead of the benchmark and "
                          "print its JSON")
@@ -607,7 +658,11 @@ def main():
         return
 
     if args.serve_only:
-        print(json.dumps({"serving": serving_run(args, P, torch, log)}), flush=True)
+        rec = {"serving": serving_run(args, P, torch, log)}
+        if args.serve_variants:
+            rec["serving_variants"] = serving_variants(args, P, torch, log,
+                                                       rec["serving"]["rate_rps"])
+        print(json.dumps(rec), flush=True)
         return
 
     if args.copy_kernel_mib:
@@ -714,9 +769,11 @@ def main():
             f"mean {direct['mcsf_vs_direct']['mean_dev']:.3g}, max "
             f"{direct['mcsf_vs_direct']['max_dev']:.3g} of the range")
 
-    serving = None
+    serving = variants = None
     if not args.no_serving:
         serving = serving_run(args, P, torch, log)
+        if args.serve_variants:
+            variants = serving_variants(args, P, torch, log, serving["rate_rps"])
 
     plans = None
     if not args.no_plan and not args.only:
@@ -788,6 +845,7 @@ def main():
         "cpu_baseline": cpu,
         "direct_comparator": direct,
         "serving": serving,
+        "serving_variants": variants,
         "plan": plans,
     }
     print(json.dumps(rec), flush=True)

@@ -321,8 +321,26 @@ typedef struct bf_server_config {
   int streams;          /* HIP streams for the rounds, 1..16; 0 = 4               */
   int depth;            /* rounds queued on the device at once, >= 1; 0 = 2        */
   double quantum_us;    /* modelled device time per request per round; 0 = 2000   */
-  int reserved[8];
+  int policy;           /* BF_POLICY_SHARE (0, default): every admitted request
+                           advances by one quantum per round (processor
+                           sharing); BF_POLICY_SHORTEST_FIRST: a round's budget
+                           of quantum x admitted requests goes to the requests
+                           with the least modelled work left, each taking all it
+                           needs in that order                                   */
+  int autotune;         /* 1: the first request of each (d, window radius,
+                           precision, strip width, half-octave size class of H
+                           and of W) measures its strip height with bf_autotune's
+                           probes at submit (the submitting thread waits, a few
+                           ms); later requests of the class use the measured
+                           strip count.  0 (default): occupancy model, or a
+                           height bf_autotune recorded for the exact shape       */
+  int graph_rounds;     /* 1: each round's launches on a stream are captured in a
+                           HIP graph and launched as one graph; 0 (default):
+                           launched directly                                     */
+  int reserved[5];
 } bf_server_config;
+
+enum { BF_POLICY_SHARE = 0, BF_POLICY_SHORTEST_FIRST = 1 };
 
 typedef struct bf_request {
   const float* f;       /* DEVICE image, H x W x d floats; pixel (y, x) starts at
@@ -346,6 +364,16 @@ typedef struct bf_request {
   int spatial;          /* as bf_opts.spatial: BF_SPATIAL_*                        */
   int whiten;           /* as bf_opts.whiten: BF_WHITEN_*                          */
   int reserved[1];
+  const float* f_host;  /* HOST image instead of f (f = NULL): H rows of W*d floats,
+                           pixel (y, x) at f_host + (y*pitch + x)*d; copied to the
+                           device by the server after admission (latency includes
+                           the upload).  Pinned memory (hipHostMalloc) keeps the
+                           copy asynchronous; must stay unchanged until the
+                           request ends                                           */
+  float* out_host;      /* HOST H*W*d output: written by a device-to-host copy
+                           before the request is reported done (latency includes
+                           it); out may then be NULL (the device result lives in
+                           the server's arena).  Pinned memory recommended      */
 } bf_request;
 
 enum {

@@ -25,6 +25,8 @@ PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
 BF_SPATIAL_GAUSS, BF_SPATIAL_BOX, BF_SPATIAL_HAT, BF_SPATIAL_BOX3 = 0, 1, 2, 3
 BF_SPATIAL_RUNSUM = 16
 BF_WHITEN_EIG, BF_WHITEN_CHOL, BF_WHITEN_SYM = 0, 1, 2
+BF_POLICY_SHARE, BF_POLICY_SHORTEST_FIRST = 0, 1
+POLICIES = {"share": BF_POLICY_SHARE, "shortest": BF_POLICY_SHORTEST_FIRST}
 WHITEN = {"eig": BF_WHITEN_EIG, "chol": BF_WHITEN_CHOL, "sym": BF_WHITEN_SYM}
 
 
@@ -97,7 +99,10 @@ class bf_server_config(ctypes.Structure):
         ("streams", ctypes.c_int),
         ("depth", ctypes.c_int),
         ("quantum_us", ctypes.c_double),
-        ("reserved", ctypes.c_int * 8),
+        ("policy", ctypes.c_int),
+        ("autotune", ctypes.c_int),
+        ("graph_rounds", ctypes.c_int),
+        ("reserved", ctypes.c_int * 5),
     ]
 
 
@@ -121,6 +126,8 @@ class bf_request(ctypes.Structure):
         ("spatial", ctypes.c_int),
         ("whiten", ctypes.c_int),
         ("reserved", ctypes.c_int * 1),
+        ("f_host", ctypes.c_void_p),
+        ("out_host", ctypes.c_void_p),
     ]
 
 
@@ -468,11 +475,11 @@ def _status_dict(st):
 
 
 def _image_view(f):
-    """(pointer, H, W, d, pitch) of an (H, W, d) float32 CUDA tensor whose
-    rows may be strided (e.g. a crop of a larger image)."""
+    """(pointer, H, W, d, pitch) of an (H, W, d) float32 tensor (CUDA or
+    host) whose rows may be strided (e.g. a crop of a larger image)."""
     import torch
-    if not (f.is_cuda and f.dtype == torch.float32 and f.dim() == 3):
-        raise ValueError("f must be an (H, W, d) float32 CUDA tensor")
+    if not (f.dtype == torch.float32 and f.dim() == 3):
+        raise ValueError("f must be an (H, W, d) float32 tensor")
     H, W, d = f.shape
     s0, s1, s2 = f.stride()
     if not ((s2 == 1 or d == 1) and (s1 == d or W == 1) and s0 % d == 0 and s0 // d >= W):
@@ -487,7 +494,7 @@ class Server:
     or the server closed."""
 
     def __init__(self, arena_bytes=0, max_active=0, max_queued=0, streams=0, depth=0,
-                 quantum_us=0.0):
+                 quantum_us=0.0, policy="share", autotune=False, graph_rounds=False):
         cfg = bf_server_config()
         lib().bf_server_config_init(ctypes.byref(cfg))
         cfg.arena_bytes = int(arena_bytes)
@@ -496,6 +503,9 @@ class Server:
         cfg.streams = int(streams)
         cfg.depth = int(depth)
         cfg.quantum_us = float(quantum_us)
+        cfg.policy = POLICIES[policy] if isinstance(policy, str) else int(policy)
+        cfg.autotune = 1 if autotune else 0
+        cfg.graph_rounds = 1 if graph_rounds else 0
         h = ctypes.c_void_p()
         _check(lib().bf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -505,18 +515,23 @@ class Server:
                arrival=0.0, dedup=False, spatial="gauss", whiten="eig"):
         """Queue the filter of ``f`` (see bf_vec_ex for the arguments);
         ``arrival`` is the server-clock time the request arrives (0: now).
-        Returns (ticket, out)."""
+        ``f`` is a CUDA tensor, or a host (CPU, preferably pinned) tensor that
+        the server uploads itself; ``out`` a CUDA tensor or a host tensor the
+        server downloads into (default: like ``f``).  Returns (ticket, out)."""
         import torch
         ptr, H, W, d, pitch = _image_view(f)
+        host_in = not f.is_cuda
         if out is None:
-            out = torch.empty((H, W, d), dtype=torch.float32, device=f.device)
-        elif not (out.is_cuda and out.dtype == torch.float32 and tuple(out.shape) == (H, W, d)
+            out = torch.empty((H, W, d), dtype=torch.float32, device=f.device,
+                              pin_memory=host_in)
+        elif not (out.dtype == torch.float32 and tuple(out.shape) == (H, W, d)
                   and out.is_contiguous()):
-            raise ValueError("out must be a contiguous (H, W, d) float32 CUDA tensor")
+            raise ValueError("out must be a contiguous (H, W, d) float32 tensor")
         Ch = _host_f64(C, (d, d))
         r = bf_request()
         lib().bf_request_init(ctypes.byref(r))
-        r.f, r.out = ptr, out.data_ptr()
+        r.f, r.f_host = (None, ptr) if host_in else (ptr, None)
+        r.out, r.out_host = (out.data_ptr(), None) if out.is_cuda else (None, out.data_ptr())
         r.H, r.W, r.d, r.pitch = H, W, d, pitch
         r.sigma_s = float(sigma_s)
         r.C = Ch.ctypes.data

@@ -639,8 +639,19 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   if (rc) return rc;
   if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
     return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
+  return autotune_strip_height(f, H, W, W, d, sigma_s, precision, (hipStream_t)stream, tile_h,
+                               ms_per_term);
+}
+
+}  // extern "C"
+
+namespace bfvec {
+
+int autotune_strip_height(const float* f, int H, int W, int pitch, int d, double sigma_s,
+                          int precision, hipStream_t stream, int* tile_h, float* ms_per_term) {
+  int rc = BF_OK;
   const int R = window_radius(sigma_s);
-  if ((rc = check_fused_size(H, W, W, d, R))) return rc;
+  if ((rc = check_fused_size(H, W, pitch, d, R))) return rc;
   int TH0 = 0;   // validates the window against the LDS budget
   if ((rc = choose_strip_height(d, R, precision, H, W, 0, &TH0))) return rc;
   (void)TH0;
@@ -708,7 +719,7 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
     a.taps = dbuf + n_acc + off_taps;
     a.p64 = 0;   // probe phases are small
     fused_geometry(a, H, W, R, precision, ths[i], 0, TW);
-    a.fpitch = W;
+    a.fpitch = pitch;
     a.t0 = 0;
     a.t1 = KP;
     e = launch_fused(d, precision, a, st);   // warm-up
@@ -744,6 +755,10 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   if (ms_per_term) *ms_per_term = best / KP;
   return BF_OK;
 }
+
+}  // namespace bfvec
+
+extern "C" {
 
 int bf_minmax(const float* f, int H, int W, int d, float* lo, float* hi, void* stream) {
   clear_error();

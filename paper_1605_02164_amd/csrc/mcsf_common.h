@@ -201,8 +201,17 @@ int check_acc_size(const FusedArgs& a, int d);
 
 // Process-wide table of measured strip heights, keyed by the current device,
 // d, R, precision, the image shape and the strip width.
+// A measurement also stands for its size class (H and W in half octaves,
+// round(2 log2 n)): shapes of the class without their own entry take its
+// number of strips down the image.
 void record_tuned_height(int d, int R, int prec, int H, int W, int TH, int TW = kTW);
 int tuned_height(int d, int R, int prec, int H, int W, int TW = kTW);
+// 1 if a strip height was measured for this size class
+int tuned_class_known(int d, int R, int prec, int H, int W, int TW = kTW);
+// Measure and record the fastest strip height for an image (bf_autotune's
+// probes; row pitch `pitch` pixels) on stream st.  th / ms may be null.
+int autotune_strip_height(const float* f, int H, int W, int pitch, int d, double sigma_s,
+                          int prec, hipStream_t st, int* th, float* ms_per_term);
 // Strip geometry, staging width and ring sizes of a FusedArgs (TH is raised
 // to 16 when R = 0 so that every term has at least two pipeline steps);
 // vbox = n for variant 3, else 0.

@@ -4,6 +4,7 @@
 #include "mcsf_fused_dev.h"
 
 #include <array>
+#include <cmath>
 #include <map>
 #include <mutex>
 
@@ -191,21 +192,43 @@ namespace {
 std::mutex g_tuned_mu;
 // (device, d, R, precision, H, W, strip width) -> strip height
 std::map<std::array<int, 7>, int> g_tuned;
+// (device, d, R, precision, size class of H, size class of W, strip width)
+// -> strips down the image, from the latest measurement in that class
+std::map<std::array<int, 7>, int> g_tuned_class;
 }  // namespace
+
+int size_class(int n) { return (int)std::floor(2.0 * std::log2((double)std::max(n, 1)) + 0.5); }
 
 void record_tuned_height(int d, int R, int prec, int H, int W, int TH, int TW) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tuned_mu);
   g_tuned[{dev, d, R, prec, H, W, TW}] = TH;
+  g_tuned_class[{dev, d, R, prec, size_class(H), size_class(W), TW}] = (H + TH - 1) / TH;
 }
 
 int tuned_height(int d, int R, int prec, int H, int W, int TW) {
   int dev = 0;
   (void)hipGetDevice(&dev);
+  int nsy = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find({dev, d, R, prec, H, W, TW});
+    if (it != g_tuned.end()) return it->second;
+    auto ic = g_tuned_class.find({dev, d, R, prec, size_class(H), size_class(W), TW});
+    if (ic == g_tuned_class.end()) return 0;
+    nsy = ic->second;
+  }
+  // the class's strip count, on this image's height
+  const int mult = strip_row_multiple(d, R, prec, TW, 0);
+  return ((H + nsy - 1) / nsy + mult - 1) / mult * mult;
+}
+
+int tuned_class_known(int d, int R, int prec, int H, int W, int TW) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tuned_mu);
-  auto it = g_tuned.find({dev, d, R, prec, H, W, TW});
-  return it == g_tuned.end() ? 0 : it->second;
+  return g_tuned_class.count({dev, d, R, prec, size_class(H), size_class(W), TW}) ? 1 : 0;
 }
 
 int choose_strip_height(int d, int R, int prec, int H, int W, int requested, int* TH, int TW,

@@ -120,21 +120,55 @@ struct PlanLaunch {
   std::vector<PlanItem> items;
 };
 
-// One round of continuous batching: every job in `jobs` (admission order)
-// gets the next chunk of its terms, as many as fit in `quantum` of modelled
-// time (at least one, at most what is left), so a small request finishes in
-// its first round while a large one advances a quantum at a time (round-robin
-// processor sharing).  Jobs of one variant share launches of at most
-// `max_batch` jobs each, launches ordered by first appearance.
+// Round policies: processor sharing (every job advances by one quantum of
+// modelled time per round), or shortest remaining work first (the round's
+// budget, one quantum per job, goes to the jobs with the least modelled work
+// left, each taking all it needs, in that order; jobs past the budget wait).
+enum { kPolicyShare = 0, kPolicyShortestFirst = 1 };
+
+// One round of continuous batching.  kPolicyShare: every job in `jobs`
+// (admission order) gets the next chunk of its terms, as many as fit in
+// `quantum` of modelled time (at least one, at most what is left), so a small
+// request finishes in its first round while a large one advances a quantum at
+// a time (round-robin processor sharing).  kPolicyShortestFirst: jobs in
+// order of remaining modelled work (ties: admission order) take all their
+// remaining terms while the round's budget of quantum x (number of jobs)
+// lasts; the job that crosses the budget takes the terms that fit (at least
+// one), the rest get none this round.  Jobs of one variant share launches of
+// at most `max_batch` jobs each, launches ordered by first appearance.
 inline std::vector<PlanLaunch> plan_round(const std::vector<PlanJob>& jobs, double quantum,
-                                          int max_batch) {
+                                          int max_batch, int policy = kPolicyShare) {
   std::vector<PlanLaunch> out;
   std::map<int, size_t> open;  // variant -> index of its last launch in out
-  for (const PlanJob& j : jobs) {
+  std::vector<size_t> order(jobs.size());
+  for (size_t i = 0; i < jobs.size(); ++i) order[i] = i;
+  std::vector<int> take(jobs.size(), 0);
+  if (policy == kPolicyShortestFirst) {
+    auto work = [&](size_t i) {
+      return (double)std::max(0, jobs[i].K - jobs[i].next_t) * jobs[i].cost_per_term;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return work(x) < work(y); });
+    double budget = quantum * (double)jobs.size();
+    for (size_t i : order) {
+      const int left = jobs[i].K - jobs[i].next_t;
+      if (left <= 0 || budget <= 0.0) continue;
+      int n = left;
+      if (jobs[i].cost_per_term > 0.0 && work(i) > budget)
+        n = (int)std::max(1.0, std::floor(budget / jobs[i].cost_per_term));
+      take[i] = n;
+      budget -= n * jobs[i].cost_per_term;
+    }
+  }
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const PlanJob& j = jobs[order[oi]];
     const int left = j.K - j.next_t;
     if (left <= 0) continue;
     int n = left;
-    if (j.cost_per_term > 0.0 && quantum > 0.0) {
+    if (policy == kPolicyShortestFirst) {
+      n = take[order[oi]];
+      if (n <= 0) continue;
+    } else if (j.cost_per_term > 0.0 && quantum > 0.0) {
       const double q = std::ceil(quantum / j.cost_per_term);
       n = (int)std::max(1.0, std::min((double)left, q));
     }

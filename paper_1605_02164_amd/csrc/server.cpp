@@ -78,6 +78,9 @@ struct Req {
   size_t dev_bytes = 0, pin_bytes = 0, dev_off = 0, pin_off = 0;
   bool has_dev = false, has_pin = false, need_minmax = false;
   float* part = nullptr;  // device reduction partials (nparts*17) then result (17)
+  size_t n_part = 0, n_img = 0, n_out = 0;   // floats: partials, uploaded image, device output
+  float* dev_img = nullptr;   // arena copy of a host image (f_host), or null
+  float* dev_out = nullptr;   // arena output when the caller gives only out_host
   float* pin = nullptr;   // pinned: min/max result (17, padded to 32) then term table
   double cost_term = 0.0;
   int next_t = 0;
@@ -91,6 +94,8 @@ struct Req {
 
 struct Round {
   std::vector<hipEvent_t> evs;
+  std::vector<hipGraphExec_t> execs;   // graph rounds: freed when the round has passed
+  std::vector<hipGraph_t> graphs;
 };
 
 }  // namespace
@@ -104,6 +109,8 @@ struct Server {
   Arena dev_arena, pin_arena;
   std::vector<hipStream_t> streams;
   hipStream_t aux = nullptr;
+  hipStream_t tune_stream = nullptr;   // autotune probes at submit (cfg.autotune)
+  std::mutex tune_mu;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -255,7 +262,14 @@ struct Server {
       r->has_dev = r->has_pin = true;
       float* dev = reinterpret_cast<float*>(dev_base + doff);
       r->a.acc = dev;
-      r->part = dev + r->n_acc + r->n_tab;
+      {
+        const size_t b_part = Arena::round_up((r->n_acc + r->n_tab) * sizeof(float), kAlign);
+        const size_t b_img = b_part + Arena::round_up(r->n_part * sizeof(float), kAlign);
+        const size_t b_out = b_img + Arena::round_up(r->n_img * sizeof(float), kAlign);
+        r->part = reinterpret_cast<float*>(dev_base + doff + b_part);
+        r->dev_img = r->n_img ? reinterpret_cast<float*>(dev_base + doff + b_img) : nullptr;
+        r->dev_out = r->n_out ? reinterpret_cast<float*>(dev_base + doff + b_out) : nullptr;
+      }
       r->pin = reinterpret_cast<float*>(pin_base + poff);
       r->ev_done = take_event();
       {
@@ -274,8 +288,17 @@ struct Server {
         r->ev_mm = take_event();
         float* res = r->part + (size_t)r->nparts * kMMFloats;
         hipError_t e = r->ev_mm ? hipSuccess : hipErrorOutOfMemory;
+        if (e == hipSuccess && r->dev_img) {
+          // host image: upload it first (its pitch kept on the host side)
+          const size_t row = (size_t)r->in.W * r->in.d * sizeof(float);
+          e = hipMemcpy2DAsync(r->dev_img, row, r->in.f_host,
+                               (size_t)r->in.pitch * r->in.d * sizeof(float), row, r->in.H,
+                               hipMemcpyHostToDevice, aux);
+          r->a.f = r->dev_img;
+          r->a.fpitch = r->in.W;
+        }
         if (e == hipSuccess)
-          e = launch_minmax(r->in.f, r->in.H, r->in.W, r->in.pitch, r->in.d, r->part, r->nparts,
+          e = launch_minmax(r->a.f, r->in.H, r->in.W, r->a.fpitch, r->in.d, r->part, r->nparts,
                             res, aux);
         if (e == hipSuccess)
           e = hipMemcpyAsync(r->pin, res, kMMFloats * sizeof(float), hipMemcpyDeviceToHost, aux);
@@ -328,7 +351,23 @@ struct Server {
     for (size_t i = 0; i < active.size(); ++i)
       jobs.push_back(PlanJob{(int)i, active[i]->variant, active[i]->next_t, active[i]->K_run,
                              active[i]->cost_term});
-    const std::vector<PlanLaunch> plan = plan_round(jobs, cfg.quantum_us, kMaxBatch);
+    const std::vector<PlanLaunch> plan = plan_round(jobs, cfg.quantum_us, kMaxBatch, cfg.policy);
+    Round rd;
+    std::map<int, bool> capturing;   // graph rounds: streams being captured
+    auto begin_capture = [&](int si) -> hipError_t {
+      if (!cfg.graph_rounds || capturing.count(si)) return hipSuccess;
+      capturing[si] = true;
+      return hipStreamBeginCapture(streams[si], hipStreamCaptureModeRelaxed);
+    };
+    // a device error while streams are being captured: end the captures
+    // (their graphs are discarded) before the error path touches the streams
+    auto abort_captures = [&] {
+      for (auto& kv : capturing) {
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(streams[kv.first], &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      }
+      capturing.clear();
+    };
     std::set<int> used;
     std::vector<Req*> ended;
     std::set<Req*> failed;
@@ -350,14 +389,29 @@ struct Server {
       }
       hipStream_t st = streams[r0->stream];
       const bool injected = fault_at != 0 && ++launch_count == fault_at;
-      hipError_t e = injected ? hipErrorLaunchFailure
-                              : launch_fused_batch(r0->in.d, r0->R, r0->kvar, b, st);
+      hipError_t e = begin_capture(r0->stream);
+      if (e != hipSuccess) {
+        set_fatal(e, "round capture");
+        abort_captures();
+        return true;
+      }
+      e = injected ? hipErrorLaunchFailure : launch_fused_batch(r0->in.d, r0->R, r0->kvar, b, st);
+      if (e != hipSuccess && cfg.graph_rounds && !injected) {
+        set_fatal(e, "batched fused launch under capture");
+        abort_captures();
+        return true;
+      }
       if (e != hipSuccess) {
         // Refused at launch (arguments, resources, or the injected fault):
         // nothing of it runs and the device stays usable, so only this
         // launch's requests fail, once their earlier chunks on the stream
         // have drained (their arena blocks are then free to reuse).
         (void)hipGetLastError();
+        if (cfg.graph_rounds) {   // no stream drain while capturing: the server fails
+          abort_captures();
+          set_fatal(e, "batched fused launch refused in a graph round");
+          return true;
+        }
         failed_msg = std::string(injected ? "injected fault: " : "") +
                      "batched fused launch: " + hipGetErrorString(e);
         const hipError_t q = hipStreamSynchronize(st);
@@ -377,22 +431,50 @@ struct Server {
         if (r->next_t < r->K_run) continue;
         FinalizeArgs fa{};
         fa.acc = r->a.acc;
-        fa.out = r->in.out;
+        fa.out = r->in.out ? r->in.out : r->dev_out;
         for (int m = 0; m < 8; ++m) fa.cen[m] = r->a.cen[m];
         fa.H = r->in.H;
         fa.W = r->in.W;
         fa.Hp = r->a.Hp;
         fa.Wp = r->a.nsx * r->a.TWc;
         e = launch_finalize(r->in.d, fa, st);
-        if (e == hipSuccess) e = hipEventRecord(r->ev_done, st);
+        if (e == hipSuccess && r->in.out_host)
+          e = hipMemcpyAsync(r->in.out_host, fa.out,
+                             (size_t)r->in.H * r->in.W * r->in.d * sizeof(float),
+                             hipMemcpyDeviceToHost, st);
+        // the completion event follows the stream's graph in graph rounds
+        if (e == hipSuccess && !cfg.graph_rounds) e = hipEventRecord(r->ev_done, st);
         if (e != hipSuccess) {
           set_fatal(e, "finalize launch");
+          abort_captures();
           return true;
         }
         ended.push_back(r);
       }
     }
-    Round rd;
+    // graph rounds: end each stream's capture and launch its graph; then the
+    // completion events of the requests that ended on it
+    for (auto& kv : capturing) {
+      hipGraph_t g = nullptr;
+      hipGraphExec_t x = nullptr;
+      hipError_t e = hipStreamEndCapture(streams[kv.first], &g);
+      if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (e == hipSuccess) e = hipGraphLaunch(x, streams[kv.first]);
+      if (g) rd.graphs.push_back(g);
+      if (x) rd.execs.push_back(x);
+      if (e != hipSuccess) {
+        set_fatal(e, "graph round");
+        rounds.push_back(std::move(rd));
+        return true;
+      }
+    }
+    if (cfg.graph_rounds)
+      for (Req* r : ended)
+        if (hipEventRecord(r->ev_done, streams[r->stream]) != hipSuccess) {
+          set_fatal(hipErrorUnknown, "completion event");
+          rounds.push_back(std::move(rd));
+          return true;
+        }
     for (int s : used) {
       hipEvent_t ev = take_event();
       if (!ev || hipEventRecord(ev, streams[s]) != hipSuccess) {
@@ -441,6 +523,8 @@ struct Server {
       }
       if (!done) break;
       for (hipEvent_t& ev : rd.evs) give_event(ev);
+      for (hipGraphExec_t x : rd.execs) (void)hipGraphExecDestroy(x);
+      for (hipGraph_t g : rd.graphs) (void)hipGraphDestroy(g);
       rounds.pop_front();
       progress = true;
     }
@@ -472,8 +556,11 @@ struct Server {
   void fail_all() {
     for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     (void)hipStreamSynchronize(aux);
-    for (Round& rd : rounds)
+    for (Round& rd : rounds) {
       for (hipEvent_t& ev : rd.evs) give_event(ev);
+      for (hipGraphExec_t x : rd.execs) (void)hipGraphExecDestroy(x);
+      for (hipGraph_t g : rd.graphs) (void)hipGraphDestroy(g);
+    }
     rounds.clear();
     std::vector<Req*> all;
     for (auto* v : {&preparing, &active, &finishing}) {
@@ -574,7 +661,9 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   r->in = *q;
   bf_request& in = r->in;
   if (in.pitch == 0) in.pitch = in.W;
-  if (!in.f || !in.out) return fail(BF_EINVAL, "f and out must be non-null device pointers");
+  if ((in.f != nullptr) == (in.f_host != nullptr))
+    return fail(BF_EINVAL, "give exactly one of f (device) and f_host (host)");
+  if (!in.out && !in.out_host) return fail(BF_EINVAL, "give out (device) or out_host (host)");
   if (in.H < 1 || in.W < 1 || in.H > 65536 || in.W > 65536)
     return fail(BF_EINVAL, "H and W must be in [1, 65536]");
   if (in.d < 1 || in.d > 8) return fail(BF_EINVAL, "d must be in [1, 8]");
@@ -595,7 +684,11 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     const size_t obytes = (size_t)in.H * in.W * in.d * sizeof(float);
     const char* a = (const char*)in.f;
     const char* b = (const char*)in.out;
-    if (a < b + obytes && b < a + fbytes) return fail(BF_EINVAL, "out must not overlap f");
+    if (a && b && a < b + obytes && b < a + fbytes) return fail(BF_EINVAL, "out must not overlap f");
+    const char* ah = (const char*)in.f_host;
+    const char* bh = (const char*)in.out_host;
+    if (ah && bh && ah < bh + obytes && bh < ah + fbytes)
+      return fail(BF_EINVAL, "out_host must not overlap f_host");
   }
   std::memcpy(r->Cm, in.C, sizeof(double) * in.d * in.d);
   in.C = r->Cm;
@@ -612,6 +705,14 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     if (e == hipSuccess && cur != s->device) e = hipSetDevice(s->device);
     if (e != hipSuccess) return hip_err(e, "hipSetDevice");
     rc = choose_strip_width(in.d, r->R, r->kvar, in.H, in.W, 0, &TW);
+    // autotune: measure this size class once, on the request's own image
+    if (!rc && s->cfg.autotune && in.f && r->kvar <= 2 && spatial_boxes(in.spatial) == 0 &&
+        !tuned_class_known(in.d, r->R, r->kvar, in.H, in.W, TW)) {
+      std::lock_guard<std::mutex> tk(s->tune_mu);
+      if (!tuned_class_known(in.d, r->R, r->kvar, in.H, in.W, TW))
+        rc = autotune_strip_height(in.f, in.H, in.W, in.pitch, in.d, in.sigma_s, in.precision,
+                                   s->tune_stream, nullptr, nullptr);
+    }
     if (!rc) rc = choose_strip_height(in.d, r->R, r->kvar, in.H, in.W, 0, &TH, TW);
     if (cur != s->device) (void)hipSetDevice(cur);
     if (rc) return rc;
@@ -625,11 +726,16 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   // term table at most K rows of d+1 floats, K weights (merged draws), 2R+1 taps
   // hi and lo term rows, weights, taps (term_table's layout)
   r->n_tab = (size_t)in.K * (2 * in.d + 3) + (size_t)(2 * r->R + 1);
-  r->need_minmax = in.N == 0 || in.center || in.precision == BF_FP16;
+  // a host image is uploaded on the reduction's stream before the kernels
+  r->need_minmax = in.N == 0 || in.center || in.precision == BF_FP16 || in.f_host;
   r->nparts = minmax_parts((size_t)in.H * in.W);
-  const size_t n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMResult : 0;
+  r->n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMResult : 0;
+  r->n_img = in.f_host ? (size_t)in.H * in.W * in.d : 0;
+  r->n_out = in.out ? 0 : (size_t)in.H * in.W * in.d;
   r->dev_bytes = Arena::round_up((r->n_acc + r->n_tab) * sizeof(float), kAlign) +
-                 Arena::round_up(n_part * sizeof(float), kAlign);
+                 Arena::round_up(r->n_part * sizeof(float), kAlign) +
+                 Arena::round_up(r->n_img * sizeof(float), kAlign) +
+                 Arena::round_up(r->n_out * sizeof(float), kAlign);
   r->pin_bytes = (32 + r->n_tab) * sizeof(float);
   r->cost_term = model_term_us(r->a, in.d, r->kvar);
   if (!s->dev_arena.fits_ever(r->dev_bytes))
@@ -676,7 +782,9 @@ int bf_server_create(const bf_server_config* cfg_in, bf_server** out) {
   if (cfg.depth == 0) cfg.depth = 2;
   if (cfg.quantum_us == 0.0) cfg.quantum_us = 2000.0;
   if (cfg.max_active < 1 || cfg.max_queued < 0 || cfg.streams < 1 || cfg.streams > 16 ||
-      cfg.depth < 1 || !(cfg.quantum_us > 0.0) || cfg.arena_bytes < (1u << 20))
+      cfg.depth < 1 || !(cfg.quantum_us > 0.0) || cfg.arena_bytes < (1u << 20) ||
+      (cfg.policy != BF_POLICY_SHARE && cfg.policy != BF_POLICY_SHORTEST_FIRST) ||
+      (cfg.autotune != 0 && cfg.autotune != 1) || (cfg.graph_rounds != 0 && cfg.graph_rounds != 1))
     return fail(BF_EINVAL, "bad server configuration");
   auto s = std::make_unique<bf_server>();
   s->cfg = cfg;
@@ -702,7 +810,9 @@ int bf_server_create(const bf_server_config* cfg_in, bf_server** out) {
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) (i < cfg.streams ? s->streams.push_back(st) : (void)(s->aux = st));
   }
+  if (e == hipSuccess && cfg.autotune) e = hipStreamCreateWithFlags(&s->tune_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
+    if (s->aux) (void)hipStreamDestroy(s->aux);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     (void)hipFree(s->dev_base);
     (void)hipHostFree(s->pin_base);
@@ -819,6 +929,10 @@ int bf_server_destroy(bf_server* s) {
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->aux) (void)hipStreamDestroy(s->aux);
+  if (s->tune_stream) {
+    (void)hipStreamSynchronize(s->tune_stream);
+    (void)hipStreamDestroy(s->tune_stream);
+  }
   (void)hipFree(s->dev_base);
   (void)hipHostFree(s->pin_base);
   delete s;

@@ -123,6 +123,61 @@ static std::string planner_random(unsigned seed) {
   return "";
 }
 
+// Shortest-remaining-work-first rounds: chunks stay contiguous and every job
+// finishes; each round's modelled work stays within quantum x (active jobs)
+// plus one term; the job with the least remaining work is served first and
+// runs to completion whenever the budget allows; a served job with less
+// remaining work than an unserved one never exists.
+static std::string planner_shortest_first(unsigned seed) {
+  std::mt19937_64 rng(seed);
+  for (int trial = 0; trial < 200; ++trial) {
+    const int nj = 1 + rng() % 40, max_batch = 1 + rng() % 16;
+    const double quantum = 50.0 + (rng() % 5000);
+    std::vector<PlanJob> jobs;
+    for (int j = 0; j < nj; ++j)
+      jobs.push_back(PlanJob{j, (int)(rng() % 5), 0, 1 + (int)(rng() % 300),
+                             0.5 + (rng() % 2000) / 10.0});
+    int rounds = 0;
+    for (;;) {
+      std::vector<PlanJob> act;
+      for (auto& j : jobs)
+        if (j.next_t < j.K) act.push_back(j);
+      if (act.empty()) break;
+      if (++rounds > 100000) return "no termination";
+      const auto plan = plan_round(act, quantum, max_batch, kPolicyShortestFirst);
+      if (plan.empty()) return "round with active jobs but no work";
+      std::vector<int> seen(nj, 0);
+      double work = 0.0, max_term = 0.0;
+      for (auto& j : act) max_term = std::max(max_term, j.cost_per_term);
+      double least = 1e300;
+      for (auto& j : act) least = std::min(least, (j.K - j.next_t) * j.cost_per_term);
+      double served_max = -1.0, unserved_min = 1e300;
+      std::vector<double> rem(nj, 0.0);
+      for (auto& j : act) rem[j.job] = (j.K - j.next_t) * j.cost_per_term;
+      for (const auto& L : plan) {
+        if (L.items.empty() || (int)L.items.size() > max_batch) return "bad launch size";
+        for (const auto& it : L.items) {
+          PlanJob& j = jobs[it.job];
+          if (j.variant != L.variant) return "job in another variant's launch";
+          if (seen[it.job]++) return "job twice in one round";
+          if (it.t0 != j.next_t) return "chunk not contiguous";
+          if (it.t1 <= it.t0 || it.t1 > j.K) return "empty or overlong chunk";
+          work += (it.t1 - it.t0) * j.cost_per_term;
+          if (rem[it.job] == least && least <= quantum * act.size() && it.t1 != j.K)
+            return "shortest job not finished within the budget";
+          served_max = std::max(served_max, rem[it.job]);
+          j.next_t = it.t1;
+        }
+      }
+      for (auto& j : act)
+        if (!seen[j.job]) unserved_min = std::min(unserved_min, rem[j.job]);
+      if (work > quantum * act.size() + max_term + 1e-6) return "round above its budget";
+      if (unserved_min < served_max) return "a shorter job waited while a longer one ran";
+    }
+  }
+  return "";
+}
+
 static std::string percentiles() {
   std::vector<double> v;
   for (int i = 100; i >= 1; --i) v.push_back(i);
@@ -138,6 +193,7 @@ int main() {
   report("arena_random_seed1", arena_random(1));
   report("arena_random_seed2", arena_random(2));
   report("planner_random", planner_random(3));
+  report("planner_shortest_first", planner_shortest_first(4));
   report("percentiles", percentiles());
   return failures ? 1 : 0;
 }

@@ -350,3 +350,41 @@ def test_injected_launch_fault_fails_only_its_requests(monkeypatch):
         torch.cuda.synchronize()
         assert torch.equal(outs[i], ref), i
     assert stats["failed"] == 1 and stats["completed"] == 4
+
+
+@pytest.mark.parametrize("policy,graph_rounds,autotune,host_io", [
+    ("shortest", False, False, False),
+    ("share", True, False, False),
+    ("share", False, True, False),
+    ("shortest", True, True, True),
+])
+def test_server_modes_match_standalone_bitwise(pools, policy, graph_rounds, autotune, host_io):
+    # shortest-remaining-work-first rounds, graph-captured rounds, strip
+    # heights measured per size class at submit, and host-resident images and
+    # results (uploaded and downloaded by the server): none changes a result
+    # bit (chunking and batching only split Algorithm 1's term loop; the strip
+    # height changes no bit)
+    print(f"case server policy={policy} graph_rounds={graph_rounds} autotune={autotune} "
+          f"host_io={host_io}", flush=True)
+    alone = [_alone(_crop(pools, spec), spec) for spec in MIX]
+    hosts = (pools[0].cpu().pin_memory(), pools[1].cpu().pin_memory()) if host_io else None
+    with P.Server(arena_bytes=1 << 30, streams=3, depth=2, quantum_us=20.0, policy=policy,
+                  graph_rounds=graph_rounds, autotune=autotune) as srv:
+        tickets = []
+        for spec in MIX:
+            fc = _crop(hosts if host_io else pools, spec)
+            _, _, _, _, _, s, K, N, prec, center, cov = spec
+            t, out = srv.submit(fc, s, _cov(cov, fc.shape[2]), K, seed=1000 + K, N=N,
+                                precision=prec, center=center)
+            assert out.is_cuda != host_io
+            tickets.append((t, out))
+        srv.drain(timeout=60.0)
+        stats = srv.stats()
+        for spec, (t, out), (ref, n_ref) in zip(MIX, tickets, alone):
+            st = srv.poll(t)
+            assert st["state"] == "done", (spec, st)
+            assert st["N_used"] == n_ref, spec
+            got = out if not host_io else out.to(DEV)
+            assert torch.equal(got, ref), (spec, float((got - ref).abs().max()))
+        assert stats["completed"] == len(MIX) and stats["failed"] == 0
+        assert stats["rounds"] >= 4

@@ -40,4 +40,4 @@ def test_scheduler_under_sanitizers(tmp_path):
     out = _build_run(tmp_path, "sched_check", [f"{ROOT}/tests/sched_check.cpp"])
     assert out.returncode == 0, out.stdout + out.stderr
     assert "runtime error" not in out.stderr and "ERROR: AddressSanitizer" not in out.stderr
-    assert sum(l.startswith("PASS") for l in out.stdout.splitlines()) == 4, out.stdout
+    assert sum(l.startswith("PASS") for l in out.stdout.splitlines()) == 5, out.stdout

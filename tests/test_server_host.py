@@ -60,4 +60,4 @@ def test_scheduler_arena_and_planner(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     lines = out.stdout.split("\n")
     assert out.returncode == 0, out.stdout
-    assert sum(l.startswith("PASS") for l in lines) == 4, out.stdout
+    assert sum(l.startswith("PASS") for l in lines) == 5, out.stdout
