@@ -604,6 +604,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="precision of the headline value; the other modes are reported beside it")
     ap.add_argument("--only", action="store_true", help="time only --precision")
+    ap.add_argument("--modes", help="comma-separated modes to time instead of the default set "
+                                    "(fp32, fp16, bf16, *_valu, *_dedup, fp32_box3, fp32_box3sl); "
+                                    "the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-plan", action="store_true",
@@ -686,29 +689,32 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
-    def step(prec, dst, dedup, spatial="gauss", valu=False):
+    def step(prec, dst, dedup, spatial="gauss", valu=False, tile_w=0):
         _, o = P.bf_vec_ex(fg, sigma_s, C, K, seed, out=dst, precision=prec,
                            stream=stream, time_kernel=True, return_opts=True, dedup=dedup,
-                           spatial=spatial, valu_only=valu)
+                           spatial=spatial, valu_only=valu, tile_w=tile_w)
         return o.N_used, o.kernel_ms, o.K_used, o.tile_h_used, o.tile_w_used, o.mfma_used
 
     tuned = {}
 
     def run(mode, dst):
         prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
-        spatial = "box3" if mode.endswith("_box3") else "gauss"
-        valu = mode.endswith("_valu")
+        tile_w = 16 if mode.endswith("_w16") else 0
+        base = mode[:-4] if tile_w else mode
+        spatial = ("box3" if base.endswith("_box3") else
+                   "box3+runsum" if base.endswith("_box3sl") else "gauss")
+        valu = base.endswith("_valu")
         if not args.no_autotune and prec not in tuned:
             # one-off, untimed: measured strip height for this shape
             tuned[prec] = P.bf_autotune(fg, sigma_s, precision=prec, stream=stream)
             log(f"{prec}: autotuned strip height {tuned[prec][0]}")
         for _ in range(args.warmup):
-            step(prec, dst, dedup, spatial, valu)
+            step(prec, dst, dedup, spatial, valu, tile_w)
         torch.cuda.synchronize()
         kms = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            N, ms, K_used, tile_h, tile_w, mf = step(prec, dst, dedup, spatial, valu)
+            N, ms, K_used, tile_h, tile_w, mf = step(prec, dst, dedup, spatial, valu, tile_w)
             kms.append(ms)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -731,13 +737,17 @@ def main():
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
         [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + \
-        ["fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3"]
+        ["fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3", "fp32_box3sl"]
+    if args.modes:
+        precs = args.modes.split(",")
+        args.precision = precs[0].split("_")[0]
     results, outs = {}, {}
     for prec in precs:
         outs[prec] = torch.empty_like(fg)
         log(f"timing {prec}: {args.warmup} warmup + {args.steps} steps")
         results[prec] = run(prec, outs[prec])
-    main_rec = results[args.precision]
+    main_mode = precs[0]
+    main_rec = results[main_mode]
     N = main_rec["N"]
     # deviation of the 16-bit modes from the FP32 output (fraction of each
     # channel's range), from the same run's outputs
@@ -759,11 +769,11 @@ def main():
         ref = torch.empty_like(fg)
         ms = _timed(lambda: P.bf_direct(fg, sigma_s, C, out=ref), 2)
         span = (fg.reshape(-1, d).amax(0) - fg.reshape(-1, d).amin(0)).clamp_min(1e-30)
-        dev = (outs[args.precision] - ref).abs().reshape(-1, d) / span
+        dev = (outs[main_mode] - ref).abs().reshape(-1, d) / span
         direct = {"ms": ms, "mpix_s": H * W / ms / 1e3,
                   "approx_flops_per_pixel": (2 * R + 1) ** 2 * (2 * d + d * d * 2 + 2 * d + 4),
                   "mcsf_vs_direct": {"max_dev": float(dev.max()), "mean_dev": float(dev.mean()),
-                                     "mse_db_255": mse_db(outs[args.precision] * 255.0,
+                                     "mse_db_255": mse_db(outs[main_mode] * 255.0,
                                                           ref * 255.0)}}
         log(f"direct filter: {ms:.1f} ms, {direct['mpix_s']:.1f} Mpix/s; MCSF deviation from it: "
             f"mean {direct['mcsf_vs_direct']['mean_dev']:.3g}, max "

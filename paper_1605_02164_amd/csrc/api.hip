@@ -310,7 +310,7 @@ int plan_fused(int H, int W, int d, double sigma_s, const bf_opts* o, int* TH, i
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
   int rc = check_fused_size(H, W, W, d, R);
   if (rc) return rc;
-  const int v = kernel_variant(o->precision, o->spatial);
+  const int v = select_variant(d, R, o->precision, o->spatial, W, o->tile_w, o->valu_only);
   if ((rc = choose_strip_width(d, R, v, H, W, o->tile_w, TW))) return rc;
   if ((rc = choose_strip_height(d, R, v, H, W, o->tile_h, TH, *TW, o->valu_only))) return rc;
   FusedArgs g{};   // the padded accumulators of this geometry must fit 32-bit offsets
@@ -328,7 +328,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
               const float* hi, int TH, int TW, float* work = nullptr, size_t work_floats = 0) {
   hipStream_t st = (hipStream_t)o->stream;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
-  const int variant = kernel_variant(o->precision, o->spatial);
+  const int variant = select_variant(d, R, o->precision, o->spatial, W, o->tile_w, o->valu_only);
   size_t off_w = 0, off_taps = 0;
   const std::vector<float> hbuf =
       term_table(d, K, w, weights, sigma_s, &off_w, &off_taps, spatial_boxes(o->spatial));

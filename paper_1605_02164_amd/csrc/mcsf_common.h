@@ -88,10 +88,16 @@ inline int spatial_boxes(int spatial) { return spatial & 3; }
 inline bool spatial_runsum(int spatial) { return (spatial & 16) != 0; }
 // Kernel variants: 0 FP32, 1 FP16 storage, 2 BF16 storage (FIR passes with
 // any spatial taps), 3 FP32 with the running-sum vertical pass of the n-fold
-// box filters (requested by the flag).
+// box filters (requested by the flag), 4 FP32 three-box filter with sliding
+// box sums in the vertical pass and the horizontal pass on the matrix cores
+// (32-column strips; the flag with three boxes where such an instance exists).
 inline int kernel_variant(int precision, int spatial) {
   return precision == 0 && spatial_runsum(spatial) && spatial_boxes(spatial) > 0 ? 3 : precision;
 }
+// kernel_variant, with variant 4 in place of 3 for three boxes at d = 3, a
+// compile-time radius (multiple of 3), W >= 32, a strip width that is not
+// forced to 16 and matrix-core passes allowed.
+int select_variant(int d, int R, int precision, int spatial, int W, int tile_w, int valu);
 // BF_OK, or BF_EINVAL / BF_EUNSUPPORTED with the message set.
 int check_spatial(int spatial, int precision);
 

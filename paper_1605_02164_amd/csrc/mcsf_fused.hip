@@ -38,6 +38,15 @@ __global__ __launch_bounds__(256) void mcsf_finalize(FinalizeArgs a) {
 
 size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
   const int NP = d + 1, NC = 2 * NP;
+  if (prec == 4) {   // taps | two staging buffers | ring | first-stage sums | cos/sin
+    const int w = 2 * (R / 3) + 1;
+    const int taps_al = ((2 * R + 1 + 3) / 4 * 4 + 7) / 8 * 8;
+    const size_t fl = (size_t)taps_al + 2 * (size_t)kB * NC * stage_width_mf32(R) +
+                      (size_t)((w + 16 + 7) / 8 * 8) * NC * kTWMax +
+                      (size_t)((2 * w + 8 + 7) / 8 * 8) * NC * kTWMax +
+                      (size_t)((R + 24 + 7) / 8 * 8) * 2 * kTWMax;
+    return fl * sizeof(float);
+  }
   const bool lp = prec == 1 || prec == 2, vb = prec == 3;
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
@@ -128,16 +137,51 @@ static bool specialised_radius(int R) {
   }
 }
 
+// variant 4: one 8-wave workgroup per CU by its LDS (checked against the
+// instance's registers)
+template <int RC>
+static int blocks_per_cu_sl() {
+  hipFuncAttributes at{};
+  int vgpr = 256;
+  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(
+                                    mcsf_fused<3, RC, 4, false, kTWMax, true>)) == hipSuccess &&
+      at.numRegs > 0)
+    vgpr = at.numRegs;
+  const int by_vgpr = std::min(8, 512 / ((vgpr + 7) / 8 * 8)) / 2;
+  const int by_lds = (int)((160 * 1024) / fused_lds_bytes(3, RC, 4, kTWMax, 1));
+  return std::max(1, std::min(by_vgpr, by_lds));
+}
+
 int fused_blocks_per_cu(int d, int R, int prec, int TW, int valu) {
   switch (prec) {
     case 0: return bpc_p<0>(d, R, TW, valu);
     case 1: return bpc_p<1>(d, R, TW, valu);
     case 2: return bpc_p<2>(d, R, TW, valu);
+    case 4:
+      switch (R) {
+        case 6: return blocks_per_cu_sl<6>();
+        case 9: return blocks_per_cu_sl<9>();
+        case 12: return blocks_per_cu_sl<12>();
+        case 15: return blocks_per_cu_sl<15>();
+        case 18: return blocks_per_cu_sl<18>();
+        case 21: return blocks_per_cu_sl<21>();
+        case 24: return blocks_per_cu_sl<24>();
+        default: return blocks_per_cu_sl<30>();
+      }
     default: return bpc_p<3>(d, R, TW, valu);
   }
 }
 
+int select_variant(int d, int R, int precision, int spatial, int W, int tile_w, int valu) {
+  const int v = kernel_variant(precision, spatial);
+  if (v == 3 && spatial_boxes(spatial) == 3 && d == 3 && specialised_radius(R) && R % 3 == 0 &&
+      W >= kTWMax && tile_w != kTW && !valu)
+    return 4;
+  return v;
+}
+
 int fused_uses_mf(int d, int R, int prec, int TW, int valu) {
+  if (prec == 4) return 1;   // its horizontal pass
   if (valu || !specialised_radius(R) || (d != 3 && d != 6) || prec > 2) return 0;
   const bool inst = TW == kTWMax ? d == 3 : (prec == 1 || prec == 2);
   return inst && use_mf(TW, prec, R) ? 1 : 0;
@@ -148,6 +192,10 @@ int strip_row_multiple(int d, int R, int prec, int TW, int valu) {
 }
 
 int choose_strip_width(int d, int R, int prec, int H, int W, int requested, int* TW) {
+  if (prec == 4) {   // select_variant guarantees the instance
+    *TW = kTWMax;
+    return BF_OK;
+  }
   const bool wide_ok = d == 3 && prec <= 2 && W >= kTWMax && specialised_radius(R) &&
                        fused_lds_bytes(d, R, prec, kTWMax) <= 160 * 1024;
   if (requested == kTWMax && !wide_ok)
@@ -286,6 +334,7 @@ hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st) {
     case 1: return launch_p<1>(d, a, a.R, st);
     case 2: return launch_p<2>(d, a, a.R, st);
     case 3: return launch_p<3>(d, a, a.R, st);
+    case 4: return d == 3 ? launch_sl_r(a, a.R, st) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

@@ -368,9 +368,12 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // strips).
 template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
-  static_assert(PREC >= 0 && PREC <= 3, "kernel variant");
+  static_assert(PREC >= 0 && PREC <= 4, "kernel variant");
   static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
-  static_assert(!MF || (RC >= 0 && (TW == 32 ? D == 3 && PREC <= 2 : PREC == 1 || PREC == 2)),
+  static_assert(PREC != 4 || (TW == 32 && MF && D == 3 && RC >= 0 && RC % 3 == 0),
+                "sliding three-box vertical pass: 32-column matrix-core instances");
+  static_assert(!MF || (RC >= 0 && (TW == 32 ? D == 3 && (PREC <= 2 || PREC == 4)
+                                             : PREC == 1 || PREC == 2)),
                 "matrix-core passes");
   using G = Geo<D, TW>;
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
@@ -388,6 +391,14 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
   constexpr bool VB = PREC == 3;                 // running-sum vertical pass
+  // Variant 4 (FP32, three boxes, 32-column strips): horizontal pass on the
+  // matrix cores over the box taps; vertical pass as three cascaded sliding
+  // box sums, O(1) operations per output whatever the radius (below).
+  constexpr bool SLV = PREC == 4;
+  constexpr int SLW = SLV ? 2 * (RC / 3) + 1 : 1;   // box width 2r + 1 (R = 3r)
+  constexpr int SL_RS = (SLW + 16 + 7) / 8 * 8;      // ring: rows i - w .. newest step
+  constexpr int SL_CRS = (RC + 24 + 7) / 8 * 8;      // cos/sin: rows i - R .. newest step
+  constexpr int SL_S1R = (2 * SLW + 8 + 7) / 8 * 8;  // first-stage sums: rows i - 2w .. i
   constexpr int NTAPR = (RC >= 0 && !LP) ? RC + 1 : 1;    // taps 0..R (symmetric)
   constexpr int NTAPP = (RC >= 0 && LP) ? RC + 1 : 1;   // packed tap pairs
 
@@ -401,7 +412,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
   const int tapp_al = (R + 1 + 3) / 4 * 4;
-  const int RS = (a.RSB + (PIPE ? 2 : 0)) * B, CRS = a.CRB * B;
+  const int RS = SLV ? SL_RS : (a.RSB + (PIPE ? 2 : 0)) * B, CRS = SLV ? SL_CRS : a.CRB * B;
   // LDS carve-up: FP32 taps | packed tap pairs (16-bit modes) | staging (two
   // buffers with PIPE) | ring | cos/sin ring.  16-bit modes store the ring as
   // row pairs.
@@ -411,10 +422,11 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   unsigned* s_to = s_te + (LP ? tapp_al : 0);
   float* s_stage = reinterpret_cast<float*>(s_to + (LP ? tapp_al : 0));
   unsigned short* s_stage16 = reinterpret_cast<unsigned short*>(s_stage);
-  float* s_ring = s_stage + stage_floats * (PIPE ? 2 : 1);
+  float* s_ring = s_stage + stage_floats * (PIPE || SLV ? 2 : 1);
   unsigned* s_ring32 = reinterpret_cast<unsigned*>(s_ring);
   unsigned short* s_ring16 = reinterpret_cast<unsigned short*>(s_ring);
-  float* s_cs = s_ring + (LP ? RS / 2 : RS) * RST;
+  float* s_s1 = s_ring + (LP ? RS / 2 : RS) * RST;   // variant 4: first-stage sums [row][ch][x]
+  float* s_cs = s_s1 + (SLV ? SL_S1R * NC * TW : 0);
   float* s_vr = s_cs + CRS * CST;   // variant 3: 16-row ring of vertical-pass outputs
 
   const int tid = threadIdx.x;
@@ -423,8 +435,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const int Wd = a.W, Hd = a.H;
 
   for (int i = tid; i < taps_al; i += NT) s_taps[i] = i < 2 * R + 1 ? a.taps[i] : 0.0f;
-  for (int i = tid; i < (LP ? RS / 2 : RS) * RST; i += NT) s_ring[i] = 0.0f;
-  for (int i = tid; i < (PIPE ? 2 : 1) * B * NC * (SW - MW); i += NT) {   // staging padding columns
+  for (int i = tid; i < (LP ? RS / 2 : RS) * RST + (SLV ? SL_S1R * NC * TW : 0); i += NT)
+    s_ring[i] = 0.0f;   // ring, and the first-stage sums of variant 4 (read before written)
+  for (int i = tid; i < (PIPE || SLV ? 2 : 1) * B * NC * (SW - MW); i += NT) {   // staging padding columns
     const int row = i / (SW - MW), col = MW + i % (SW - MW);   // rows of both buffers (PIPE)
     if constexpr (LP) s_stage16[row * SW + col] = 0;
     else s_stage[row * SW + col] = 0.0f;
@@ -599,19 +612,24 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       }
     }
   };
+  // The accumulator loads are issued by every lane in every step, whether
+  // or not the value is used (t = 0, t past the range, s < lag, the upper
+  // half of a matrix-core wave): the addresses are always rows of this strip
+  // (s < lag reads its first output step; upper lanes repeat the lower
+  // lanes' rows).  Without a branch around them the compiler knows how many
+  // memory operations follow each prefetch, and the modulation's wait for
+  // its f values no longer also waits for the accumulators just requested.
   auto load_acc = [&](float (&dst)[NACC], int t, int s) {
-    if (t > 0 && t < t1 && s >= lag) {
-      if constexpr (MFV) {
-        if (mf_on) {
-          const unsigned o = acc_lane + (unsigned)((s - lag) * B) * Wp;
+    (void)t;
+    const int so = max(s - lag, 0);
+    if constexpr (MFV) {
+      const unsigned o = acc_lane + (unsigned)(so * B) * Wp;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
-        }
-      } else {
-        const unsigned o = acc_lane + (unsigned)((s - lag) * B + p2_g * 4) * Wp;
-        dst[0] = buf_load1(acc_rsrc, 4u * o);
-        dst[1] = buf_load1(acc_rsrc, 4u * (o + Wp));
-      }
+      for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
+    } else {
+      const unsigned o = acc_lane + (unsigned)(so * B + p2_g * 4) * Wp;
+      dst[0] = buf_load1(acc_rsrc, 4u * o);
+      dst[1] = buf_load1(acc_rsrc, 4u * (o + Wp));
     }
   };
 
@@ -725,13 +743,12 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // row; rl / cl: ring / cos-sin rows of its first window row; ap: this
   // lane's accumulators of the pair (prefetched; unused for t = 0).
   auto load_accp = [&](float (&dst)[4], int t, int pr) {
-    if (t > 0 && t < t1) {
-      const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
-      const unsigned o =
-          (unsigned)(m * a.Hp + y0 + pr + 4 * (ln >> 4)) * Wp + x0 + 16 * nb + (ln & 15);
+    (void)t;   // loaded whatever t is, like load_acc
+    const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+    const unsigned o =
+        (unsigned)(m * a.Hp + y0 + pr + 4 * (ln >> 4)) * Wp + x0 + 16 * nb + (ln & 15);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
-    }
+    for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
   };
   auto vpair = [&](int t, int pr, const float (&ap)[4], int rl, int cl) {
     const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
@@ -1020,11 +1037,19 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         const f32x4_t hd = hmf(stg_h);
         vpair(tv, (sv - 1 - lag) * B, ap, rl, cl);
         hmf_store(hd, rh);
-        int ps = sv + 1, pt = tv;      // the next pair's accumulators
-        if (ps >= steps) { ps = lag; ++pt; }
-        load_accp(ap, pt, (ps - lag) * B);
       } else {
         hpass_step(stg_h, rh);
+      }
+      {
+        // the accumulators of the next pair, (re)loaded in every iteration
+        // (a load on one side of the branch only made the compiler wait for
+        // it at the merge): after a pair, the one starting at step sv + 1
+        // (the next term's first, at output row 0, past the term's end);
+        // otherwise the one starting at step max(sv, lag)
+        int pn;
+        if (g >= 1 && sv > lag && ((sv - lag) & 1)) pn = sv + 1 >= steps ? 0 : (sv + 1 - lag) * B;
+        else pn = g >= 1 && sv > lag ? (sv - lag) * B : 0;
+        load_accp(ap, 0, pn);
       }
       if (g >= 1 && ++sv == steps) {
         sv = 0;
@@ -1053,6 +1078,154 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     }
     // the last pair (its second step is the launch's last)
     vpair(tv, (sv - 1 - lag) * B, ap, rl, cl);
+    return;
+  }
+  if constexpr (SLV) {
+    // Three-box vertical pass as cascaded sliding sums, with the same one-
+    // barrier pipeline as PIPE: iteration g runs the horizontal pass of global
+    // step g (matrix cores), the vertical pass of step g - 1 and the
+    // modulation of step g + 1.  With u the horizontal-pass rows of a term
+    // (input row i of the strip's haloed rows) and w = 2r + 1:
+    //   S1(i) = S1(i-1) + u(i) - u(i-w)         (box over u)
+    //   S2(i) = S2(i-1) + S1(i) - S1(i-w)       (box over S1)
+    //   L2(i) = L2(i-1) + S1(i-w) - S1(i-2w)    (= S2(i-w))
+    //   S3(i) = S3(i-1) + S2(i) - L2(i)         (box over S2)
+    // so S3(i) is the three-box filter of u over rows i - 2R .. i, the
+    // vertical pass of output row o = i - 2R (rows before the term's first
+    // count as zero).  The sums are FP64 registers of one lane per (column,
+    // channel) (waves 0..NP-1), reset at each term's first row; S1 is stored
+    // rounded to FP32 and S2, L2 add and subtract those same stored values,
+    // so the telescoping sums stay exact and nothing drifts down the strip.
+    // The cos and sin channels of a pair sit in lanes l and l + 32 and
+    // exchange halves for the demodulation; each lane then updates 4 rows.
+    float* const stg0 = s_stage;
+    float* const stg1 = s_stage + stage_floats;
+    const bool sl_on = tid < 64 * NP;
+    const int sl_x = tid & 31, sl_k = (tid >> 5) & 1, sl_m = tid >> 6;
+    const int sl_col = (2 * sl_m + sl_k) * TW + sl_x;     // [ch][x] within a ring row
+    double S1 = 0.0, S2 = 0.0, L2 = 0.0, S3 = 0.0;
+    float sa[4] = {0.0f, 0.0f, 0.0f, 0.0f}, sb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // accumulator rows of this lane in v-step s: o = 8s + (k ? 4 : 0) + v - 2R
+    // (issued by every lane whatever t is, from rows clamped into the strip,
+    // for the reason given at load_acc)
+    auto load_accs = [&](float (&dst)[4], int t, int sv2) {
+      (void)t;
+      const int mc = min(sl_m, NP - 1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = min(max(B * sv2 + 4 * sl_k + v - 2 * R, 0), a.TH - 1);
+        dst[v] = buf_load1(acc_rsrc, 4u * ((unsigned)(mc * a.Hp + y0 + o) * Wp + x0 + sl_x));
+      }
+    };
+    auto slide = [&](int t, int sv, const float (&av)[4], int rv, int sr, int cv) {
+      if (!sl_on) return;
+      if (sv == 0) S1 = S2 = L2 = S3 = 0.0;
+      // every LDS read of the step first (rows of earlier steps, or of this
+      // step's first-stage sums when w < 8), then the four recurrences
+      float un[B], uo[B], fb[B], cs[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int i = B * sv + j;
+        un[j] = s_ring[(rv + j) * RST + sl_col];
+        int ro = rv + j - SLW;
+        ro = ro < 0 ? ro + RS : ro;
+        uo[j] = i >= SLW ? s_ring[ro * RST + sl_col] : 0.0f;
+        int rb = sr + j - 2 * SLW;
+        rb = rb < 0 ? rb + SL_S1R : rb;
+        rb = rb < 0 ? rb + SL_S1R : rb;
+        fb[j] = i >= 2 * SLW ? s_s1[rb * (NC * TW) + sl_col] : 0.0f;
+        int rc = cv + j - R;   // cos/sin row of output pixel o = i - 2R: input row i - R
+        rc = rc < 0 ? rc + CRS : rc;
+        cs[j] = s_cs[rc * CST + sl_k * TW + sl_x];
+      }
+      float fa[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        if (j < SLW) {   // row i - w lies in an earlier step
+          int ra = sr + j - SLW;
+          ra = ra < 0 ? ra + SL_S1R : ra;
+          fa[j] = B * sv + j >= SLW ? s_s1[ra * (NC * TW) + sl_col] : 0.0f;
+        }
+      }
+      float s1f[B], q[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        S1 += (double)un[j] - (double)uo[j];
+        s1f[j] = (float)S1;
+        if (j >= SLW) fa[j] = s1f[j - SLW];   // w < 8: this step's own sums
+        S2 += (double)s1f[j] - (double)fa[j];
+        L2 += (double)fa[j] - (double)fb[j];
+        S3 += S2 - L2;
+        q[j] = cs[j] * (float)S3;
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) s_s1[(sr + j) * (NC * TW) + sl_col] = s1f[j];
+      // lanes 0-31 take rows 0-3, lanes 32-63 rows 4-7 (cos + sin of a pair)
+      float r4[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        unsigned lo = __builtin_bit_cast(unsigned, q[v]), hi = __builtin_bit_cast(unsigned, q[v + 4]);
+        swap_halves(lo, hi);
+        r4[v] = __builtin_bit_cast(float, lo) + __builtin_bit_cast(float, hi);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = B * sv + 4 * sl_k + v - 2 * R;
+        if (o >= 0 && o < a.TH)
+          buf_store1(acc_rsrc, 4u * ((unsigned)(sl_m * a.Hp + y0 + o) * Wp + x0 + sl_x),
+                     fmaf(tw, r4[v], t > 0 ? av[v] : 0.0f));
+      }
+    };
+    load_accs(sa, t0, 0);
+    load_accs(sb, steps > 1 ? t0 : t0 + 1, steps > 1 ? 1 : 0);
+    modulate(t0, 0, fA, stg0, 0);
+    load_f(fA, 2 % steps);
+    __syncthreads();
+    int tv = t0, sv = 0, tm = t0, sm = 1;
+    if (sm == steps) { sm = 0; ++tm; }
+    if (tm < t1) load_wr(tm);
+    // rows of step g (horizontal pass), of step g - 1 (vertical pass: ring,
+    // first-stage sums, cos/sin) and of step g + 1 (modulation: cos/sin)
+    int rh = 0, rv = RS - B, sr = SL_S1R - B, cv = CRS - B, cm = B;
+    auto iter = [&](int g, const float* stg_h, float* stg_m, float (&fm)[MI][D],
+                    float (&av)[4]) {
+      hpass_step(stg_h, rh);
+      if (g >= 1) {
+        slide(tv, sv, av, rv, sr, cv);
+        int s2 = sv + 2, t2 = tv;       // accumulators of step g + 1
+        if (s2 >= steps) { s2 -= steps; ++t2; }
+        if (s2 >= steps) { s2 -= steps; ++t2; }
+        load_accs(av, t2, s2);
+        if (++sv == steps) {
+          sv = 0;
+          if (++tv < t1) load_tw(tv);
+        }
+      }
+      if (g + 1 < total) {
+        modulate(tm, sm, fm, stg_m, cm);
+        int s3 = sm + 2;
+        if (s3 >= steps) s3 -= steps;
+        if (s3 >= steps) s3 -= steps;
+        load_f(fm, s3);
+        if (++sm == steps) {
+          sm = 0;
+          if (++tm < t1) load_wr(tm);
+        }
+      }
+      __syncthreads();
+      rh = wrap(rh + B, RS);
+      rv = wrap(rv + B, RS);
+      sr = wrap(sr + B, SL_S1R);
+      cv = wrap(cv + B, CRS);
+      cm = wrap(cm + B, CRS);
+    };
+    // v-step g - 1 uses the accumulators of its parity: sa even, sb odd
+    for (int g = 0; g < total; g += 2) {
+      iter(g, stg0, stg1, fB, sb);
+      if (g + 1 < total) iter(g + 1, stg1, stg0, fA, sa);
+    }
+    if ((total - 1) & 1) slide(tv, sv, sb, rv, sr, cv);
+    else slide(tv, sv, sa, rv, sr, cv);
     return;
   }
   int t = t0, s = 0;
@@ -1193,6 +1366,47 @@ static hipError_t launch_drp(const A& a, int R, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3(nwg), dim3(64 * (D + 1) * (TW / 16)), lds, st, a);
   return hipGetLastError();
+}
+
+// Variant 4 (three boxes, sliding sums): only the 32-column matrix-core
+// instances at the compile-time radii exist.
+template <int RC, class A>
+static hipError_t launch_sl(const A& a, hipStream_t st) {
+  int nwg;
+  void (*kern)(A);
+  if constexpr (std::is_same_v<A, BatchArgs>) {
+    for (int k = 0; k < a.n; ++k)
+      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != kTWMax) return hipErrorInvalidValue;
+    kern = a.req[0].p64 ? mcsf_fused_batch<3, RC, 4, true, kTWMax, true>
+                        : mcsf_fused_batch<3, RC, 4, false, kTWMax, true>;
+    nwg = a.first[a.n];
+  } else {
+    if (a.TWc != kTWMax) return hipErrorInvalidValue;
+    kern = a.p64 ? mcsf_fused<3, RC, 4, true, kTWMax, true> : mcsf_fused<3, RC, 4, false, kTWMax, true>;
+    nwg = a.nsx * a.nsy;
+  }
+  const size_t lds = fused_lds_bytes(3, RC, 4, kTWMax, 1);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(64 * 4 * 2), lds, st, a);
+  return hipGetLastError();
+}
+
+template <class A>
+static hipError_t launch_sl_r(const A& a, int R, hipStream_t st) {
+  switch (R) {
+    case 6: return launch_sl<6>(a, st);
+    case 9: return launch_sl<9>(a, st);
+    case 12: return launch_sl<12>(a, st);
+    case 15: return launch_sl<15>(a, st);
+    case 18: return launch_sl<18>(a, st);
+    case 21: return launch_sl<21>(a, st);
+    case 24: return launch_sl<24>(a, st);
+    case 30: return launch_sl<30>(a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Radii with a fully unrolled specialisation (the workload radii and the

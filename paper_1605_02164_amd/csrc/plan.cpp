@@ -143,7 +143,7 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   double Wm[64];
   if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));
-  const int variant = kernel_variant(o->precision, o->spatial);
+  const int variant = select_variant(d, R, o->precision, o->spatial, W, o->tile_w, o->valu_only);
   if ((rc = check_fused_size(H, W, W, d, R))) return rc;
   int TH = 0, TW = 0;
   if ((rc = choose_strip_width(d, R, variant, H, W, o->tile_w, &TW))) return rc;

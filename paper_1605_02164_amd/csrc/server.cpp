@@ -52,13 +52,13 @@ constexpr int kMMFloats = 17;  // min/max partial block: 8 minima, 8 maxima, fla
 // Modelled device cost of one term of a planned request, in microseconds:
 // executed flops of all its workgroup steps (modulation of the haloed rows,
 // both passes; the 16-bit passes do two taps per instruction, the running-sum
-// vertical pass of variant 3 about eight operations per output) at a nominal
+// vertical passes of variants 3 and 4 about eight operations per output) at a nominal
 // rate.  Only ratios between requests matter for the chunking.
 double model_term_us(const FusedArgs& a, int d, int prec) {
   const double NC = 2.0 * (d + 1), taps = 2.0 * a.R + 1.0;
   const double mod = (double)kB * (a.TWc + 2 * a.R) * (4.0 * d + 2.0);
   const double one = (double)kB * NC * a.TWc * taps * 2.0;   // one FIR pass, FP32
-  const double pass = prec == 3 ? one + (double)kB * NC * a.TWc * 8.0
+  const double pass = prec >= 3 ? one + (double)kB * NC * a.TWc * 8.0
                                 : 2.0 * one * (prec == BF_FP32 ? 1.0 : 0.5);
   const double per_step = mod + pass;
   const double flops = per_step * a.steps * (double)a.nsx * a.nsy;
@@ -695,7 +695,7 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   int rc = whiten(in.d, r->Cm, r->Wm, in.whiten);
   if (rc) return rc;
   r->R = window_radius(in.sigma_s, spatial_boxes(in.spatial));
-  r->kvar = kernel_variant(in.precision, in.spatial);
+  r->kvar = select_variant(in.d, r->R, in.precision, in.spatial, in.W, 0, 0);
   if ((rc = check_fused_size(in.H, in.W, in.pitch, in.d, r->R))) return rc;
   int TH = 0, TW = 0;
   {

@@ -248,7 +248,8 @@ def test_strip_width_validation_before_device_work():
     assert vec(32, d=4) == B.BF_EUNSUPPORTED                       # d = 3 only
     assert vec(32, W=31) == B.BF_EUNSUPPORTED                      # narrower than a strip
     assert vec(32, sigma=2.5) == B.BF_EUNSUPPORTED                 # R = 8: runtime radius
-    assert vec(32, spatial="box3+runsum") == B.BF_EUNSUPPORTED     # running-sum variant
+    assert vec(32, spatial="box+runsum") == B.BF_EUNSUPPORTED      # running-sum box: 16 columns
+    assert vec(32, spatial="hat+runsum") == B.BF_EUNSUPPORTED      # (three boxes have both)
     assert b"32-column" in L.bf_last_error()
 
 
