@@ -35,9 +35,11 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "pending: counters not yet taken on these kernel sources",
-    "fetch_factor": 1048576 / 524306.5625,
+    "sha256": "8b078f7f66254d5ac66fcefd126c9d23c360028bcb21bdf62dcab0357e017a5f",
+    "fetch_factor": 1048576 / 524313.5625,
     "write_factor": 1048576 / 1048576.0,
+    "fp32": {"fetch_kib": 91494009.625, "write_kib": 67108864.0, "valu_flops": 318635507712.0, "mfma_flops": 10771777978368.0},
+    "fp16": {"fetch_kib": 102556786.75, "write_kib": 67108844.3125, "valu_flops": 505198673920.0, "mfma_flops": 21182778703872.0},
 }
 COUNTERS_PROFILE = "profiles/mcsf_fused_voronoi4096_d3_s10_K256.md"
 
@@ -605,7 +607,8 @@ def main():
                     help="precision of the headline value; the other modes are reported beside it")
     ap.add_argument("--only", action="store_true", help="time only --precision")
     ap.add_argument("--modes", help="comma-separated modes to time instead of the default set "
-                                    "(fp32, fp16, bf16, *_valu, *_dedup, fp32_box3, fp32_box3sl); "
+                                    "(fp32, fp16, bf16, *_valu, *_dedup, fp32_box3, fp32_box3rs, fp32_box3sl; "
+                                    "a _w16 suffix forces 16-column strips); "
                                     "the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -701,8 +704,12 @@ def main():
         prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
         tile_w = 16 if mode.endswith("_w16") else 0
         base = mode[:-4] if tile_w else mode
+        # box3: FIR passes over the three-box taps; box3rs: FP64 running sums
+        # (automatic width); box3sl: sliding sums (32-column strips)
         spatial = ("box3" if base.endswith("_box3") else
-                   "box3+runsum" if base.endswith("_box3sl") else "gauss")
+                   "box3+runsum" if base.endswith(("_box3rs", "_box3sl")) else "gauss")
+        if base.endswith("_box3sl"):
+            tile_w = 32
         valu = base.endswith("_valu")
         if not args.no_autotune and prec not in tuned:
             # one-off, untimed: measured strip height for this shape
@@ -737,7 +744,8 @@ def main():
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
         [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + \
-        ["fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3", "fp32_box3sl"]
+        ["fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3", "fp32_box3rs",
+         "fp32_box3sl"]
     if args.modes:
         precs = args.modes.split(",")
         args.precision = precs[0].split("_")[0]

@@ -77,6 +77,15 @@ inline constexpr int stage_width_mf32(int R) {
 constexpr int kSWMax = stage_width(kRMax);
 // 2R rows of look-ahead, in steps of kB rows
 inline constexpr int lag_steps(int R) { return (2 * R + kB - 1) / kB; }
+// Cos/sin ring of the pipelined FP32 instances, in steps of kB rows: a pair
+// window starting lag + 2 steps behind the newest modulated step reads the
+// cos/sin of its rows R .. R + 15, so (lag + 4) kB - R rows are live.
+inline constexpr int pipe_cs_steps(int R) { return ((lag_steps(R) + 4) * kB - R + kB - 1) / kB; }
+// Row padding of the cos/sin ring where the matrix-core vertical pass reads
+// it in 16-lane groups 4 rows apart (pipelined FP32, 16-bit storage in
+// 32-column strips): 4 rows of 2 TW + 4 floats are 16 mod 64 floats apart,
+// so the groups fall on different LDS banks.
+inline constexpr int cs_row_pad(bool padded) { return padded ? 4 : 0; }
 // Ring of horizontal-pass rows, in steps of kB rows: the FIR vertical pass
 // reads the 2R rows behind the newest step (vbox = 0); the running-sum pass
 // of the n-fold box also reads the n rows before those (vbox = n).
@@ -90,13 +99,14 @@ inline bool spatial_runsum(int spatial) { return (spatial & 16) != 0; }
 // any spatial taps), 3 FP32 with the running-sum vertical pass of the n-fold
 // box filters (requested by the flag), 4 FP32 three-box filter with sliding
 // box sums in the vertical pass and the horizontal pass on the matrix cores
-// (32-column strips; the flag with three boxes where such an instance exists).
+// (the flag with three boxes and 32-column strips asked for, where such an
+// instance exists).
 inline int kernel_variant(int precision, int spatial) {
   return precision == 0 && spatial_runsum(spatial) && spatial_boxes(spatial) > 0 ? 3 : precision;
 }
 // kernel_variant, with variant 4 in place of 3 for three boxes at d = 3, a
-// compile-time radius (multiple of 3), W >= 32, a strip width that is not
-// forced to 16 and matrix-core passes allowed.
+// compile-time radius (multiple of 3), W >= 32, tile_w = 32 and matrix-core
+// passes allowed (the automatic width keeps variant 3, measured faster).
 int select_variant(int d, int R, int precision, int spatial, int W, int tile_w, int valu);
 // BF_OK, or BF_EINVAL / BF_EUNSUPPORTED with the message set.
 int check_spatial(int spatial, int precision);

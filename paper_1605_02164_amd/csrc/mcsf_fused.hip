@@ -56,14 +56,16 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
   // two staging buffers and two more ring steps
   const bool pipe = use_pipe(prec, R, mf != 0);
   // variant 3 sizes the ring for the largest n (three boxes)
-  const int RS = (ring_steps(R, vb ? 3 : 0) + (pipe ? 2 : 0)) * kB, CRS = (lag + 2) * kB;
+  const int RS = (ring_steps(R, vb ? 3 : 0) + (pipe ? 2 : 0)) * kB;
+  const int CRS = (pipe ? pipe_cs_steps(R) : lag + 2) * kB;
+  const int CST = 2 * TW + cs_row_pad(pipe || (mf && lp && TW == kTWMax));
   const size_t fl = (size_t)taps_al + (lp ? 2 * (size_t)tapp_al : 0) +
                     (size_t)kB * NC * (pipe ? 2 : 1) *
                         (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
                             : (mf ? stage_width_mf32(R) : stage_width(R, TW))) +
                     (size_t)(lp ? RS / 2 : RS) *
                         (NC * TW + (mf && lp ? kRingPadMF : 0) + (pipe ? kRingPadPipe : 0)) +
-                    (size_t)CRS * 2 * TW +
+                    (size_t)CRS * CST +
                     (vb ? (size_t)16 * NC * TW : 0);
   return fl * sizeof(float);
 }
@@ -174,8 +176,11 @@ int fused_blocks_per_cu(int d, int R, int prec, int TW, int valu) {
 
 int select_variant(int d, int R, int precision, int spatial, int W, int tile_w, int valu) {
   const int v = kernel_variant(precision, spatial);
+  // variant 4 only where 32-column strips are asked for: at 4096^2, R = 30,
+  // K = 256 it took 216 ms against 174 ms for the 16-column running sums
+  // (variant 3), so the automatic choice keeps variant 3
   if (v == 3 && spatial_boxes(spatial) == 3 && d == 3 && specialised_radius(R) && R % 3 == 0 &&
-      W >= kTWMax && tile_w != kTW && !valu)
+      W >= kTWMax && tile_w == kTWMax && !valu)
     return 4;
   return v;
 }

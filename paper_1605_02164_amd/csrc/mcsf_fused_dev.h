@@ -388,7 +388,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // columns, which a stride of 16 mod 32 floats spreads over the LDS banks.
   constexpr bool PIPE = use_pipe(PREC, RC, MF);
   constexpr int RST = NC * TW + (MFV ? kRingPadMF : 0) + (PIPE ? kRingPadPipe : 0);   // ring row stride: [ch][x]
-  constexpr int CST = 2 * TW;        // cos/sin ring row stride: [k][x]
+  constexpr int CST = 2 * TW + cs_row_pad(PIPE || (MFV && TW == 32));   // cos/sin ring row: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
   constexpr bool VB = PREC == 3;                 // running-sum vertical pass
   // Variant 4 (FP32, three boxes, 32-column strips): horizontal pass on the
@@ -412,7 +412,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const int ntap4 = (2 * R + 1 + 3) / 4 * 4;
   const int taps_al = (ntap4 + 7) / 8 * 8;
   const int tapp_al = (R + 1 + 3) / 4 * 4;
-  const int RS = SLV ? SL_RS : (a.RSB + (PIPE ? 2 : 0)) * B, CRS = SLV ? SL_CRS : a.CRB * B;
+  const int CRB = PIPE ? pipe_cs_steps(RC) : a.CRB;
+  const int RS = SLV ? SL_RS : (a.RSB + (PIPE ? 2 : 0)) * B, CRS = SLV ? SL_CRS : CRB * B;
   // LDS carve-up: FP32 taps | packed tap pairs (16-bit modes) | staging (two
   // buffers with PIPE) | ring | cos/sin ring.  16-bit modes store the ring as
   // row pairs.
@@ -637,7 +638,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // behind it (rows the vertical pass starts from), advanced by B per step
   const int RSBk = RS / B;
   int rslot = 0, cslot = 0;
-  int rslot_lag = (RSBk - lag % RSBk) % RSBk * B, cslot_lag = (a.CRB - lag % a.CRB) % a.CRB * B;
+  int rslot_lag = (RSBk - lag % RSBk) % RSBk * B, cslot_lag = (CRB - lag % CRB) % CRB * B;
   float wr[D];       // frequencies of the term being modulated
   float tw = 1.0f;   // weight of the term being demodulated
   auto load_wr = [&](int t) {
@@ -713,9 +714,16 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // schedule can place the vertical pass's ring loads between the products
   // and the ring stores: the banded product of the staging buffer stg, then
   // the store of its results into ring rows r0.
+  // Product row m of block mb is staging row 2mb + ((m >> 2) & 1) (of the
+  // step), channel 2 (m & 3) + (m >> 3): lane l then holds row 2mb + (l/16
+  // & 1) of channels 2v + l/32, v < 4, so that the four 16-lane groups of a
+  // ring store sit at 0, RST, TW and RST + TW floats: 0, 16, 32 and 48 mod 64
+  // with the pipelined ring's padding, each group on 16 banks of its own.
   auto hmf = [&](const float* stg) {
+    static_assert(!(MF && !LP) || NC == 8, "FP32 matrix-core pass: 2 rows x 8 channels per block");
     const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
-    const float* arow = stg + (16 * mb + (ln & 15)) * SW + 16 * nb + (ln >> 4);
+    const int m = ln & 15, srow = (2 * mb + ((m >> 2) & 1)) * NC + 2 * (m & 3) + (m >> 3);
+    const float* arow = stg + srow * SW + 16 * nb + (ln >> 4);
     f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < KS4; ++k) d = mfma4(arow[4 * k], hb4[k], d);
@@ -723,11 +731,10 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   };
   auto hmf_store = [&](const f32x4_t& d, int r0) {
     const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+    const int g = ln >> 4, row = 2 * mb + (g & 1);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
-      s_ring[(r0 + row) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)] = d[v];
-    }
+    for (int v = 0; v < 4; ++v)
+      s_ring[(r0 + row) * RST + (2 * v + (g >> 1)) * TW + 16 * nb + (ln & 15)] = d[v];
   };
 
   // ---- FP32 matrix-core vertical pass of a pair of steps (PIPE instances) --
@@ -779,7 +786,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     // Matrix-core horizontal pass: the step's staging rows m = NC row +
     // channel (16 NP of them) form NP blocks of 16; wave w takes block w % NP
     // and output columns 16(w/NP) .. +15.  Lane l's results are items
-    // m = 16(w%NP) + 4(l/16) + v, column 16(w/NP) + l%16.
+    // m = 16(w%NP) + 4(l/16) + v, column 16(w/NP) + l%16 (FP32: items in
+    // the order given at hmf).
     if constexpr (MF && !LP) {
       // FP32: k-blocks of 4 samples (one per lane group of 16)
       hmf_store(hmf(stg), rslot);
@@ -1029,7 +1037,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     int rh = 0;
     int rl = (RSBk - (lag + 2) % RSBk) % RSBk * B;
     int cm = B % CRS;
-    int cl = (a.CRB - (lag + 2) % a.CRB) % a.CRB * B;
+    int cl = (CRB - (lag + 2) % CRB) % CRB * B;
     auto iter = [&](int g, const float* stg_h, float* stg_m, float (&fm)[MI][D]) {
       if (g >= 1 && sv > lag && ((sv - lag) & 1)) {
         // the pair (sv - 1, sv) of term tv and the horizontal pass of step
@@ -1189,7 +1197,8 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     int rh = 0, rv = RS - B, sr = SL_S1R - B, cv = CRS - B, cm = B;
     auto iter = [&](int g, const float* stg_h, float* stg_m, float (&fm)[MI][D],
                     float (&av)[4]) {
-      hpass_step(stg_h, rh);
+      // the sliding sums first: while waves 0..NP-1 run them on the VALU,
+      // the other waves' horizontal-pass products have the matrix cores
       if (g >= 1) {
         slide(tv, sv, av, rv, sr, cv);
         int s2 = sv + 2, t2 = tv;       // accumulators of step g + 1
@@ -1201,6 +1210,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
           if (++tv < t1) load_tw(tv);
         }
       }
+      hpass_step(stg_h, rh);
       if (g + 1 < total) {
         modulate(tm, sm, fm, stg_m, cm);
         int s3 = sm + 2;

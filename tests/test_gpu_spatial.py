@@ -135,12 +135,13 @@ def test_box_family_plan_and_server_match_standalone(precision, name):
 
 @pytest.mark.parametrize("R", [6, 9, 12, 15, 18, 21, 24, 30])
 def test_box3_sliding_sums_every_radius(R):
-    # Three boxes with BF_SPATIAL_RUNSUM at d = 3 and a compile-time radius run
-    # 32-column strips whose vertical pass is cascaded sliding box sums (and
-    # whose horizontal pass is a matrix-core product over the box taps); a
-    # forced 16-column strip runs the FP64 running-sum instance instead.  Both
-    # against the oracle's three-box filter over a whole image of several
-    # strips both ways (ragged), at the automatic strip height and at 24 rows.
+    # Three boxes with BF_SPATIAL_RUNSUM at d = 3 and a compile-time radius:
+    # with 32-column strips asked for, the vertical pass is cascaded sliding
+    # box sums (and the horizontal pass a matrix-core product over the box
+    # taps); the automatic width and forced 16-column strips run the FP64
+    # running-sum instance.  All against the oracle's three-box filter over a
+    # whole image of several strips both ways (ragged), at the automatic strip
+    # height and at 24 rows.
     r = R // 3
     sigma = float(np.sqrt(r * (r + 1)))      # box_radius(sigma, 3) = r exactly
     assert O.window_radius(sigma, 3) == R
@@ -151,10 +152,10 @@ def test_box3_sliding_sums_every_radius(R):
     K, N, seed = 5, 14, 3 + R
     ref, z = oracle_full(f, sigma, C, K, seed, N, 3)
     fg = cuda(f)
-    for tile_w, tile_h in ((0, 0), (0, 24), (16, 24)):
+    for tile_w, tile_h in ((32, 0), (32, 24), (16, 24), (0, 0)):
         got, o = P.bf_vec_ex(fg, sigma, C, K, seed, N=N, spatial="box3+runsum", tile_w=tile_w,
                              tile_h=tile_h, return_opts=True)
         say(f"  tile_w={o.tile_w_used} tile_h={o.tile_h_used} matrix cores={o.mfma_used}")
-        assert o.tile_w_used == (16 if tile_w == 16 else 32)
-        assert o.mfma_used == (0 if tile_w == 16 else 1)
+        assert o.tile_w_used == (32 if tile_w == 32 else 16)
+        assert o.mfma_used == (1 if tile_w == 32 else 0)
         check(host(got), ref, f, z, TOL["fp32"])

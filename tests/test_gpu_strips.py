@@ -164,7 +164,7 @@ def test_automatic_width():
     assert width(f3, 3.0, C3) == 32
     assert width(f3, 2.5, C3) == 16                                    # R = 8
     assert width(f3, 3.0, C3, spatial="box+runsum") == 16              # FP64 running sums
-    assert width(f3, 3.0, C3, spatial="box3+runsum") == 32             # sliding three-box sums
+    assert width(f3, 3.0, C3, spatial="box3+runsum") == 16             # (sliding sums: asked for)
     f4 = voronoi_image(256, 320, 4, 6, 0.0, 1.0, 0.02, 5)
     assert width(f4, 3.0, np.eye(4) * 0.1 ** 2) == 16                  # d = 4
     f3 = voronoi_image(4096, 20, 3, 6, 0.0, 1.0, 0.02, 3)
