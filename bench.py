@@ -28,18 +28,20 @@ PEAK_FP32_NONPACKED = 78.6  # TFLOP/s: the same without packed-FP32 issue
 
 # HBM bytes per launch of the benchmark's fused kernel, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
-# counters read for a 1 GiB device copy (FETCH_SIZE 524,308.8125 KiB: factor
-# 1.99992; WRITE_SIZE 1,048,576 KiB: factor 1.0).  Valid only for the kernel
+# counters read for a 1 GiB device copy (FETCH_SIZE 524,313.375 KiB: factor
+# 1.99988; WRITE_SIZE 1,048,576 KiB: factor 1.0), with the executed VALU and
+# matrix-core flops of the same launches (rocprofv3 --pmc
+# SQ_INSTS_VALU_FLOPS_* x 64 lanes, SQ_INSTS_VALU_MFMA_MOPS_* x 512).  Valid only for the kernel
 # sources they were taken on (TRAFFIC_SOURCES hash); otherwise reported null.
 TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "8b078f7f66254d5ac66fcefd126c9d23c360028bcb21bdf62dcab0357e017a5f",
-    "fetch_factor": 1048576 / 524313.5625,
+    "sha256": "60b45146149d51e269b36ca4675a358b3db7db4f02c4da8969a27b27eff53277",
+    "fetch_factor": 1048576 / 524313.375,
     "write_factor": 1048576 / 1048576.0,
-    "fp32": {"fetch_kib": 91494009.625, "write_kib": 67108864.0, "valu_flops": 318635507712.0, "mfma_flops": 10771777978368.0},
-    "fp16": {"fetch_kib": 102556786.75, "write_kib": 67108844.3125, "valu_flops": 505198673920.0, "mfma_flops": 21182778703872.0},
+    "fp32": {"fetch_kib": 88312406.375, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},
+    "fp16": {"fetch_kib": 100750744.75, "write_kib": 67108535.5625, "valu_flops": 505198673920.0, "mfma_flops": 20615843020800.0},
 }
 COUNTERS_PROFILE = "profiles/mcsf_fused_voronoi4096_d3_s10_K256.md"
 
