@@ -113,9 +113,10 @@ def cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=None, crop=1024, direct_cro
     2. O1, the direct filter of eqs. (BF)/(normal) with the exact Gaussian
        range kernel (the paper's comparison method), on a smaller centred
        crop, pixels split over the workers.
-    3. The GPU outputs (gpu_outs: mode -> (H, W, d) tensor) against O2,
-       the direct filter with the same sampled kernel, at seeded pixels:
-       max and mean error as a fraction of each channel's range.
+    3. The GPU outputs (gpu_outs: mode -> ((H, W, d) tensor, spatial
+       filter: 0 Gaussian, 3 three boxes)) against O2, the direct filter with
+       the same sampled kernel and spatial filter, at seeded pixels: max and
+       mean error as a fraction of each channel's range.
     """
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
@@ -170,22 +171,26 @@ def cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=None, crop=1024, direct_cro
         pts = np.stack([rng.integers(0, H, n), rng.integers(0, W, n)], axis=1)
         corners = np.array([[0, 0], [0, W - 1], [H - 1, 0], [H - 1, W - 1]])
         pts = np.unique(np.concatenate([pts, corners]), axis=0)
-        with threadpool_limits(limits=1), ThreadPoolExecutor(workers) as ex:
-            t0 = time.perf_counter()
-            res = list(ex.map(lambda c: O.direct_sampled(f64, sigma_s, w, pixels=c),
-                              np.array_split(pts, 8 * workers)))
-            dt2 = time.perf_counter() - t0
-        ref = np.concatenate([r[0] for r in res])
+        refs, dt2 = {}, 0.0
+        for sp in sorted({v[1] for v in gpu_outs.values()}):
+            with threadpool_limits(limits=1), ThreadPoolExecutor(workers) as ex:
+                t0 = time.perf_counter()
+                res = list(ex.map(lambda c: O.direct_sampled(f64, sigma_s, w, pixels=c,
+                                                             spatial=sp),
+                                  np.array_split(pts, 8 * workers)))
+                dt2 += time.perf_counter() - t0
+            refs[sp] = np.concatenate([r[0] for r in res])
         span = f64.reshape(-1, d).max(0) - f64.reshape(-1, d).min(0)
         span[span == 0] = 1.0
         acc = {}
-        for mode, out in gpu_outs.items():
+        for mode, (out, sp) in gpu_outs.items():
             # out: a device tensor of the GPU run; only the sampled pixels come back
             g = out[pts[:, 0], pts[:, 1]].double().cpu().numpy()
-            e = np.abs(g - ref) / span
+            e = np.abs(g - refs[sp]) / span
             acc[mode] = {"max_err": float(e.max()), "mean_err": float(e.mean())}
         rec["accuracy_vs_oracle"] = {
-            "reference": "O2: direct filter with the same K sampled terms (FP64)",
+            "reference": "O2: direct filter with the same K sampled terms and the mode's "
+                         "spatial filter (FP64)",
             "pixels": int(len(pts)), "unit": "fraction of each channel's range",
             "oracle_s": dt2, "modes": acc}
     return rec
@@ -329,6 +334,7 @@ def serving_run(args, P, torch, log_fn, policy="share", graph_rounds=False, auto
         "streams": args.serve_streams, "dedup": dedup,
         "max_active": args.serve_max_active, "rounds": stats["rounds"],
         "launches": stats["launches"], "arena_peak_gib": stats["arena_peak"] / 2**30,
+        "model_scale": stats["model_scale"],
         "spot_check_bitwise_equal_alone": same,
     }
     log_fn(f"serving: p50 {rec['p50_ms']:.1f} ms, p99 {rec['p99_ms']:.1f} ms "
@@ -802,8 +808,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
-        gauss = {m: outs[m] for m in results if results[m]["spatial"] == "gauss"}
-        cpu = cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=gauss)
+        sp_code = {"gauss": 0, "box3": 3, "box3+runsum": 3}
+        cpu = cpu_baseline(f, C, sigma_s, K, seed, N,
+                           gpu_outs={m: (outs[m], sp_code[results[m]["spatial"]])
+                                     for m in results})
         log(f"cpu baseline {cpu['value']:.4g} Mpix/s ({cpu['sample']}); direct O1 "
             f"{cpu['direct_o1']['value']:.4g} Mpix/s")
         for m, e in cpu["accuracy_vs_oracle"]["modes"].items():

@@ -405,7 +405,11 @@ typedef struct bf_server_stats {
   uint64_t arena_bytes, arena_peak;
   int admitted;         /* requests admitted now                                  */
   int queued;           /* requests waiting for admission now                     */
-  int reserved[6];
+  float model_scale;    /* measured device time / modelled time of the rounds so
+                           far (running average; the round planner multiplies the
+                           modelled cost of a term by it, so quantum_us is in
+                           measured microseconds); 1 before the first round     */
+  int reserved[5];
 } bf_server_stats;
 
 /* Fill *cfg with the defaults (all zero fields mean "default"). */

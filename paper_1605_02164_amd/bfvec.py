@@ -157,7 +157,8 @@ class bf_server_stats(ctypes.Structure):
         ("arena_peak", ctypes.c_uint64),
         ("admitted", ctypes.c_int),
         ("queued", ctypes.c_int),
-        ("reserved", ctypes.c_int * 6),
+        ("model_scale", ctypes.c_float),
+        ("reserved", ctypes.c_int * 5),
     ]
 
 

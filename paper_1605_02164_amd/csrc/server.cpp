@@ -52,8 +52,10 @@ constexpr int kMMFloats = 17;  // min/max partial block: 8 minima, 8 maxima, fla
 // Modelled device cost of one term of a planned request, in microseconds:
 // executed flops of all its workgroup steps (modulation of the haloed rows,
 // both passes; the 16-bit passes do two taps per instruction, the running-sum
-// vertical passes of variants 3 and 4 about eight operations per output) at a nominal
-// rate.  Only ratios between requests matter for the chunking.
+// vertical passes of variants 3 and 4 about eight operations per output) at a
+// nominal 50 TFLOP/s.  The server scales it by the measured device time of
+// its rounds over their modelled time (Server::model_scale), so the nominal
+// rate only sets the first rounds.
 double model_term_us(const FusedArgs& a, int d, int prec) {
   const double NC = 2.0 * (d + 1), taps = 2.0 * a.R + 1.0;
   const double mod = (double)kB * (a.TWc + 2 * a.R) * (4.0 * d + 2.0);
@@ -93,7 +95,9 @@ struct Req {
 };
 
 struct Round {
-  std::vector<hipEvent_t> evs;
+  std::vector<hipEvent_t> evs;         // end of the round's work on each stream it used
+  std::vector<hipEvent_t> starts;      // its start on that stream (timing events)
+  std::vector<double> model_us;        // modelled device time of its launches there
   std::vector<hipGraphExec_t> execs;   // graph rounds: freed when the round has passed
   std::vector<hipGraph_t> graphs;
 };
@@ -127,7 +131,7 @@ struct Server {
   std::multimap<std::pair<double, uint64_t>, Req*> pending;
   std::vector<Req*> preparing, active, finishing;
   std::deque<Round> rounds;
-  std::vector<hipEvent_t> event_pool;
+  std::vector<hipEvent_t> event_pool, tevent_pool;
   int fatal = 0;
   std::string fatal_msg;
   std::thread worker;
@@ -150,6 +154,41 @@ struct Server {
   void give_event(hipEvent_t& e) {
     if (e) event_pool.push_back(e);
     e = nullptr;
+  }
+  // timing-enabled events: the start and end of a round on each stream
+  hipEvent_t take_tevent() {
+    if (!tevent_pool.empty()) {
+      hipEvent_t e = tevent_pool.back();
+      tevent_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void give_tevent(hipEvent_t& e) {
+    if (e) tevent_pool.push_back(e);
+    e = nullptr;
+  }
+  // Measured device time of the rounds over their modelled time, a running
+  // average over rounds (each stream of a round one sample; concurrent
+  // streams share the device, so a sample measures the time its work took
+  // there, which is what a round's length is made of).
+  double model_scale = 1.0;
+  // event polling interval of the scheduler thread while the device is busy
+  static constexpr int kPollMinUs = 20, kPollMaxUs = 160;
+  int poll_us = kPollMinUs;
+  void calibrate(const Round& rd) {
+    for (size_t i = 0; i < rd.starts.size() && i < rd.evs.size(); ++i) {
+      float ms = 0.0f;
+      if (!rd.starts[i] || !rd.evs[i] || rd.model_us[i] <= 0.0 ||
+          hipEventElapsedTime(&ms, rd.starts[i], rd.evs[i]) != hipSuccess)
+        continue;
+      const double ratio = std::min(20.0, std::max(0.05, 1e3 * ms / rd.model_us[i]));
+      model_scale += 0.2 * (ratio - model_scale);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    stats.model_scale = (float)model_scale;
   }
 
   void release(Req* r) {
@@ -350,7 +389,7 @@ struct Server {
     jobs.reserve(active.size());
     for (size_t i = 0; i < active.size(); ++i)
       jobs.push_back(PlanJob{(int)i, active[i]->variant, active[i]->next_t, active[i]->K_run,
-                             active[i]->cost_term});
+                             active[i]->cost_term * model_scale});
     const std::vector<PlanLaunch> plan = plan_round(jobs, cfg.quantum_us, kMaxBatch, cfg.policy);
     Round rd;
     std::map<int, bool> capturing;   // graph rounds: streams being captured
@@ -368,7 +407,7 @@ struct Server {
       }
       capturing.clear();
     };
-    std::set<int> used;
+    std::map<int, size_t> stream_slot;   // stream -> index into rd.starts / rd.model_us
     std::vector<Req*> ended;
     std::set<Req*> failed;
     std::string failed_msg;
@@ -389,6 +428,19 @@ struct Server {
       }
       hipStream_t st = streams[r0->stream];
       const bool injected = fault_at != 0 && ++launch_count == fault_at;
+      if (!stream_slot.count(r0->stream)) {
+        // the round's start on this stream (outside any capture)
+        hipEvent_t ev = take_tevent();
+        if (!ev || hipEventRecord(ev, st) != hipSuccess) {
+          give_tevent(ev);
+          set_fatal(hipErrorUnknown, "round start event");
+          abort_captures();
+          return true;
+        }
+        stream_slot[r0->stream] = rd.starts.size();
+        rd.starts.push_back(ev);
+        rd.model_us.push_back(0.0);
+      }
       hipError_t e = begin_capture(r0->stream);
       if (e != hipSuccess) {
         set_fatal(e, "round capture");
@@ -424,7 +476,8 @@ struct Server {
         continue;
       }
       wgs += (uint64_t)b.first[b.n];
-      used.insert(r0->stream);
+      for (const PlanItem& it : L.items)
+        rd.model_us[stream_slot[r0->stream]] += (it.t1 - it.t0) * active[it.job]->cost_term;
       for (const PlanItem& it : L.items) {
         Req* r = active[it.job];
         r->next_t = it.t1;
@@ -475,15 +528,24 @@ struct Server {
           rounds.push_back(std::move(rd));
           return true;
         }
-    for (int s : used) {
-      hipEvent_t ev = take_event();
-      if (!ev || hipEventRecord(ev, streams[s]) != hipSuccess) {
+    // the round's end on every stream it started on, in the order of
+    // rd.starts (a stream whose launches were all refused ends at once)
+    std::vector<hipEvent_t> ends(rd.starts.size(), nullptr);
+    for (const auto& kv : stream_slot) {
+      hipEvent_t ev = take_tevent();
+      if (!ev || hipEventRecord(ev, streams[kv.first]) != hipSuccess) {
         set_fatal(hipErrorUnknown, "round event");
-        give_event(ev);
+        give_tevent(ev);
         break;
       }
-      rd.evs.push_back(ev);
+      ends[kv.second] = ev;
     }
+    for (size_t i = 0; i < ends.size(); ++i) {
+      if (ends[i]) continue;   // fatal above: keep the lists aligned for the cleanup
+      ends[i] = rd.starts[i];
+      rd.starts[i] = nullptr;
+    }
+    rd.evs = std::move(ends);
     rounds.push_back(std::move(rd));
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -522,7 +584,9 @@ struct Server {
         if (q != hipSuccess) set_fatal(q, "round");
       }
       if (!done) break;
-      for (hipEvent_t& ev : rd.evs) give_event(ev);
+      calibrate(rd);
+      for (hipEvent_t& ev : rd.evs) give_tevent(ev);
+      for (hipEvent_t& ev : rd.starts) give_tevent(ev);
       for (hipGraphExec_t x : rd.execs) (void)hipGraphExecDestroy(x);
       for (hipGraph_t g : rd.graphs) (void)hipGraphDestroy(g);
       rounds.pop_front();
@@ -557,7 +621,8 @@ struct Server {
     for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     (void)hipStreamSynchronize(aux);
     for (Round& rd : rounds) {
-      for (hipEvent_t& ev : rd.evs) give_event(ev);
+      for (hipEvent_t& ev : rd.evs) give_tevent(ev);
+      for (hipEvent_t& ev : rd.starts) give_tevent(ev);
       for (hipGraphExec_t x : rd.execs) (void)hipGraphExecDestroy(x);
       for (hipGraph_t g : rd.graphs) (void)hipGraphDestroy(g);
     }
@@ -613,9 +678,17 @@ struct Server {
       progress |= finish_preparing();
       progress |= admit();
       progress |= enqueue_round();
-      if (progress) continue;
+      if (progress) {
+        poll_us = kPollMinUs;
+        continue;
+      }
       if (busy) {
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // device work in flight and nothing to do until some of it ends:
+        // poll its events with a backoff (doubling up to kPollMaxUs while
+        // nothing changes), woken at once by a submission
+        std::unique_lock<std::mutex> lk(mu);
+        if (incoming.empty() && !stop) cv_work.wait_for(lk, std::chrono::microseconds(poll_us));
+        poll_us = std::min(2 * poll_us, kPollMaxUs);
         continue;
       }
       // idle: sleep until a submission, the next arrival, or stop
@@ -788,6 +861,7 @@ int bf_server_create(const bf_server_config* cfg_in, bf_server** out) {
     return fail(BF_EINVAL, "bad server configuration");
   auto s = std::make_unique<bf_server>();
   s->cfg = cfg;
+  s->stats.model_scale = 1.0f;
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) return hip_err(e, "hipGetDevice");
   // host staging: one term table per admitted request at most K = 65536, d = 8
@@ -927,6 +1001,7 @@ int bf_server_destroy(bf_server* s) {
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   if (s->aux) (void)hipStreamSynchronize(s->aux);
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->tevent_pool) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->aux) (void)hipStreamDestroy(s->aux);
   if (s->tune_stream) {

@@ -388,3 +388,5 @@ def test_server_modes_match_standalone_bitwise(pools, policy, graph_rounds, auto
             assert torch.equal(got, ref), (spec, float((got - ref).abs().max()))
         assert stats["completed"] == len(MIX) and stats["failed"] == 0
         assert stats["rounds"] >= 4
+        # the cost model's scale, measured from the rounds' device time
+        assert 0.05 <= stats["model_scale"] <= 20.0 and stats["model_scale"] != 1.0, stats
