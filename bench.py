@@ -778,6 +778,23 @@ def main():
     assert main_rec["K_used"] == K
     dt = main_rec["ms_per_step"] * args.steps / 1e3
 
+    # host steps of a call, timed on their own (median of 50 calls each, µs):
+    # A1 whitening, A2 the min/max reduction (device, with the copy of 2d
+    # floats back) and the order rule, A3 the term draws (with whitening)
+    def med_us(fn, n=50):
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts) * 1e6)
+    lo, hi = P.bf_minmax(fg)
+    host_steps = {"A1_whiten_us": med_us(lambda: P.bf_whiten(C)),
+                  "A2_minmax_us": med_us(lambda: P.bf_minmax(fg)),
+                  "A2_choose_N_us": med_us(lambda: P.bf_choose_N(C, lo, hi)),
+                  "A3_sample_terms_us": med_us(lambda: P.bf_sample_terms(C, N, K, seed))}
+    log("host steps: " + ", ".join(f"{k} {v:.1f}" for k, v in host_steps.items()))
+
     # same-GPU comparator: the direct filter of eq. (BF) with the exact
     # Gaussian range kernel on the same image and window
     direct = None
@@ -871,6 +888,7 @@ def main():
             "executed_matrix_core_tflops": ex_mfma,
         },
         "cpu_baseline": cpu,
+        "host_steps": host_steps,
         "direct_comparator": direct,
         "serving": serving,
         "serving_variants": variants,
