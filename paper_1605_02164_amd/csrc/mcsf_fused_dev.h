@@ -351,6 +351,16 @@ __device__ __forceinline__ float buf_load1(__amdgpu_buffer_rsrc_t r, unsigned by
 __device__ __forceinline__ void buf_store1(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
 }
+// The same with the address split into a per-lane part (voff, a VGPR kept
+// across the loop) and a wave-uniform part (soff, an SGPR): the uniform row
+// offsets of a step then cost no vector instructions.
+__device__ __forceinline__ float buf_load1s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_store1s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                            float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
 
 // Read-only table entry through the constant address space: a uniform index
 // then becomes a scalar load.
@@ -554,6 +564,16 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   const unsigned acc_lane =
       MFV ? (unsigned)(mf_m * a.Hp + y0 + mf_r0) * Wp + x0 + mf_x
          : (unsigned)(p2_m * a.Hp + y0 + 2 * p2_k) * Wp + x0 + p2_x;
+  // matrix-core vertical pass: this lane's operand column in the ring, and
+  // its pair-row group 4g (g = (lane / 16) % 4) within a k-block
+  const int mf_g4 = 4 * ((tid >> 4) & 3);
+  const int mfv_lane = (2 * mf_m) * TW + mf_x + mf_g4 * RST;
+  // matrix-core horizontal pass with 16-bit storage (d = 3): this lane's
+  // ring offset in halves, without the step's rows (the store below)
+  const int hs_lane = [&] {
+    const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP, g = ln >> 4;
+    return 2 * (mb * RST + 4 * (g & 1) * TW + 16 * nb + (ln & 15)) + (g >> 1);
+  }();
   // variant 3: running sums of one (column, channel) per lane of the first
   // 16*NC lanes; sparse-difference weights (-1)^k C(n,k), offsets k(2r+1)
   const int vb_x = tid & 15, vb_ch = tid >> 4;
@@ -582,6 +602,17 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     m_xin[i] = tid + i * NT < nmod && j < TW + 2 * R && m_x[i] >= 0 && m_x[i] < Wd;
   }
   const int ybase = y0 - R;
+  // cos/sin ring slot of each modulation slot whose column is an output
+  // column (row within the step, column): a per-lane offset from the ring
+  // row of the step
+  int m_cs[MI];
+  bool m_csin[MI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+    const int xc = m_x[i] - x0;
+    m_csin[i] = xc >= 0 && xc < TW;
+    m_cs[i] = m_rr[i] * CST + xc;
+  }
 
   // Prefetch buffers, two steps deep (ping-pong A/B by step parity): raw f of
   // each modulation slot, loaded from a clamped in-image address so the loads
@@ -624,9 +655,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     (void)t;
     const int so = max(s - lag, 0);
     if constexpr (MFV) {
-      const unsigned o = acc_lane + (unsigned)(so * B) * Wp;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
+      for (int v = 0; v < 4; ++v)
+        dst[v] = buf_load1s(acc_rsrc, 4u * acc_lane, 4u * (unsigned)(so * B + v) * Wp);
     } else {
       const unsigned o = acc_lane + (unsigned)(so * B + p2_g * 4) * Wp;
       dst[0] = buf_load1(acc_rsrc, 4u * o);
@@ -701,10 +732,9 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
           st[(2 * D) * SW] = c;
           st[(2 * D + 1) * SW] = sn;
         }
-        const int xc = m_x[i] - x0;
-        if (xc >= 0 && xc < TW) {
-          s_cs[(cs0 + m_rr[i]) * CST + xc] = c;
-          s_cs[(cs0 + m_rr[i]) * CST + TW + xc] = sn;
+        if (m_csin[i]) {
+          s_cs[cs0 * CST + m_cs[i]] = c;
+          s_cs[cs0 * CST + m_cs[i] + TW] = sn;
         }
       }
     }
@@ -749,13 +779,17 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // updates four accumulator rows.  pr: strip row of the pair's first output
   // row; rl / cl: ring / cos-sin rows of its first window row; ap: this
   // lane's accumulators of the pair (prefetched; unused for t = 0).
+  // this lane's accumulator column and first row of a pair, without the
+  // pair's first output row (a uniform offset)
+  const unsigned accp_lane = [&] {
+    const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
+    return (unsigned)(m * a.Hp + y0 + 4 * (ln >> 4)) * Wp + x0 + 16 * nb + (ln & 15);
+  }();
   auto load_accp = [&](float (&dst)[4], int t, int pr) {
     (void)t;   // loaded whatever t is, like load_acc
-    const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
-    const unsigned o =
-        (unsigned)(m * a.Hp + y0 + pr + 4 * (ln >> 4)) * Wp + x0 + 16 * nb + (ln & 15);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dst[v] = buf_load1(acc_rsrc, 4u * (o + v * Wp));
+    for (int v = 0; v < 4; ++v)
+      dst[v] = buf_load1s(acc_rsrc, 4u * accp_lane, 4u * (unsigned)(pr + v) * Wp);
   };
   auto vpair = [&](int t, int pr, const float (&ap)[4], int rl, int cl) {
     const int ln = tid & 63, m = (tid >> 6) % NP, nb = (tid >> 6) / NP;
@@ -770,12 +804,12 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       dc = mfma4(hb4[k], cc[row * RST], dc);
       ds = mfma4(hb4[k], cc[row * RST + TW], ds);
     }
-    const unsigned o = (unsigned)(m * a.Hp + y0 + pr + 4 * (ln >> 4)) * Wp + x0 + col;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const float* cs = s_cs + wrap(cl + R + 4 * (ln >> 4) + v, CRS) * CST + col;
       const float q = fmaf(cs[TW], ds[v], cs[0] * dc[v]);
-      buf_store1(acc_rsrc, 4u * (o + v * Wp), fmaf(tw, q, t > 0 ? ap[v] : 0.0f));
+      buf_store1s(acc_rsrc, 4u * accp_lane, 4u * (unsigned)(pr + v) * Wp,
+                  fmaf(tw, q, t > 0 ? ap[v] : 0.0f));
     }
   };
 
@@ -803,11 +837,20 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       // no hand-written instruction reads the product's registers (the
       // compiler places the wait states a matrix-core result needs only before
       // the instructions it generates).
+      if constexpr (NC == 8) {
+        // item m = 16mb + 4g + v (g = lane / 16) is row 2mb + g/2 of the
+        // step, channel 4(g & 1) + v: with rslot even, pair-row rslot/2 + mb,
+        // half g/2 -- a per-lane offset plus rslot * RST and v * 2 TW
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
-        s_ring16[2 * (((rslot + row) >> 1) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)) +
-                 (row & 1)] = to16<PREC>(d[v]);
+        for (int v = 0; v < 4; ++v)
+          s_ring16[rslot * RST + hs_lane + v * 2 * TW] = to16<PREC>(d[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * mb + 4 * (ln >> 4) + v, row = m / NC;
+          s_ring16[2 * (((rslot + row) >> 1) * RST + (m - row * NC) * TW + 16 * nb + (ln & 15)) +
+                   (row & 1)] = to16<PREC>(d[v]);
+        }
       }
     } else {
       float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -857,25 +900,33 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
         // around the ring and read finite values.
         constexpr int RSP = ring_steps(RC, 0) * kB / 2;
         static_assert(RSP % 4 == 0 && (RSP - 4) + 16 * (KSV - 1) + 12 < 3 * RSP, "pair-row wrap");
-        const unsigned* colc = s_ring32 + (2 * mf_m) * TW + mf_x;
-        const int pb = rslot_lag / 2 + 4 * ((tid >> 4) & 3);
+        // Lane group g reads pair-rows p = rslot_lag/2 + 16k + 4g (mod RSP):
+        // the uniform part is reduced on the scalar unit, and a lane whose 4g
+        // carries it past RSP takes the other of two uniform offsets.
+        const unsigned* colc = s_ring32 + mfv_lane;
         f32x4_t dc = {0.0f, 0.0f, 0.0f, 0.0f}, ds = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int k = 0; k < KSV; ++k) {
-          int p = pb + 16 * k;
-          p = p >= RSP ? p - RSP : p;
-          p = p >= RSP ? p - RSP : p;
-          const unsigned* r0 = colc + p * RST;
+          int u = rslot_lag / 2 + 16 * k;
+          u = u >= RSP ? u - RSP : u;
+          u = u >= RSP ? u - RSP : u;
+          const unsigned* r0 = colc + u * RST - (mf_g4 >= RSP - u ? RSP * RST : 0);
           dc = mfma32<PREC>(va[k], make_uint4(r0[0], r0[RST], r0[2 * RST], r0[3 * RST]), dc);
           ds = mfma32<PREC>(va[k], make_uint4(r0[TW], r0[RST + TW], r0[2 * RST + TW], r0[3 * RST + TW]), ds);
         }
         if (mf_on) {
-          const unsigned o = acc_lane + (unsigned)((s - lag) * B) * Wp;
+          const int cb = cslot_lag + R;   // cos/sin row of output row 0 of the step
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float* cs = s_cs + wrap(cslot_lag + R + mf_r0 + v, CRS) * CST + mf_x;
+            // rows cb + v (lanes 0-15) and cb + 4 + v (lanes 16-31)
+            // (offsets multiplied before the select: readfirstlane keeps the
+            // compiler from moving the multiply after it, onto the lanes)
+            const int oa = __builtin_amdgcn_readfirstlane(wrap(cb + v, CRS) * CST);
+            const int ob = __builtin_amdgcn_readfirstlane(wrap(cb + 4 + v, CRS) * CST);
+            const float* cs = s_cs + mf_x + (mf_r0 ? ob : oa);
             const float q = fmaf(cs[TW], ds[v], cs[0] * dc[v]);
-            buf_store1(acc_rsrc, 4u * (o + v * Wp), fmaf(tw, q, t > 0 ? acur[v] : 0.0f));
+            buf_store1s(acc_rsrc, 4u * acc_lane, 4u * (unsigned)((s - lag) * B + v) * Wp,
+                        fmaf(tw, q, t > 0 ? acur[v] : 0.0f));
           }
         }
       }
