@@ -37,11 +37,11 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "60b45146149d51e269b36ca4675a358b3db7db4f02c4da8969a27b27eff53277",
-    "fetch_factor": 1048576 / 524313.375,
+    "sha256": "76442bea490b4f0ec6209a8ddcc502e4d7d60ff85c050ce663d8edeedf0a6e8e",
+    "fetch_factor": 1048576 / 524313.1875,
     "write_factor": 1048576 / 1048576.0,
-    "fp32": {"fetch_kib": 88312406.375, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},
-    "fp16": {"fetch_kib": 100750744.75, "write_kib": 67108535.5625, "valu_flops": 505198673920.0, "mfma_flops": 20615843020800.0},
+    "fp32": {"fetch_kib": 75691138.625, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},
+    "fp16": {"fetch_kib": 97834029.625, "write_kib": 67108791.4375, "valu_flops": 505198673920.0, "mfma_flops": 20615843020800.0},
 }
 COUNTERS_PROFILE = "profiles/mcsf_fused_voronoi4096_d3_s10_K256.md"
 

@@ -406,6 +406,10 @@ struct Server {
         if (hipStreamEndCapture(streams[kv.first], &g) == hipSuccess && g) (void)hipGraphDestroy(g);
       }
       capturing.clear();
+      // and the round's start events go back to the pool (the round is dropped)
+      for (hipEvent_t& ev : rd.starts) give_tevent(ev);
+      rd.starts.clear();
+      rd.model_us.clear();
     };
     std::map<int, size_t> stream_slot;   // stream -> index into rd.starts / rd.model_us
     std::vector<Req*> ended;
@@ -469,6 +473,7 @@ struct Server {
         const hipError_t q = hipStreamSynchronize(st);
         if (q != hipSuccess) {
           set_fatal(q, "stream drain after a refused launch");
+          abort_captures();
           return true;
         }
         for (const PlanItem& it : L.items) failed.insert(active[it.job]);
