@@ -37,7 +37,7 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "76442bea490b4f0ec6209a8ddcc502e4d7d60ff85c050ce663d8edeedf0a6e8e",
+    "sha256": "b7d51389d15530fad96cc33ae542096bbd3ce838db018bed9172add08fbcd369",
     "fetch_factor": 1048576 / 524313.1875,
     "write_factor": 1048576 / 1048576.0,
     "fp32": {"fetch_kib": 75691138.625, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},

@@ -28,8 +28,10 @@
 // and the taps live in registers; a runtime-R variant serves every other
 // radius.  At the compile-time radii the passes can also run as banded
 // (Toeplitz) matrix products on the matrix cores (MF instances, below): both
-// passes with 16-bit storage, the horizontal pass of 32-column FP32 strips.
-// A VALU instance of every width stays available (bf_opts.valu_only).
+// passes with 16-bit storage; in 32-column FP32 strips the horizontal pass
+// from R = 12 and, from R = 21, both passes in a software pipeline with one
+// barrier per step (PIPE, below).  A VALU instance of every width stays
+// available (bf_opts.valu_only).
 //
 // Low-precision variants (PREC 1 = FP16, 2 = BF16) store the modulated
 // channels and the horizontal-pass rows as 16-bit pairs; their VALU passes
@@ -53,6 +55,11 @@
 // columns to the left.  (Measured on gfx950 this pass is slower than the FIR
 // vertical pass at every radius up to 40, so the library runs box filters as
 // FIR taps unless the running-sum pass is requested.)
+//
+// Variant 4 (FP32, three boxes, d = 3, 32-column strips asked for) runs the
+// vertical pass as three cascaded sliding box sums and the horizontal pass
+// on the matrix cores (described at its loop below).  It too measures slower
+// than the FIR passes at R = 30, so the automatic strip width keeps variant 3.
 
 #include <hip/hip_runtime.h>
 
