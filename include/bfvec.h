@@ -73,8 +73,11 @@ enum { BF_WHITEN_EIG = 0, BF_WHITEN_CHOL = 1, BF_WHITEN_SYM = 2 };
  * window radius R = n r.  Both passes run as FIR passes over these taps.
  * BF_SPATIAL_RUNSUM (or-ed into a box value, BF_FP32 only) runs the vertical
  * pass as exact running sums instead, whose cost does not depend on sigma_s
- * (the paper's O(1) remark); on MI355X it is slower than the FIR pass for
- * every supported window (R <= 40), so it is not the default. */
+ * (the paper's O(1) remark): FP64 running sums in 16-column strips, or, for
+ * BF_SPATIAL_BOX3 at d = 3 with tile_w = 32 at a compile-time radius, three
+ * cascaded sliding box sums with the horizontal pass on the matrix cores.
+ * On MI355X both are slower than the FIR pass for every supported window
+ * (R <= 40), so neither is the default. */
 enum { BF_SPATIAL_GAUSS = 0, BF_SPATIAL_BOX = 1, BF_SPATIAL_HAT = 2, BF_SPATIAL_BOX3 = 3,
        BF_SPATIAL_RUNSUM = 16 };
 
@@ -106,17 +109,19 @@ typedef struct bf_opts {
   int tile_w;      /* strip width in columns: 0 = automatic (default), 16, or
                       32.  32 needs d = 3, a window radius with a compile-time
                       kernel (6, 9, 12, 15, 18, 21, 24 or 30: the Gaussian's
-                      3 sigma_s), BF_FP32/FP16/BF16 without BF_SPATIAL_RUNSUM,
+                      3 sigma_s), BF_FP32/FP16/BF16 (with BF_SPATIAL_RUNSUM:
+                      BF_SPATIAL_BOX3 and a radius that is a multiple of 3),
                       and W >= 32 (else BF_EUNSUPPORTED); automatic picks 32
                       there unless it cuts resident waves per CU below 3/4 or
                       the image is too small to fill the GPU (fewer than two
                       16-column, 8-row strips per compute unit).  At these
                       radii the passes run as banded matrix products on the
                       matrix cores: both with FP16/BF16 storage (either
-                      width), and for FP32 the horizontal one of 32-column
-                      strips from a radius of 12 up, which sums the taps in
-                      another order than 16-column strips: FP32 results there
-                      differ between widths by rounding only.  Otherwise the
+                      width), and for FP32 in 32-column strips the horizontal
+                      one from a radius of 12 up and both from 21 up; these
+                      sum the taps in another order than 16-column strips, so
+                      FP32 results there differ between widths by rounding
+                      only.  Otherwise the
                       width changes no output bit.  bf_vec_ex, plans and the
                       server agree bit for bit at equal width.                */
   int tile_w_used; /* OUT: strip width the fused kernel ran with (16 or 32)   */
