@@ -608,8 +608,8 @@ def write_study(path, rec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="voronoi4096_d3_s10_K256")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="precision of the headline value; the other modes are reported beside it")
@@ -739,7 +739,9 @@ def main():
         flops_run = algorithmic_flops_per_pixel(d, R, K_used) * H * W
         tf = None if spatial != "gauss" else flops_run / (kernel_ms * 1e-3) / 1e12
         rec = {"value": H * W * args.steps / dt / 1e6, "ms_per_step": 1e3 * dt / args.steps,
-               "kernel_ms": kernel_ms, "achieved_tflops": tf,
+               "kernel_ms": kernel_ms, "kernel_ms_median": float(np.median(kms)),
+               "kernel_ms_min": float(np.min(kms)), "kernel_ms_max": float(np.max(kms)),
+               "achieved_tflops": tf,
                "frac_of_fp32_peak": None if tf is None else tf / PEAK_FP32_VALU,
                "N": N, "K_used": K_used, "tile_h": tile_h, "tile_w": tile_w,
                "matrix_core_passes": bool(mf), "spatial": spatial,
