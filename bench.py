@@ -645,6 +645,10 @@ def main():
     ap.add_argument("--realizations", type=int, default=400)
     ap.add_argument("--out", help="with --study: also write the result (and the command line) "
                                   "to this markdown file")
+    ap.add_argument("--ubench", action="store_true",
+                    help="only run the device probes (bf_ubench: matrix, FMA, transcendental, "
+                         "LDS and HBM rates) and print their JSON (with --out: also a markdown "
+                         "table)")
     ap.add_argument("--copy-kernel-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters against known traffic) and exit")
@@ -677,6 +681,33 @@ def main():
             rec["serving_variants"] = serving_variants(args, P, torch, log,
                                                        rec["serving"]["rate_rps"])
         print(json.dumps(rec), flush=True)
+        return
+
+    if args.ubench:
+        rows = []
+        for probe, params, unit in (("mfma_f32", (1, 2, 4, 8), "TFLOP/s"),
+                                    ("mfma_f32_solo", (1, 2, 4), "TFLOP/s"),
+                                    ("mfma_f16", (1, 2, 4, 8), "TFLOP/s"),
+                                    ("valu_f32", (1, 2, 4, 8), "TFLOP/s"),
+                                    ("trans_f32", (0,), "Top/s"),
+                                    ("lds_read", (0,), "TB/s"),
+                                    ("hbm_copy", (1024,), "TB/s")):
+            for q in params:
+                rows.append({"probe": probe, "param": q, "rate": P.bf_ubench(probe, q),
+                             "unit": unit})
+                log(f"{probe} param {q}: {rows[-1]['rate']:.2f} {unit}")
+        rec = {"ubench": rows, "command": "python bench.py " + " ".join(sys.argv[1:])}
+        print(json.dumps(rec), flush=True)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write("# Device probes (bf_ubench), one MI355X\n\n")
+                fh.write(f"Command: `{rec['command']}`\n\n")
+                fh.write("Each probe: one workgroup of 8 waves (two per SIMD) per compute unit, "
+                         "best of three timed launches; param = independent chains per wave "
+                         "(matrix) or per lane (FMA), or the copy size in MiB.\n\n")
+                fh.write("| probe | param | rate | unit |\n|---|---|---|---|\n")
+                for r in rows:
+                    fh.write(f"| {r['probe']} | {r['param']} | {r['rate']:.2f} | {r['unit']} |\n")
         return
 
     if args.copy_kernel_mib:

@@ -458,6 +458,29 @@ double bf_server_clock(const bf_server* srv);
  * scheduler and free the server's device and host memory. */
 int bf_server_destroy(bf_server* srv);
 
+/* ---- Device probes ---------------------------------------------------------
+ * The rates a roofline of the fused kernel is read against, measured on the
+ * current device (not part of the filter).  Each
+ * probe launches one small kernel per repetition on the null stream, one
+ * workgroup of 8 waves (two per SIMD) per compute unit, and reports the best
+ * of three timed launches in *rate:
+ *   BF_UB_MFMA_F32   16x16x4 FP32 matrix products; param independent
+ *                    accumulator chains per wave (1, 2, 4 or 8); TFLOP/s
+ *   BF_UB_MFMA_F16   16x16x32 FP16 matrix products, likewise; TFLOP/s
+ *   BF_UB_VALU_F32   FP32 FMAs (packed FP32 issue is disabled in this build),
+ *                    param chains per lane; TFLOP/s
+ *   BF_UB_TRANS_F32  v_sin_f32, 8 chains per lane; tera-operations/s
+ *   BF_UB_LDS_READ   conflict-free 128-bit LDS reads; TB/s over all CUs
+ *   BF_UB_HBM_COPY   a device copy of param MiB (1..16384), read + write
+ *                    bytes over time; TB/s (allocates 2 param MiB)
+ *   BF_UB_MFMA_F32_SOLO  as BF_UB_MFMA_F32 with one wave per SIMD (4 waves
+ *                    per compute unit): a wave's dependent chain alone
+ * Synchronous.  BF_EINVAL for an unknown probe, a bad param or rate NULL
+ * (before any device work); BF_EDEVICE on a HIP error. */
+enum { BF_UB_MFMA_F32 = 0, BF_UB_MFMA_F16 = 1, BF_UB_VALU_F32 = 2, BF_UB_TRANS_F32 = 3,
+       BF_UB_LDS_READ = 4, BF_UB_HBM_COPY = 5, BF_UB_MFMA_F32_SOLO = 6 };
+int bf_ubench(int probe, int param, double* rate);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* bf_last_error(void);
 

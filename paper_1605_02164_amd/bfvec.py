@@ -54,8 +54,10 @@ EXPORTS = [
     "bf_server_config_init", "bf_request_init", "bf_server_create", "bf_server_submit",
     "bf_server_poll", "bf_server_wait", "bf_server_drain", "bf_server_forget",
     "bf_server_get_stats", "bf_server_clock", "bf_server_destroy",
-    "bf_plan_create", "bf_plan_execute", "bf_plan_destroy", "bf_vec_static",
+    "bf_plan_create", "bf_plan_execute", "bf_plan_destroy", "bf_vec_static", "bf_ubench",
 ]
+UBENCH = {"mfma_f32": 0, "mfma_f16": 1, "valu_f32": 2, "trans_f32": 3, "lds_read": 4,
+          "hbm_copy": 5, "mfma_f32_solo": 6}
 BF_STATIC_SCRATCH_BYTES = 64 << 20
 
 
@@ -208,6 +210,7 @@ def lib():
     L.bf_plan_create.argtypes = [I, I, I, D, P, I, U64, ctypes.POINTER(bf_opts), ctypes.POINTER(P)]
     L.bf_plan_execute.argtypes = [P, P, P, P]
     L.bf_plan_destroy.argtypes = [P]
+    L.bf_ubench.argtypes = [I, I, ctypes.POINTER(D)]
     for name in ("bf_vec", "bf_vec_ex", "bf_vec_static", "bf_vec_terms", "bf_whiten",
                  "bf_whiten_mode",
                  "bf_sample_terms",
@@ -215,7 +218,7 @@ def lib():
                  "bf_server_create",
                  "bf_server_submit", "bf_server_poll", "bf_server_wait", "bf_server_drain",
                  "bf_server_forget", "bf_server_get_stats", "bf_server_destroy",
-                 "bf_plan_create", "bf_plan_execute", "bf_plan_destroy"):
+                 "bf_plan_create", "bf_plan_execute", "bf_plan_destroy", "bf_ubench"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -412,6 +415,16 @@ def bf_direct(f, sigma_s, C, out=None):
     Ch = _host_f64(C, (d, d))
     _check(lib().bf_direct(f.data_ptr(), H, W, d, float(sigma_s), _ptr(Ch), out.data_ptr()))
     return out
+
+
+def bf_ubench(probe, param=0):
+    """A device probe of include/bfvec.h (bf_ubench): probe one of UBENCH's
+    names, param the chains per wave/lane (matrix and FMA probes) or the copy
+    size in MiB.  Returns the rate (TFLOP/s, tera-operations/s or TB/s)."""
+    r = ctypes.c_double(0.0)
+    _check(lib().bf_ubench(UBENCH[probe] if isinstance(probe, str) else int(probe), int(param),
+                           ctypes.byref(r)))
+    return r.value
 
 
 class Plan:

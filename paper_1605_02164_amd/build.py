@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbfvec.so")
 
 SOURCES = ["host.cpp", "server.cpp", "plan.cpp", "api.hip", "mcsf_fused.hip",
-           "mcsf_batch.hip"]
+           "mcsf_batch.hip", "ubench.hip"]
 
 # Packed FP32 VALU instructions are disabled for all device code.
 HIPFLAGS = [

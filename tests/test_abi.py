@@ -311,3 +311,12 @@ def test_valu_only_option_validated():
     rc = B.lib().bf_vec_ex(0x1000, 8, 8, 3, 1.0, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
                            0x100000, ctypes.byref(o))
     assert rc == B.BF_EINVAL and "valu_only" in B.lib().bf_last_error().decode()
+
+
+@pytest.mark.parametrize("probe,param", [(9, 1), (-1, 1), (0, 3), (1, 0), (2, 16), (5, 0),
+                                         (5, 20000), (6, 3)])
+def test_ubench_arguments_refused_before_device_work(probe, param):
+    r = ctypes.c_double(1.0)
+    assert B.lib().bf_ubench(probe, param, ctypes.byref(r)) == B.BF_EINVAL
+    assert r.value == 0.0 and "bf_ubench" in B.lib().bf_last_error().decode()
+    assert B.lib().bf_ubench(0, 1, None) == B.BF_EINVAL
