@@ -691,7 +691,9 @@ def main():
                                     ("valu_f32", (1, 2, 4, 8), "TFLOP/s"),
                                     ("trans_f32", (0,), "Top/s"),
                                     ("lds_read", (0,), "TB/s"),
-                                    ("hbm_copy", (1024,), "TB/s")):
+                                    ("hbm_copy", (1024,), "TB/s"),
+                                    ("overlap_f32", (0,), "fraction"),
+                                    ("overlap_f16", (0,), "fraction")):
             for q in params:
                 rows.append({"probe": probe, "param": q, "rate": P.bf_ubench(probe, q),
                              "unit": unit})
@@ -704,7 +706,10 @@ def main():
                 fh.write(f"Command: `{rec['command']}`\n\n")
                 fh.write("Each probe: one workgroup of 8 waves (two per SIMD) per compute unit, "
                          "best of three timed launches; param = independent chains per wave "
-                         "(matrix) or per lane (FMA), or the copy size in MiB.\n\n")
+                         "(matrix) or per lane (FMA), or the copy size in MiB. overlap_*: one "
+                         "wave per SIMD runs matrix products, the other FMAs of about the same "
+                         "duration; (t_matrix + t_fma - t_both) / min(t_matrix, t_fma), 1 when "
+                         "they run side by side, 0 when their times add.\n\n")
                 fh.write("| probe | param | rate | unit |\n|---|---|---|---|\n")
                 for r in rows:
                     fh.write(f"| {r['probe']} | {r['param']} | {r['rate']:.2f} | {r['unit']} |\n")

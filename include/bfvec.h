@@ -475,10 +475,18 @@ int bf_server_destroy(bf_server* srv);
  *                    bytes over time; TB/s (allocates 2 param MiB)
  *   BF_UB_MFMA_F32_SOLO  as BF_UB_MFMA_F32 with one wave per SIMD (4 waves
  *                    per compute unit): a wave's dependent chain alone
+ *   BF_UB_OVERLAP_F32  overlap of matrix and vector work on one SIMD: one
+ *                    wave runs two chains of 16x16x4 FP32 products, the
+ *                    other wave of the SIMD FP32 FMAs of about the same
+ *                    duration; *rate = (t_matrix + t_fma - t_both) /
+ *                    min(t_matrix, t_fma): 1 when they run side by side, 0
+ *                    when their times add (param ignored, pass 0)
+ *   BF_UB_OVERLAP_F16  the same with 16x16x32 FP16 products
  * Synchronous.  BF_EINVAL for an unknown probe, a bad param or rate NULL
  * (before any device work); BF_EDEVICE on a HIP error. */
 enum { BF_UB_MFMA_F32 = 0, BF_UB_MFMA_F16 = 1, BF_UB_VALU_F32 = 2, BF_UB_TRANS_F32 = 3,
-       BF_UB_LDS_READ = 4, BF_UB_HBM_COPY = 5, BF_UB_MFMA_F32_SOLO = 6 };
+       BF_UB_LDS_READ = 4, BF_UB_HBM_COPY = 5, BF_UB_MFMA_F32_SOLO = 6,
+       BF_UB_OVERLAP_F32 = 7, BF_UB_OVERLAP_F16 = 8 };
 int bf_ubench(int probe, int param, double* rate);
 
 /* Message for the last failing call on this thread ("" if none). */

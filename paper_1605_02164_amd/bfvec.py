@@ -57,7 +57,7 @@ EXPORTS = [
     "bf_plan_create", "bf_plan_execute", "bf_plan_destroy", "bf_vec_static", "bf_ubench",
 ]
 UBENCH = {"mfma_f32": 0, "mfma_f16": 1, "valu_f32": 2, "trans_f32": 3, "lds_read": 4,
-          "hbm_copy": 5, "mfma_f32_solo": 6}
+          "hbm_copy": 5, "mfma_f32_solo": 6, "overlap_f32": 7, "overlap_f16": 8}
 BF_STATIC_SCRATCH_BYTES = 64 << 20
 
 

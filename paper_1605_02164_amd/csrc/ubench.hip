@@ -111,6 +111,48 @@ __global__ __launch_bounds__(kThreads) void ub_lds_read(float* out, int iters) {
   out[blockIdx.x * kThreads + threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
 }
 
+// Matrix and vector work side by side: waves 0-3 (one per SIMD) run two
+// chains of FP32 (F16 = false) or FP16 matrix products when WHAT & 1, waves
+// 4-7 eight chains of FP32 FMAs when WHAT & 2.
+template <bool F16, int WHAT>
+__global__ __launch_bounds__(kThreads) void ub_mix(float* out, int iters, int fma_iters) {
+  const int w = threadIdx.x >> 6;
+  float s = 0.0f;
+  if (w < 4 && (WHAT & 1)) {
+    f32x4_t acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = acc0;
+    if constexpr (F16) {
+      f16x8_t a, b;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        a[k] = (_Float16)(1.0f + k * 1e-3f);
+        b[k] = (_Float16)(1e-3f * (threadIdx.x & 7));
+      }
+      for (int i = 0; i < iters; ++i) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc1, 0, 0, 0);
+      }
+    } else {
+      const float a = 1.0f + threadIdx.x * 1e-7f, b = 1e-3f;
+      for (int i = 0; i < iters; ++i) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1, 0, 0, 0);
+      }
+    }
+    s = acc0[0] + acc1[3];
+  } else if (w >= 4 && (WHAT & 2)) {
+    float x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = 1.0f + (threadIdx.x + c) * 1e-7f;
+    for (int i = 0; i < fma_iters; ++i) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) x[c] = fmaf(x[c], 0.999999f, 1e-7f);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s += x[c];
+  }
+  out[blockIdx.x * kThreads + threadIdx.x] = s;
+}
+
 // Grid-stride copy of n float4.
 __global__ __launch_bounds__(256) void ub_copy(const float4* __restrict__ src,
                                                float4* __restrict__ dst, size_t n) {
@@ -164,11 +206,13 @@ extern "C" int bf_ubench(int probe, int param, double* rate) {
   *rate = 0.0;
   const bool chains = probe == BF_UB_MFMA_F32 || probe == BF_UB_MFMA_F16 ||
                       probe == BF_UB_VALU_F32 || probe == BF_UB_MFMA_F32_SOLO;
+  const bool overlap = probe == BF_UB_OVERLAP_F32 || probe == BF_UB_OVERLAP_F16;
   if (chains && param != 1 && param != 2 && param != 4 && param != 8)
     return fail(BF_EINVAL, "bf_ubench: chains must be 1, 2, 4 or 8");
   if (probe == BF_UB_HBM_COPY && (param < 1 || param > 16384))
     return fail(BF_EINVAL, "bf_ubench: copy size must be 1..16384 MiB");
-  if (probe < BF_UB_MFMA_F32 || probe > BF_UB_MFMA_F32_SOLO)
+  if (overlap && param != 0) return fail(BF_EINVAL, "bf_ubench: overlap probes take param 0");
+  if (probe < BF_UB_MFMA_F32 || probe > BF_UB_OVERLAP_F16)
     return fail(BF_EINVAL, "bf_ubench: unknown probe");
   const int ncu = cu_count();
   if (ncu <= 0) return fail(BF_EDEVICE, "bf_ubench: no device");
@@ -215,6 +259,26 @@ extern "C" int bf_ubench(int probe, int param, double* rate) {
     rc = best_ms([&] { ub_valu_f32<c><<<ncu, kThreads>>>(out, iters * 8); }, &ms);
     work = waves * 64.0 * iters * 8 * c * 2.0;
   };
+  if (overlap) {
+    // durations chosen so that each side alone takes about the same time
+    // (one wave per SIMD: ~36 cycles per FP32 product pair member, ~9 per
+    // FMA instruction; FP16 products are 4x shorter)
+    const bool f16 = probe == BF_UB_OVERLAP_F16;
+    const int mi = f16 ? 16000 : 4000, fi = 4000;
+    float tm = 0.0f, tf = 0.0f, tb = 0.0f;
+    if (f16) {
+      rc = best_ms([&] { ub_mix<true, 1><<<ncu, kThreads>>>(out, mi, fi); }, &tm);
+      if (rc == BF_OK) rc = best_ms([&] { ub_mix<true, 2><<<ncu, kThreads>>>(out, mi, fi); }, &tf);
+      if (rc == BF_OK) rc = best_ms([&] { ub_mix<true, 3><<<ncu, kThreads>>>(out, mi, fi); }, &tb);
+    } else {
+      rc = best_ms([&] { ub_mix<false, 1><<<ncu, kThreads>>>(out, mi, fi); }, &tm);
+      if (rc == BF_OK) rc = best_ms([&] { ub_mix<false, 2><<<ncu, kThreads>>>(out, mi, fi); }, &tf);
+      if (rc == BF_OK) rc = best_ms([&] { ub_mix<false, 3><<<ncu, kThreads>>>(out, mi, fi); }, &tb);
+    }
+    (void)hipFree(out);
+    if (rc == BF_OK) *rate = (tm + tf - tb) / std::min(tm, tf);
+    return rc;
+  }
   switch (probe) {
     case BF_UB_MFMA_F32:
     case BF_UB_MFMA_F32_SOLO:

@@ -314,7 +314,7 @@ def test_valu_only_option_validated():
 
 
 @pytest.mark.parametrize("probe,param", [(9, 1), (-1, 1), (0, 3), (1, 0), (2, 16), (5, 0),
-                                         (5, 20000), (6, 3)])
+                                         (5, 20000), (6, 3), (7, 1), (8, 2), (10, 0)])
 def test_ubench_arguments_refused_before_device_work(probe, param):
     r = ctypes.c_double(1.0)
     assert B.lib().bf_ubench(probe, param, ctypes.byref(r)) == B.BF_EINVAL
