@@ -123,7 +123,7 @@ def cpu_baseline(f, C, sigma_s, K, seed, N, gpu_outs=None, crop=1024, direct_cro
     from threadpoolctl import threadpool_limits
     from oracle import mcsf as O
     model, nproc, usable = _cpu_info()
-    workers = max(1, min(16, usable))   # the machine's CPU share for one GPU
+    workers = max(1, min(16, usable))   # at most 16 host threads per GPU
     H, W, d = f.shape
     f64 = f.astype(np.float64)
     Wm = O.whiten(C)
