@@ -615,7 +615,8 @@ def main():
                     help="precision of the headline value; the other modes are reported beside it")
     ap.add_argument("--only", action="store_true", help="time only --precision")
     ap.add_argument("--modes", help="comma-separated modes to time instead of the default set "
-                                    "(fp32, fp16, bf16, *_valu, *_dedup, fp32_box3, fp32_box3rs, fp32_box3sl; "
+                                    "(fp32, fp16, bf16, fp32_split, *_valu, *_dedup, fp32_box3, "
+                                    "fp32_box3rs, fp32_box3sl; "
                                     "a _w16 suffix forces 16-column strips); "
                                     "the first is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -745,7 +746,9 @@ def main():
     tuned = {}
 
     def run(mode, dst):
-        prec, dedup = mode.split("_")[0], mode.endswith("_dedup")
+        # fp32_split: FP32 with the vertical pass on FP16 hi + lo pairs
+        prec = "fp32_split" if mode.startswith("fp32_split") else mode.split("_")[0]
+        dedup = mode.endswith("_dedup")
         tile_w = 16 if mode.endswith("_w16") else 0
         base = mode[:-4] if tile_w else mode
         # box3: FIR passes over the three-box taps; box3rs: FP64 running sums
@@ -790,8 +793,8 @@ def main():
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
         [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + \
-        ["fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3", "fp32_box3rs",
-         "fp32_box3sl"]
+        ["fp32_split", "fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3",
+         "fp32_box3rs", "fp32_box3sl"]
     if args.modes:
         precs = args.modes.split(",")
         args.precision = precs[0].split("_")[0]

@@ -54,8 +54,18 @@ enum {
 };
 
 /* Storage type of the modulated channels and of the horizontal-pass
- * intermediates.  Accumulation of both passes and of num/Z is FP32 always. */
-enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2 };
+ * intermediates.  Accumulation of both passes and of num/Z is FP32 always.
+ * BF_FP32_SPLIT: FP32 channels and horizontal pass, with the horizontal-pass
+ * rows kept as FP16 pairs hi + lo (about 22 significant bits; hi = the value
+ * rounded to FP16, lo = the remainder rounded) and the vertical pass as exact
+ * FP16 products hi.hi + lo.hi + hi.lo on the matrix cores, so that it leaves
+ * the FP32 datapath the horizontal pass and the modulation use.  Errors
+ * against the FP64 reference measure the same as BF_FP32's.  Exists for
+ * d = 3, window radius 21, 24 or 30 (the Gaussian's sigma_s 7, 8, 10) and
+ * W >= 32 (else BF_EUNSUPPORTED), not with valu_only, plans or the server;
+ * its FP16 halves need the FP16 range rule of BF_FP16.  (3 and 4 are not
+ * precisions.) */
+enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2, BF_FP32_SPLIT = 5 };
 
 /* Whitening W with W^T W = C^{-1} (eq. (COB) fixes W only up to that): the
  * eigen-decomposition of eq. (COB) (default, see bf_whiten), W = L^{-1} with
@@ -83,7 +93,7 @@ enum { BF_SPATIAL_GAUSS = 0, BF_SPATIAL_BOX = 1, BF_SPATIAL_HAT = 2, BF_SPATIAL_
 
 typedef struct bf_opts {
   int N;           /* raised-cosine order (eq. (approx)); 0 = automatic rule  */
-  int precision;   /* BF_FP32 (default), BF_FP16, BF_BF16                      */
+  int precision;   /* BF_FP32 (default), BF_FP16, BF_BF16, BF_FP32_SPLIT       */
   int center;      /* 1 (default): phase taken on f - c with c the per-channel
                       midpoint (exact in arithmetic: the filter commutes with
                       constant shifts); 0: phase on f itself                   */

@@ -20,8 +20,8 @@ BF_OK, BF_EINVAL, BF_ENOTSPD, BF_ENOMEM, BF_EDEVICE, BF_EUNSUPPORTED, BF_EBUSY, 
  BF_REQ_CANCELLED) = range(6)
 REQ_STATES = {BF_REQ_QUEUED: "queued", BF_REQ_PREPARING: "preparing", BF_REQ_RUNNING: "running",
               BF_REQ_DONE: "done", BF_REQ_FAILED: "failed", BF_REQ_CANCELLED: "cancelled"}
-BF_FP32, BF_FP16, BF_BF16 = 0, 1, 2
-PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16}
+BF_FP32, BF_FP16, BF_BF16, BF_FP32_SPLIT = 0, 1, 2, 5
+PRECISIONS = {"fp32": BF_FP32, "fp16": BF_FP16, "bf16": BF_BF16, "fp32_split": BF_FP32_SPLIT}
 BF_SPATIAL_GAUSS, BF_SPATIAL_BOX, BF_SPATIAL_HAT, BF_SPATIAL_BOX3 = 0, 1, 2, 3
 BF_SPATIAL_RUNSUM = 16
 BF_WHITEN_EIG, BF_WHITEN_CHOL, BF_WHITEN_SYM = 0, 1, 2

@@ -152,8 +152,9 @@ namespace {
 
 int check_opts(const bf_opts* o) {
   if (o->N < 0 || o->N > 65536) return fail(BF_EINVAL, "opts.N must be 0 (auto) or in [1, 65536]");
-  if (o->precision != BF_FP32 && o->precision != BF_FP16 && o->precision != BF_BF16)
-    return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16 or BF_BF16");
+  if (o->precision != BF_FP32 && o->precision != BF_FP16 && o->precision != BF_BF16 &&
+      o->precision != BF_FP32_SPLIT)
+    return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16, BF_BF16 or BF_FP32_SPLIT");
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->tile_w != 0 && o->tile_w != kTW && o->tile_w != kTWMax)
@@ -162,6 +163,8 @@ int check_opts(const bf_opts* o) {
   if (o->whiten < BF_WHITEN_EIG || o->whiten > BF_WHITEN_SYM)
     return fail(BF_EINVAL, "opts.whiten must be BF_WHITEN_EIG, _CHOL or _SYM");
   if (o->valu_only != 0 && o->valu_only != 1) return fail(BF_EINVAL, "opts.valu_only must be 0 or 1");
+  if (o->precision == BF_FP32_SPLIT && o->valu_only)
+    return fail(BF_EUNSUPPORTED, "BF_FP32_SPLIT runs its passes on the matrix cores (valu_only = 0)");
   return check_spatial(o->spatial, o->precision);
 }
 
@@ -346,7 +349,7 @@ int run_terms(const float* f, int H, int W, int d, double sigma_s, const double*
   a.valu = o->valu_only;
   int rc = check_acc_size(a, d);
   if (rc) return rc;
-  if (o->precision == BF_FP16) {
+  if (o->precision == BF_FP16 || o->precision == BF_FP32_SPLIT) {
     if (!lo) return fail(BF_EINVAL, "FP16 storage needs the image range (internal)");
     if ((rc = check_fp16_range(d, sigma_s, spatial_boxes(o->spatial), lo, hi, a.cen))) return rc;
   }
@@ -531,7 +534,8 @@ int bf_vec_static(const float* f, int H, int W, int d, double sigma_s, const dou
   float* work = nullptr;
   if ((rc = scratch_for_current_device(&work))) return rc;
   float lo[8] = {0}, hi[8] = {0};
-  const bool have_range = o->N == 0 || o->center || o->precision == BF_FP16;
+  const bool have_range = o->N == 0 || o->center || o->precision == BF_FP16 ||
+                          o->precision == BF_FP32_SPLIT;
   if (have_range && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream, work))) return rc;
   int N = o->N;
   if (N == 0 && (rc = choose_order(d, Wm, lo, hi, &N))) return rc;
@@ -569,7 +573,8 @@ int bf_vec_ex(const float* f, int H, int W, int d, double sigma_s, const double*
   if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
   float lo[8] = {0}, hi[8] = {0};
   // the order rule, centring and the FP16 range check need the extrema
-  const bool have_range = o->N == 0 || o->center || o->precision == BF_FP16;
+  const bool have_range = o->N == 0 || o->center || o->precision == BF_FP16 ||
+                          o->precision == BF_FP32_SPLIT;
   if (have_range) {
     if ((rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   }
@@ -623,7 +628,8 @@ int bf_vec_terms(const float* f, int H, int W, int d, double sigma_s, const doub
   int TH = 0, TW = 0;
   if ((rc = plan_fused(H, W, d, sigma_s, o, &TH, &TW))) return rc;
   float lo[8] = {0}, hi[8] = {0};
-  const bool have_range = o->center || o->precision == BF_FP16;
+  const bool have_range = o->center || o->precision == BF_FP16 ||
+                          o->precision == BF_FP32_SPLIT;
   if (have_range && (rc = run_minmax(f, H, W, d, lo, hi, (hipStream_t)o->stream))) return rc;
   o->N_used = o->N;
   o->K_used = K;
@@ -637,8 +643,9 @@ int bf_autotune(const float* f, int H, int W, int d, double sigma_s, int precisi
   // f is read only; a distinct dummy output pointer passes the common checks
   int rc = check_common(f, H, W, d, sigma_s, (const char*)f + (size_t)H * W * d * sizeof(float));
   if (rc) return rc;
-  if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
-    return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
+  if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16 &&
+      precision != BF_FP32_SPLIT)
+    return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16, BF_BF16 or BF_FP32_SPLIT");
   return autotune_strip_height(f, H, W, W, d, sigma_s, precision, (hipStream_t)stream, tile_h,
                                ms_per_term);
 }

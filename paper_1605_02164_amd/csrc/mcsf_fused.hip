@@ -64,7 +64,8 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
                         (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
                             : (mf ? stage_width_mf32(R) : stage_width(R, TW))) +
                     (size_t)(lp ? RS / 2 : RS) *
-                        (NC * TW + (mf && lp ? kRingPadMF : 0) + (pipe ? kRingPadPipe : 0)) +
+                        (NC * TW + ((mf && lp) || prec == 5 ? kRingPadMF : 0) +
+                         (pipe && prec != 5 ? kRingPadPipe : 0)) +
                     (size_t)CRS * CST +
                     (vb ? (size_t)16 * NC * TW : 0);
   return fl * sizeof(float);
@@ -154,8 +155,29 @@ static int blocks_per_cu_sl() {
   return std::max(1, std::min(by_vgpr, by_lds));
 }
 
+// variant 5: one 8-wave workgroup per CU by its LDS (checked against the
+// instance's registers)
+template <int RC>
+static int blocks_per_cu_sp() {
+  hipFuncAttributes at{};
+  int vgpr = 256;
+  if (hipFuncGetAttributes(&at, reinterpret_cast<const void*>(
+                                    mcsf_fused<3, RC, 5, false, kTWMax, true>)) == hipSuccess &&
+      at.numRegs > 0)
+    vgpr = at.numRegs;
+  const int by_vgpr = std::min(8, 512 / ((vgpr + 7) / 8 * 8)) / 2;
+  const int by_lds = (int)((160 * 1024) / fused_lds_bytes(3, RC, 5, kTWMax, 1));
+  return std::max(1, std::min(by_vgpr, by_lds));
+}
+
 int fused_blocks_per_cu(int d, int R, int prec, int TW, int valu) {
   switch (prec) {
+    case 5:
+      switch (R) {
+        case 21: return blocks_per_cu_sp<21>();
+        case 24: return blocks_per_cu_sp<24>();
+        default: return blocks_per_cu_sp<30>();
+      }
     case 0: return bpc_p<0>(d, R, TW, valu);
     case 1: return bpc_p<1>(d, R, TW, valu);
     case 2: return bpc_p<2>(d, R, TW, valu);
@@ -186,7 +208,7 @@ int select_variant(int d, int R, int precision, int spatial, int W, int tile_w, 
 }
 
 int fused_uses_mf(int d, int R, int prec, int TW, int valu) {
-  if (prec == 4) return 1;   // its horizontal pass
+  if (prec == 4 || prec == 5) return 1;   // variant 4: its horizontal pass; 5: both
   if (valu || !specialised_radius(R) || (d != 3 && d != 6) || prec > 2) return 0;
   const bool inst = TW == kTWMax ? d == 3 : (prec == 1 || prec == 2);
   return inst && use_mf(TW, prec, R) ? 1 : 0;
@@ -198,6 +220,14 @@ int strip_row_multiple(int d, int R, int prec, int TW, int valu) {
 
 int choose_strip_width(int d, int R, int prec, int H, int W, int requested, int* TW) {
   if (prec == 4) {   // select_variant guarantees the instance
+    *TW = kTWMax;
+    return BF_OK;
+  }
+  if (prec == 5) {
+    if (d != 3 || !split_radius(R) || W < kTWMax || requested == kTW)
+      return fail(BF_EUNSUPPORTED,
+                  "BF_FP32_SPLIT needs d = 3, a window radius of 21, 24 or 30 (sigma_s 7, 8 or "
+                  "10 for the Gaussian), W >= 32 and 32-column strips");
     *TW = kTWMax;
     return BF_OK;
   }
@@ -340,6 +370,7 @@ hipError_t launch_fused(int d, int prec, const FusedArgs& a, hipStream_t st) {
     case 2: return launch_p<2>(d, a, a.R, st);
     case 3: return launch_p<3>(d, a, a.R, st);
     case 4: return d == 3 ? launch_sl_r(a, a.R, st) : hipErrorInvalidValue;
+    case 5: return d == 3 ? launch_sp_r(a, a.R, st) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

@@ -152,6 +152,16 @@ __device__ __forceinline__ unsigned pack2(float lo, float hi) {
 }
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+// x as an FP16 pair hi + lo: hi = x rounded to FP16, lo = the remainder
+// x - hi rounded to FP16 (exact in FP32), so hi + lo carries about 22
+// significant bits (fewer where lo is subnormal, |x| < 2^-3: an absolute
+// error below 2^-25 there).
+__device__ __forceinline__ void split16(float x, unsigned short& h, unsigned short& l) {
+  const _Float16 hh = (_Float16)x;
+  const _Float16 ll = (_Float16)(x - (float)hh);
+  h = __builtin_bit_cast(unsigned short, hh);
+  l = __builtin_bit_cast(unsigned short, ll);
+}
 // 16x16x4 FP32 product: lane l holds a[l%16][l/16], b[l/16][l%16] and d as
 // above.
 __device__ __forceinline__ f32x4_t mfma4(float a, float b, f32x4_t d) {
@@ -385,11 +395,13 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 // strips).
 template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
-  static_assert(PREC >= 0 && PREC <= 4, "kernel variant");
+  static_assert(PREC >= 0 && PREC <= 5, "kernel variant");
+  static_assert(PREC != 5 || (TW == 32 && MF && D == 3 && RC >= 21),
+                "split vertical pass: pipelined 32-column FP32 instances");
   static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
   static_assert(PREC != 4 || (TW == 32 && MF && D == 3 && RC >= 0 && RC % 3 == 0),
                 "sliding three-box vertical pass: 32-column matrix-core instances");
-  static_assert(!MF || (RC >= 0 && (TW == 32 ? D == 3 && (PREC <= 2 || PREC == 4)
+  static_assert(!MF || (RC >= 0 && (TW == 32 ? D == 3 && (PREC <= 2 || PREC == 4 || PREC == 5)
                                              : PREC == 1 || PREC == 2)),
                 "matrix-core passes");
   using G = Geo<D, TW>;
@@ -404,7 +416,12 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // an operand read of the vertical pass touches 4 consecutive rows x 16
   // columns, which a stride of 16 mod 32 floats spreads over the LDS banks.
   constexpr bool PIPE = use_pipe(PREC, RC, MF);
-  constexpr int RST = NC * TW + (MFV ? kRingPadMF : 0) + (PIPE ? kRingPadPipe : 0);   // ring row stride: [ch][x]
+  // Variant 5: the ring holds the horizontal-pass rows as FP16 pairs hi + lo
+  // in two planes of pair-rows (two rows' halves in one dword, as the 16-bit
+  // instances store them), and the vertical pass runs on FP16 products.
+  constexpr bool SPV = PREC == 5;
+  constexpr int RST = NC * TW + (MFV || SPV ? kRingPadMF : 0) +
+                      (PIPE && !SPV ? kRingPadPipe : 0);   // ring row stride: [ch][x]
   constexpr int CST = 2 * TW + cs_row_pad(PIPE || (MFV && TW == 32));   // cos/sin ring row: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
   constexpr bool VB = PREC == 3;                 // running-sum vertical pass
@@ -534,6 +551,28 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     }
   }
 
+  // Variant 5: tap operands of the vertical FP16 products, as hi and lo
+  // halves: A[r][k] = w[32s + k - r] for the pair's 16 output rows r and the
+  // 32 window rows k of k-block s (KBS blocks cover the 16 + 2R rows); this
+  // lane holds row r = l%16, k = 8(l/16) .. +7.
+  constexpr int KBS = SPV ? (16 + 2 * RC + 31) / 32 : 1;
+  uint4 vah[KBS], val[KBS];
+  if constexpr (SPV) {
+    const int ln = tid & 63;
+    auto tap = [&](int u, bool lo) -> unsigned {
+      unsigned short h, l;
+      split16(u >= 0 && u <= 2 * RC ? s_taps[u] : 0.0f, h, l);
+      return lo ? l : h;
+    };
+#pragma unroll
+    for (int s = 0; s < KBS; ++s) {
+      const int u = 32 * s + 8 * (ln >> 4) - (ln & 15);
+      vah[s] = make_uint4(tap(u, false) | tap(u + 1, false) << 16, tap(u + 2, false) | tap(u + 3, false) << 16,
+                          tap(u + 4, false) | tap(u + 5, false) << 16, tap(u + 6, false) | tap(u + 7, false) << 16);
+      val[s] = make_uint4(tap(u, true) | tap(u + 1, true) << 16, tap(u + 2, true) | tap(u + 3, true) << 16,
+                          tap(u + 4, true) | tap(u + 5, true) << 16, tap(u + 6, true) | tap(u + 7, true) << 16);
+    }
+  }
   // ---- per-thread fixed roles -------------------------------------------------
   // pass 1 item: 4-column block xq, channel ch, row rr of the step.  xq varies
   // fastest across lanes: the items' 128-bit ring writes then cover contiguous
@@ -769,9 +808,22 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   auto hmf_store = [&](const f32x4_t& d, int r0) {
     const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
     const int g = ln >> 4, row = 2 * mb + (g & 1);
+    if constexpr (SPV) {
+      // row r0 + row is half (g & 1) of pair-row r0/2 + mb (r0 is a multiple
+      // of 8); the lo plane follows the hi plane's RS/2 pair-rows
+      const int i0 = 2 * ((r0 / 2 + mb) * RST + (g >> 1) * TW + 16 * nb + (ln & 15)) + (g & 1);
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      s_ring[(r0 + row) * RST + (2 * v + (g >> 1)) * TW + 16 * nb + (ln & 15)] = d[v];
+      for (int v = 0; v < 4; ++v) {
+        unsigned short h, l;
+        split16(d[v], h, l);
+        s_ring16[i0 + 4 * v * TW] = h;
+        s_ring16[i0 + 4 * v * TW + RS * RST] = l;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        s_ring[(r0 + row) * RST + (2 * v + (g >> 1)) * TW + 16 * nb + (ln & 15)] = d[v];
+    }
   };
 
   // ---- FP32 matrix-core vertical pass of a pair of steps (PIPE instances) --
@@ -805,11 +857,39 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     // (rl is a multiple of 8, the ring of 8), so only the uniform part wraps
     const float* cc = s_ring + ((ln >> 4) * RST + (2 * m) * TW + col);
     f32x4_t dc = {0.0f, 0.0f, 0.0f, 0.0f}, ds = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (SPV) {
+      // KBS k-blocks of 32 window rows (16 pair-rows); lane group l/16
+      // reads pair-rows 4(l/16) .. +3 of a block, which never straddle the
+      // wrap (rl/2 and RS/2 are multiples of 4).  Window rows past 16 + 2R
+      // meet zero taps: at R = 30 the last block reaches the rows of the
+      // step being stored and, past the ring's end, the window's first
+      // rows again (finite values either way).
+      (void)cc;
+      const unsigned* hp = s_ring32 + (2 * m) * TW + col;
+      const unsigned* lp = hp + (RS / 2) * RST;
 #pragma unroll
-    for (int k = 0; k < KS4; ++k) {
-      const int row = wrap(rl + 4 * k, RS);
-      dc = mfma4(hb4[k], cc[row * RST], dc);
-      ds = mfma4(hb4[k], cc[row * RST + TW], ds);
+      for (int kb = 0; kb < KBS; ++kb) {
+        const int pb = wrap(rl / 2 + 16 * kb + 4 * (ln >> 4), RS / 2) * RST;
+        const uint4 hc = make_uint4(hp[pb], hp[pb + RST], hp[pb + 2 * RST], hp[pb + 3 * RST]);
+        const uint4 lc = make_uint4(lp[pb], lp[pb + RST], lp[pb + 2 * RST], lp[pb + 3 * RST]);
+        const uint4 hs = make_uint4(hp[pb + TW], hp[pb + RST + TW], hp[pb + 2 * RST + TW],
+                                    hp[pb + 3 * RST + TW]);
+        const uint4 ls = make_uint4(lp[pb + TW], lp[pb + RST + TW], lp[pb + 2 * RST + TW],
+                                    lp[pb + 3 * RST + TW]);
+        dc = mfma32<1>(vah[kb], hc, dc);
+        ds = mfma32<1>(vah[kb], hs, ds);
+        dc = mfma32<1>(vah[kb], lc, dc);
+        ds = mfma32<1>(vah[kb], ls, ds);
+        dc = mfma32<1>(val[kb], hc, dc);
+        ds = mfma32<1>(val[kb], hs, ds);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KS4; ++k) {
+        const int row = wrap(rl + 4 * k, RS);
+        dc = mfma4(hb4[k], cc[row * RST], dc);
+        ds = mfma4(hb4[k], cc[row * RST + TW], ds);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1474,6 +1554,40 @@ static hipError_t launch_sl_r(const A& a, int R, hipStream_t st) {
     case 24: return launch_sl<24>(a, st);
     case 30: return launch_sl<30>(a, st);
     default: return hipErrorInvalidValue;
+  }
+}
+
+// Variant 5 (split vertical pass): the pipelined 32-column instances at
+// R = 21, 24 and 30; single requests only.
+template <int RC>
+static hipError_t launch_sp(const FusedArgs& a, hipStream_t st) {
+  if (a.TWc != kTWMax || a.valu || a.TH % (2 * kB)) return hipErrorInvalidValue;
+  void (*kern)(FusedArgs) =
+      a.p64 ? mcsf_fused<3, RC, 5, true, kTWMax, true> : mcsf_fused<3, RC, 5, false, kTWMax, true>;
+  const size_t lds = fused_lds_bytes(3, RC, 5, kTWMax, 1);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int nwg = a.nsx * a.nsy;
+  if (nwg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(64 * 4 * 2), lds, st, a);
+  return hipGetLastError();
+}
+
+template <class A>
+static hipError_t launch_sp_r(const A& a, int R, hipStream_t st) {
+  if constexpr (std::is_same_v<A, BatchArgs>) {
+    (void)a;
+    (void)R;
+    (void)st;
+    return hipErrorInvalidValue;
+  } else {
+    switch (R) {
+      case 21: return launch_sp<21>(a, st);
+      case 24: return launch_sp<24>(a, st);
+      case 30: return launch_sp<30>(a, st);
+      default: return hipErrorInvalidValue;
+    }
   }
 }
 

@@ -157,6 +157,28 @@ def test_invalid_options_rejected():
     assert rc == B.BF_EINVAL
 
 
+@pytest.mark.parametrize("kw", [
+    dict(sigma=2.0),                      # R = 6: no split instance
+    dict(sigma=5.0),                      # R = 15
+    dict(d=6, C=np.eye(6) * 0.01),        # d = 6
+    dict(W=24),                           # narrower than a 32-column strip
+    dict(tile_w=16),
+    dict(valu_only=True),
+])
+def test_split_precision_refused_before_device_work(kw):
+    # BF_FP32_SPLIT runs only the pipelined d = 3 instances at R = 21, 24, 30
+    d = kw.pop("d", 3)
+    C = kw.pop("C", np.eye(3) * 0.01)
+    sigma = kw.pop("sigma", 10.0)
+    W = kw.pop("W", 64)
+    o = B.make_opts(precision="fp32_split", **kw)
+    Ch = np.ascontiguousarray(C, dtype=np.float64)
+    rc = B.lib().bf_vec_ex(0x1000, 64, W, d, sigma, Ch.ctypes.data_as(ctypes.c_void_p), 4, 1,
+                           0x4000000, ctypes.byref(o))
+    assert rc == B.BF_EUNSUPPORTED, B.lib().bf_last_error().decode()
+    assert "SPLIT" in B.lib().bf_last_error().decode()
+
+
 def test_term_table_validation():
     w = np.array([[1.0, float("inf"), 0.0]])
     rc = B.lib().bf_vec_terms(0x1000, 4, 4, 3, 1.0, w.ctypes.data_as(ctypes.c_void_p), None, 1,
@@ -206,6 +228,7 @@ def test_plan_validation_before_device_work():
     assert create(sigma=float("nan")) == B.BF_EINVAL
     assert create(Cp=None) == B.BF_EINVAL
     assert create(precision=7) == B.BF_EINVAL
+    assert create(precision="fp32_split", sigma=10.0, H=64, W=64) == B.BF_EINVAL   # not in plans
     assert create(time_kernel=True) == B.BF_EINVAL
     bad = np.array([[1.0, 2, 0], [2, 1, 0], [0, 0, 1]])
     assert create(Cp=bad.ctypes.data_as(ctypes.c_void_p)) == B.BF_ENOTSPD
