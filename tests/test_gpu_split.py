@@ -15,7 +15,10 @@ held to the FP32 bounds of the other parity tests:
   strip seams, against O2 (the direct filter with the same terms);
 * strip heights change no output bit (the pair's k-blocks are fixed relative
   to the pair), and the result stays within 1e-5 of the range of plain FP32;
-* the FP16 range rule of BF_FP16 applies to the FP16 halves.
+* the FP16 range rule of BF_FP16 applies to the FP16 halves;
+* phases beyond 2^8 turns (uncentred data near 100) take the instance with
+  the FP64 phase reduction; there the halves' rounding (2^-22 of |f|) grows
+  relative to the range by max|f| / range, and the bound is scaled so.
 """
 
 import numpy as np
@@ -127,3 +130,38 @@ def test_split_fp16_range_guard():
     with pytest.raises(P.BfError) as e:
         P.bf_vec_ex(cuda(f), 10.0, C, 4, 1, precision="fp32_split")
     assert e.value.code == B.BF_EUNSUPPORTED and "FP16" in str(e.value)
+
+
+def test_split_large_phases_reduced_in_fp64():
+    # uncentred data near 100 with sigma_r = 0.02: phases reach thousands of
+    # turns and the instance with the FP64 phase reduction runs; the split
+    # halves hold |f| x sum(omega_1) ~ 2.5e3 (within the FP16 range rule)
+    say("case split large phases: 160x160x3 in [100, 101], sigma_r = 0.02, no centring")
+    # (an image several windows across, so that most pixels see a well
+    # conditioned normaliser)
+    f = voronoi_image(160, 160, 3, 3, 100.0, 101.0, 0.02, 123)
+    C = 0.02 ** 2 * np.eye(3)
+    K, seed, sigma = 32, 17, 10.0
+    got, N_used = P.bf_vec_ex(cuda(f), sigma, C, K, seed, center=False, precision="fp32_split")
+    got = host(got)
+    f64 = f.astype(np.float64)
+    Nref, w = oracle_terms(f64, C, K, seed)
+    assert N_used == Nref
+    turns = np.abs(np.tensordot(f64, w.T, axes=(2, 0))).max() / (2 * np.pi)
+    say(f"  N={N_used} max |phase| = {turns:.0f} turns")
+    assert turns > 256
+    ref, _, Z = O.mcsf_separable(f64, sigma, w)
+    z = Z / (K * O.spatial_taps(sigma).sum() ** 2)
+    # uncentred data: the stored values carry the offset (|f| ~ 100 against a
+    # range of 1), so relative to the range the rounding of the stored halves
+    # (about 2^-22 of |f|, against FP32's 2^-24) grows by max|f| / range; the
+    # bound is FP32's 1e-4 at |f|/range = 1 scaled that way (16 ulps of the
+    # split values), taken where the ratio is well conditioned
+    ok = z >= 0.1
+    tol = 16.0 * np.abs(f64).max() / _span(f).min() * 2.0 ** -22
+    err = rel_err_per_channel(got[ok], ref[ok], f)
+    ref32 = host(P.bf_vec_ex(cuda(f), sigma, C, K, seed, center=False, precision="fp32")[0])
+    err32 = rel_err_per_channel(ref32[ok], ref[ok], f)
+    say(f"  rel_err={err} (FP32 {err32}; bound {tol:.2e}; z >= 0.1), "
+        f"{int((~ok).sum())} pixels below")
+    assert ok.sum() > 0.5 * ok.size and np.all(err <= tol), err
