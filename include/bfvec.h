@@ -124,7 +124,8 @@ typedef struct bf_opts {
                       and W >= 32 (else BF_EUNSUPPORTED); automatic picks 32
                       there unless it cuts resident waves per CU below 3/4 or
                       the image is too small to fill the GPU (fewer than two
-                      16-column, 8-row strips per compute unit).  At these
+                      16-column, 8-row strips per compute unit);
+                      BF_FP32_SPLIT runs 32 only.  At these
                       radii the passes run as banded matrix products on the
                       matrix cores: both with FP16/BF16 storage (either
                       width), and for FP32 in 32-column strips the horizontal
