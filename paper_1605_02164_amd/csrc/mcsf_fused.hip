@@ -64,7 +64,7 @@ size_t fused_lds_bytes(int d, int R, int prec, int TW, int mf) {
                         (lp ? (mf ? stage_width_mf(R) : stage_width16(R, TW)) / 2
                             : (mf ? stage_width_mf32(R) : stage_width(R, TW))) +
                     (size_t)(lp ? RS / 2 : RS) *
-                        (NC * TW + ((mf && lp) || prec == 5 ? kRingPadMF : 0) +
+                        (NC * TW + (mf && lp ? kRingPadMF : 0) +
                          (pipe && prec != 5 ? kRingPadPipe : 0)) +
                     (size_t)CRS * CST +
                     (vb ? (size_t)16 * NC * TW : 0);

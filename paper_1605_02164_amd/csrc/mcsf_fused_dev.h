@@ -417,10 +417,14 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   // columns, which a stride of 16 mod 32 floats spreads over the LDS banks.
   constexpr bool PIPE = use_pipe(PREC, RC, MF);
   // Variant 5: the ring holds the horizontal-pass rows as FP16 pairs hi + lo
-  // in two planes of pair-rows (two rows' halves in one dword, as the 16-bit
-  // instances store them), and the vertical pass runs on FP16 products.
+  // in two planes, and the vertical pass runs on FP16 products.  A plane
+  // holds one slot per 8-row step, [ch][x][q] with q the step's pair-row
+  // (rows 2q, 2q+1 as the low and high halves of a dword): the 4 dwords a
+  // lane's product operand needs (8 consecutive rows of one column) are
+  // then one 128-bit read.  RST: dwords per row pair over all slots' width
+  // (NC x TW), so that a plane is RS/2 x RST dwords.
   constexpr bool SPV = PREC == 5;
-  constexpr int RST = NC * TW + (MFV || SPV ? kRingPadMF : 0) +
+  constexpr int RST = NC * TW + (MFV ? kRingPadMF : 0) +
                       (PIPE && !SPV ? kRingPadPipe : 0);   // ring row stride: [ch][x]
   constexpr int CST = 2 * TW + cs_row_pad(PIPE || (MFV && TW == 32));   // cos/sin ring row: [k][x]
   constexpr bool LP = PREC == 1 || PREC == 2;   // 16-bit storage
@@ -573,6 +577,12 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
                           tap(u + 4, true) | tap(u + 5, true) << 16, tap(u + 6, true) | tap(u + 7, true) << 16);
     }
   }
+  // Variant 5: this lane's ring store offset in halves within a step slot:
+  // dword ((g/2) TW + x) 4 + mb of the slot, half g & 1 (see hmf_store)
+  const int spv_st = [&] {
+    const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP, g = ln >> 4;
+    return 2 * (((g >> 1) * TW + 16 * nb + (ln & 15)) * 4 + mb) + (g & 1);
+  }();
   // ---- per-thread fixed roles -------------------------------------------------
   // pass 1 item: 4-column block xq, channel ch, row rr of the step.  xq varies
   // fastest across lanes: the items' 128-bit ring writes then cover contiguous
@@ -809,15 +819,16 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     const int ln = tid & 63, mb = (tid >> 6) % NP, nb = (tid >> 6) / NP;
     const int g = ln >> 4, row = 2 * mb + (g & 1);
     if constexpr (SPV) {
-      // row r0 + row is half (g & 1) of pair-row r0/2 + mb (r0 is a multiple
-      // of 8); the lo plane follows the hi plane's RS/2 pair-rows
-      const int i0 = 2 * ((r0 / 2 + mb) * RST + (g >> 1) * TW + 16 * nb + (ln & 15)) + (g & 1);
+      // row r0 + row is half (g & 1) of pair-row q = mb of step slot r0/8
+      // (r0 is a multiple of 8): dword (r0/8) 4 RST + ((2v + g/2) TW + x) 4
+      // + mb; the lo plane follows the hi plane's RS/2 x RST dwords
+      unsigned short* const hp16 = s_ring16 + 2 * (r0 / 8) * 4 * RST;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         unsigned short h, l;
         split16(d[v], h, l);
-        s_ring16[i0 + 4 * v * TW] = h;
-        s_ring16[i0 + 4 * v * TW + RS * RST] = l;
+        hp16[spv_st + 16 * v * TW] = h;
+        hp16[spv_st + 16 * v * TW + RS * RST] = l;
       }
     } else {
 #pragma unroll
@@ -865,17 +876,16 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
       // step being stored and, past the ring's end, the window's first
       // rows again (finite values either way).
       (void)cc;
-      const unsigned* hp = s_ring32 + (2 * m) * TW + col;
-      const unsigned* lp = hp + (RS / 2) * RST;
+      // lane group l/16 reads step slot rl/8 + 4kb + l/16 (wrapped over the
+      // RS/8 slots): a uniform slot and a per-lane choice of two offsets
+      const uint4* hp = reinterpret_cast<const uint4*>(s_ring32) + (2 * m) * TW + col;
+      const uint4* lp = hp + (RS / 2) * RST / 4;
+      const int ns = RS / B, g = ln >> 4;
 #pragma unroll
       for (int kb = 0; kb < KBS; ++kb) {
-        const int pb = wrap(rl / 2 + 16 * kb + 4 * (ln >> 4), RS / 2) * RST;
-        const uint4 hc = make_uint4(hp[pb], hp[pb + RST], hp[pb + 2 * RST], hp[pb + 3 * RST]);
-        const uint4 lc = make_uint4(lp[pb], lp[pb + RST], lp[pb + 2 * RST], lp[pb + 3 * RST]);
-        const uint4 hs = make_uint4(hp[pb + TW], hp[pb + RST + TW], hp[pb + 2 * RST + TW],
-                                    hp[pb + 3 * RST + TW]);
-        const uint4 ls = make_uint4(lp[pb + TW], lp[pb + RST + TW], lp[pb + 2 * RST + TW],
-                                    lp[pb + 3 * RST + TW]);
+        const int u = __builtin_amdgcn_readfirstlane(wrap(rl / B + 4 * kb, ns));
+        const int pb = (u + g - (g >= ns - u ? ns : 0)) * RST;   // in uint4 units: slot x RST
+        const uint4 hc = hp[pb], lc = lp[pb], hs = hp[pb + TW], ls = lp[pb + TW];
         dc = mfma32<1>(vah[kb], hc, dc);
         ds = mfma32<1>(vah[kb], hs, ds);
         dc = mfma32<1>(vah[kb], lc, dc);
