@@ -37,11 +37,11 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "c457475c3a8cb61cfbf24c955bac29335d4f3bcfa2a9e0311c22d3adfc770783",
-    "fetch_factor": 1048576 / 524313.5,
+    "sha256": "a8203b40ea61434778903d473432af778cb1cb5184eb15f9a7dde15595eb23ac",
+    "fetch_factor": 1048576 / 524313.5625,
     "write_factor": 1048576 / 1048576.0,
-    "fp32": {"fetch_kib": 78532332.25, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},
-    "fp16": {"fetch_kib": 97428176.875, "write_kib": 67108754.875, "valu_flops": 505198673920.0, "mfma_flops": 20615843020800.0},
+    "fp32": {"fetch_kib": 78210137.5, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},
+    "fp16": {"fetch_kib": 97799809.1875, "write_kib": 67108715.8125, "valu_flops": 505198673920.0, "mfma_flops": 20615843020800.0},
 }
 COUNTERS_PROFILE = "profiles/mcsf_fused_voronoi4096_d3_s10_K256.md"
 

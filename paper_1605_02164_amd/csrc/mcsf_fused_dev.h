@@ -571,8 +571,10 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
 #pragma unroll
     for (int s = 0; s < KBS; ++s) {
       const int u = 32 * s + 8 * (ln >> 4) - (ln & 15);
-      vah[s] = make_uint4(tap(u, false) | tap(u + 1, false) << 16, tap(u + 2, false) | tap(u + 3, false) << 16,
-                          tap(u + 4, false) | tap(u + 5, false) << 16, tap(u + 6, false) | tap(u + 7, false) << 16);
+      vah[s] = make_uint4(tap(u, false) | tap(u + 1, false) << 16,
+                          tap(u + 2, false) | tap(u + 3, false) << 16,
+                          tap(u + 4, false) | tap(u + 5, false) << 16,
+                          tap(u + 6, false) | tap(u + 7, false) << 16);
       val[s] = make_uint4(tap(u, true) | tap(u + 1, true) << 16, tap(u + 2, true) | tap(u + 3, true) << 16,
                           tap(u + 4, true) | tap(u + 5, true) << 16, tap(u + 6, true) | tap(u + 7, true) << 16);
     }
@@ -869,15 +871,14 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
     const float* cc = s_ring + ((ln >> 4) * RST + (2 * m) * TW + col);
     f32x4_t dc = {0.0f, 0.0f, 0.0f, 0.0f}, ds = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (SPV) {
-      // KBS k-blocks of 32 window rows (16 pair-rows); lane group l/16
-      // reads pair-rows 4(l/16) .. +3 of a block, which never straddle the
-      // wrap (rl/2 and RS/2 are multiples of 4).  Window rows past 16 + 2R
-      // meet zero taps: at R = 30 the last block reaches the rows of the
-      // step being stored and, past the ring's end, the window's first
-      // rows again (finite values either way).
+      // KBS k-blocks of 32 window rows; in block kb lane group l/16 reads
+      // its 8 rows of one column, step slot rl/8 + 4kb + l/16 (wrapped over
+      // the RS/8 slots: a uniform slot and a per-lane choice of two
+      // offsets), as one 128-bit read per plane and channel.  Window rows
+      // past 16 + 2R meet zero taps: at R = 30 the last block reaches the
+      // slot of the step being stored and, past the ring's end, the
+      // window's first slot again (finite values either way).
       (void)cc;
-      // lane group l/16 reads step slot rl/8 + 4kb + l/16 (wrapped over the
-      // RS/8 slots): a uniform slot and a per-lane choice of two offsets
       const uint4* hp = reinterpret_cast<const uint4*>(s_ring32) + (2 * m) * TW + col;
       const uint4* lp = hp + (RS / 2) * RST / 4;
       const int ns = RS / B, g = ln >> 4;
