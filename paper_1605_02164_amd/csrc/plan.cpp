@@ -129,8 +129,9 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   if (!C) return fail(BF_EINVAL, "C must be non-null");
   if (o->N < 1 || o->N > 65536)
     return fail(BF_EINVAL, "plans need an explicit order: opts.N in [1, 65536]");
-  if (o->precision != BF_FP32 && o->precision != BF_FP16 && o->precision != BF_BF16)
-    return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16 or BF_BF16");
+  if (o->precision != BF_FP32 && o->precision != BF_FP16 && o->precision != BF_BF16 &&
+      o->precision != BF_FP32_SPLIT)
+    return fail(BF_EINVAL, "opts.precision must be BF_FP32, BF_FP16, BF_BF16 or BF_FP32_SPLIT");
   if (o->center != 0 && o->center != 1) return fail(BF_EINVAL, "opts.center must be 0 or 1");
   if (o->tile_h < 0) return fail(BF_EINVAL, "opts.tile_h must be >= 0");
   if (o->dedup != 0 && o->dedup != 1) return fail(BF_EINVAL, "opts.dedup must be 0 or 1");
@@ -140,6 +141,8 @@ int bf_plan_create(int H, int W, int d, double sigma_s, const double* C, int K, 
   if (o->num_out || o->z_out || o->time_kernel)
     return fail(BF_EINVAL, "plans take no num_out, z_out or time_kernel");
   if (o->valu_only != 0 && o->valu_only != 1) return fail(BF_EINVAL, "opts.valu_only must be 0 or 1");
+  if (o->precision == BF_FP32_SPLIT && o->valu_only)
+    return fail(BF_EUNSUPPORTED, "BF_FP32_SPLIT runs its passes on the matrix cores (valu_only = 0)");
   double Wm[64];
   if ((rc = whiten(d, C, Wm, o->whiten))) return rc;
   const int R = window_radius(sigma_s, spatial_boxes(o->spatial));

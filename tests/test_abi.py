@@ -228,7 +228,9 @@ def test_plan_validation_before_device_work():
     assert create(sigma=float("nan")) == B.BF_EINVAL
     assert create(Cp=None) == B.BF_EINVAL
     assert create(precision=7) == B.BF_EINVAL
-    assert create(precision="fp32_split", sigma=10.0, H=64, W=64) == B.BF_EINVAL   # not in plans
+    assert create(precision="fp32_split", sigma=2.0, H=64, W=64) == B.BF_EUNSUPPORTED   # R = 6
+    assert create(precision="fp32_split", sigma=10.0, H=64, W=64,
+                  valu_only=True) == B.BF_EUNSUPPORTED
     assert create(time_kernel=True) == B.BF_EINVAL
     bad = np.array([[1.0, 2, 0], [2, 1, 0], [0, 0, 1]])
     assert create(Cp=bad.ctypes.data_as(ctypes.c_void_p)) == B.BF_ENOTSPD

@@ -16,6 +16,7 @@ held to the FP32 bounds of the other parity tests:
 * strip heights change no output bit (the pair's k-blocks are fixed relative
   to the pair), and the result stays within 1e-5 of the range of plain FP32;
 * the FP16 range rule of BF_FP16 applies to the FP16 halves;
+* a plan (graph, FP64-phase instance) gives bf_vec_ex's bits;
 * phases beyond 2^8 turns (uncentred data near 100) take the instance with
   the FP64 phase reduction; there the halves' rounding (2^-22 of |f|) grows
   relative to the range by max|f| / range, and the bound is scaled so.
@@ -165,3 +166,19 @@ def test_split_large_phases_reduced_in_fp64():
     say(f"  rel_err={err} (FP32 {err32}; bound {tol:.2e}; z >= 0.1), "
         f"{int((~ok).sum())} pixels below")
     assert ok.sum() > 0.5 * ok.size and np.all(err <= tol), err
+
+
+def test_split_plan_bitwise_equal_to_vec_ex():
+    # a plan runs the FP64-phase instance in a captured graph; lanes below
+    # 2^8 turns run the same operations as bf_vec_ex's instance
+    say("case split plan")
+    f, C, p = workload("lab1024_d3_s5_K128")
+    f = np.ascontiguousarray(f[:256, :200])
+    sigma, K, seed = 8.0, 16, 21
+    fg = cuda(f)
+    ref, o = P.bf_vec_ex(fg, sigma, C, K, seed, precision="fp32_split", return_opts=True)
+    ref = host(ref)
+    with P.Plan(*f.shape, sigma, C, K, seed, N=o.N_used, precision="fp32_split") as plan:
+        assert plan.tile_w_used == 32 and plan.mfma_used == 1
+        for _ in range(3):
+            assert np.array_equal(host(plan(fg)), ref)
