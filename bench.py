@@ -37,7 +37,7 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "a8203b40ea61434778903d473432af778cb1cb5184eb15f9a7dde15595eb23ac",
+    "sha256": "b64b33814168195d069cdcc98923faf142631e490951982a52d52dbaaf294760",
     "fetch_factor": 1048576 / 524313.5625,
     "write_factor": 1048576 / 1048576.0,
     "fp32": {"fetch_kib": 78210137.5, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},

@@ -62,9 +62,9 @@ enum {
  * the FP32 datapath the horizontal pass and the modulation use.  Errors
  * against the FP64 reference measure the same as BF_FP32's.  Exists for
  * d = 3, window radius 21, 24 or 30 (the Gaussian's sigma_s 7, 8, 10) and
- * W >= 32 (else BF_EUNSUPPORTED), not with valu_only or the server; its
- * FP16 halves need the FP16 range rule of BF_FP16 (checked where the image's
- * range is known: not by plans, as for BF_FP16).  (3 and 4 are not
+ * W >= 32 (else BF_EUNSUPPORTED), not with valu_only; its FP16 halves need
+ * the FP16 range rule of BF_FP16 (checked where the image's range is known:
+ * bf_vec_ex and the server, not plans, as for BF_FP16).  (3 and 4 are not
  * precisions.) */
 enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2, BF_FP32_SPLIT = 5 };
 
@@ -372,7 +372,7 @@ typedef struct bf_request {
   int K;                /* Monte Carlo terms                                      */
   int N;                /* raised-cosine order; 0 = automatic rule                */
   uint64_t seed;        /* term draws, as in bf_vec_ex                            */
-  int precision;        /* BF_FP32, BF_FP16, BF_BF16                              */
+  int precision;        /* BF_FP32, BF_FP16, BF_BF16, BF_FP32_SPLIT               */
   int center;           /* as bf_opts.center                                      */
   double arrival;       /* server clock (s, see bf_server_clock) at which the
                            request arrives; <= 0: at submit.  Latency is measured

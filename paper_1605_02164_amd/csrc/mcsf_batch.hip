@@ -15,6 +15,7 @@ hipError_t launch_fused_batch(int d, int R, int prec, const BatchArgs& b, hipStr
     case 2: return launch_p<2>(d, b, R, st);
     case 3: return launch_p<3>(d, b, R, st);
     case 4: return d == 3 ? launch_sl_r(b, R, st) : hipErrorInvalidValue;
+    case 5: return d == 3 ? launch_sp_r(b, R, st) : hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

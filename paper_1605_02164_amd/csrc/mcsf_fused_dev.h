@@ -1569,17 +1569,28 @@ static hipError_t launch_sl_r(const A& a, int R, hipStream_t st) {
 }
 
 // Variant 5 (split vertical pass): the pipelined 32-column instances at
-// R = 21, 24 and 30; single requests only.
-template <int RC>
-static hipError_t launch_sp(const FusedArgs& a, hipStream_t st) {
-  if (a.TWc != kTWMax || a.valu || a.TH % (2 * kB)) return hipErrorInvalidValue;
-  void (*kern)(FusedArgs) =
-      a.p64 ? mcsf_fused<3, RC, 5, true, kTWMax, true> : mcsf_fused<3, RC, 5, false, kTWMax, true>;
+// R = 21, 24 and 30 (whole pairs of 8-row steps per strip).
+template <int RC, class A>
+static hipError_t launch_sp(const A& a, hipStream_t st) {
+  int nwg;
+  void (*kern)(A);
+  if constexpr (std::is_same_v<A, BatchArgs>) {
+    for (int k = 0; k < a.n; ++k)
+      if (a.req[k].p64 != a.req[0].p64 || a.req[k].TWc != kTWMax || a.req[k].valu ||
+          a.req[k].TH % (2 * kB))
+        return hipErrorInvalidValue;
+    kern = a.req[0].p64 ? mcsf_fused_batch<3, RC, 5, true, kTWMax, true>
+                        : mcsf_fused_batch<3, RC, 5, false, kTWMax, true>;
+    nwg = a.first[a.n];
+  } else {
+    if (a.TWc != kTWMax || a.valu || a.TH % (2 * kB)) return hipErrorInvalidValue;
+    kern = a.p64 ? mcsf_fused<3, RC, 5, true, kTWMax, true> : mcsf_fused<3, RC, 5, false, kTWMax, true>;
+    nwg = a.nsx * a.nsy;
+  }
   const size_t lds = fused_lds_bytes(3, RC, 5, kTWMax, 1);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int nwg = a.nsx * a.nsy;
   if (nwg <= 0) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3(nwg), dim3(64 * 4 * 2), lds, st, a);
   return hipGetLastError();
@@ -1587,18 +1598,11 @@ static hipError_t launch_sp(const FusedArgs& a, hipStream_t st) {
 
 template <class A>
 static hipError_t launch_sp_r(const A& a, int R, hipStream_t st) {
-  if constexpr (std::is_same_v<A, BatchArgs>) {
-    (void)a;
-    (void)R;
-    (void)st;
-    return hipErrorInvalidValue;
-  } else {
-    switch (R) {
-      case 21: return launch_sp<21>(a, st);
-      case 24: return launch_sp<24>(a, st);
-      case 30: return launch_sp<30>(a, st);
-      default: return hipErrorInvalidValue;
-    }
+  switch (R) {
+    case 21: return launch_sp<21>(a, st);
+    case 24: return launch_sp<24>(a, st);
+    case 30: return launch_sp<30>(a, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

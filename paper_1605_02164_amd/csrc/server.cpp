@@ -60,8 +60,10 @@ double model_term_us(const FusedArgs& a, int d, int prec) {
   const double NC = 2.0 * (d + 1), taps = 2.0 * a.R + 1.0;
   const double mod = (double)kB * (a.TWc + 2 * a.R) * (4.0 * d + 2.0);
   const double one = (double)kB * NC * a.TWc * taps * 2.0;   // one FIR pass, FP32
-  const double pass = prec >= 3 ? one + (double)kB * NC * a.TWc * 8.0
-                                : 2.0 * one * (prec == BF_FP32 ? 1.0 : 0.5);
+  // variants 3 and 4: the running-sum vertical pass; 5: FP32 with the
+  // vertical pass on FP16 products (measured ~0.78 of FP32's time)
+  const double pass = (prec == 3 || prec == 4) ? one + (double)kB * NC * a.TWc * 8.0
+                      : 2.0 * one * (prec == BF_FP32 ? 1.0 : prec == 5 ? 0.75 : 0.5);
   const double per_step = mod + pass;
   const double flops = per_step * a.steps * (double)a.nsx * a.nsy;
   return flops / 50e12 * 1e6;
@@ -244,7 +246,7 @@ struct Server {
                                               spatial_boxes(r->in.spatial));
     for (int m = 0; m < 8; ++m)
       r->a.cen[m] = (r->in.center && m < d) ? (float)(0.5 * ((double)lo[m] + (double)hi[m])) : 0.0f;
-    if (r->in.precision == BF_FP16 &&
+    if ((r->in.precision == BF_FP16 || r->in.precision == BF_FP32_SPLIT) &&
         check_fp16_range(d, r->in.sigma_s, spatial_boxes(r->in.spatial), lo, hi, r->a.cen) != BF_OK) {
       finish(r, BF_REQ_FAILED, BF_EUNSUPPORTED, bf_last_error());
       return false;
@@ -750,8 +752,9 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
     return fail(BF_EINVAL, "sigma_s must be finite and in [0, 32]");
   if (in.K < 1 || in.K > 65536) return fail(BF_EINVAL, "K must be in [1, 65536]");
   if (in.N < 0 || in.N > 65536) return fail(BF_EINVAL, "N must be 0 (auto) or in [1, 65536]");
-  if (in.precision != BF_FP32 && in.precision != BF_FP16 && in.precision != BF_BF16)
-    return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16 or BF_BF16");
+  if (in.precision != BF_FP32 && in.precision != BF_FP16 && in.precision != BF_BF16 &&
+      in.precision != BF_FP32_SPLIT)
+    return fail(BF_EINVAL, "precision must be BF_FP32, BF_FP16, BF_BF16 or BF_FP32_SPLIT");
   if (in.center != 0 && in.center != 1) return fail(BF_EINVAL, "center must be 0 or 1");
   if (in.dedup != 0 && in.dedup != 1) return fail(BF_EINVAL, "dedup must be 0 or 1");
   if (int rs = check_spatial(in.spatial, in.precision)) return rs;
@@ -805,7 +808,8 @@ int plan_request(Server* s, const bf_request* q, Req* r) {
   // hi and lo term rows, weights, taps (term_table's layout)
   r->n_tab = (size_t)in.K * (2 * in.d + 3) + (size_t)(2 * r->R + 1);
   // a host image is uploaded on the reduction's stream before the kernels
-  r->need_minmax = in.N == 0 || in.center || in.precision == BF_FP16 || in.f_host;
+  r->need_minmax = in.N == 0 || in.center || in.precision == BF_FP16 ||
+                   in.precision == BF_FP32_SPLIT || in.f_host;
   r->nparts = minmax_parts((size_t)in.H * in.W);
   r->n_part = r->need_minmax ? (size_t)r->nparts * kMMFloats + kMMResult : 0;
   r->n_img = in.f_host ? (size_t)in.H * in.W * in.d : 0;

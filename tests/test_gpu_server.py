@@ -390,3 +390,28 @@ def test_server_modes_match_standalone_bitwise(pools, policy, graph_rounds, auto
         assert stats["rounds"] >= 4
         # the cost model's scale, measured from the rounds' device time
         assert 0.05 <= stats["model_scale"] <= 20.0 and stats["model_scale"] != 1.0, stats
+
+
+def test_split_precision_served_equals_standalone():
+    # the split FP32 mode's batched instances (d = 3, R = 21, 24, 30): several
+    # requests per launch, term ranges resumed across rounds, each result
+    # the bits of bf_vec_ex; an unsupported radius is refused at submit
+    specs = [(96, 70, 7.0), (64, 100, 8.0), (80, 96, 10.0), (64, 64, 10.0)]
+    imgs = [torch.from_numpy(voronoi_image(H, W, 3, 5, 0.0, 1.0, 0.02, seed=500 + i)).to(DEV)
+            for i, (H, W, _) in enumerate(specs)]
+    C = 0.1 ** 2 * np.eye(3)
+    with P.Server(arena_bytes=1 << 28, quantum_us=5.0) as srv:
+        ts = []
+        for i, ((H, W, s), f) in enumerate(zip(specs, imgs)):
+            for k in (5, 40):
+                t, out = srv.submit(f, s, C, k, seed=i * 10 + k, precision="fp32_split")
+                ts.append((f, s, k, i, t, out))
+        with pytest.raises(P.BfError) as e:
+            srv.submit(imgs[0], 2.0, C, 4, 1, precision="fp32_split")
+        assert e.value.code == B.BF_EUNSUPPORTED
+        srv.drain(timeout=60.0)
+        for f, s, k, i, t, out in ts:
+            assert srv.poll(t)["state"] == "done"
+            ref, _ = P.bf_vec_ex(f, s, C, k, seed=i * 10 + k, precision="fp32_split")
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (s, k, i)
