@@ -16,7 +16,8 @@ held to the FP32 bounds of the other parity tests:
 * strip heights change no output bit (the pair's k-blocks are fixed relative
   to the pair), and the result stays within 1e-5 of the range of plain FP32;
 * the FP16 range rule of BF_FP16 applies to the FP16 halves;
-* a plan (graph, FP64-phase instance) gives bf_vec_ex's bits;
+* a plan (graph, FP64-phase instance) and bf_vec_static give bf_vec_ex's
+  bits, and merged +-Y draws stay within FP32 rounding of the full sum;
 * phases beyond 2^8 turns (uncentred data near 100) take the instance with
   the FP64 phase reduction; there the halves' rounding (2^-22 of |f|) grows
   relative to the range by max|f| / range, and the bound is scaled so.
@@ -182,3 +183,23 @@ def test_split_plan_bitwise_equal_to_vec_ex():
         assert plan.tile_w_used == 32 and plan.mfma_used == 1
         for _ in range(3):
             assert np.array_equal(host(plan(fg)), ref)
+
+
+def test_split_static_dedup_and_weighted_terms():
+    # the split instances behind the other entry points: bf_vec_static (static
+    # scratch) gives bf_vec_ex's bits; merged +-Y draws (exact in arithmetic)
+    # stay within FP32 rounding of the K drawn terms
+    say("case split static / dedup")
+    f = voronoi_image(256, 320, 3, 12, 0.0, 1.0, 0.02, seed=77)
+    C = 0.1 ** 2 * np.eye(3)
+    fg = cuda(f)
+    ref, o = P.bf_vec_ex(fg, 10.0, C, 48, 5, precision="fp32_split", return_opts=True)
+    got, os_ = P.bf_vec_static(fg, 10.0, C, 48, 5, precision="fp32_split", return_opts=True)
+    assert (os_.tile_h_used, os_.tile_w_used) == (o.tile_h_used, o.tile_w_used)
+    assert np.array_equal(host(got), host(ref))
+    dd, od = P.bf_vec_ex(fg, 10.0, C, 48, 5, precision="fp32_split", dedup=True, return_opts=True)
+    say(f"  K_used {od.K_used} of 48")
+    assert od.K_used < 48
+    e = np.abs(host(dd) - host(ref)).reshape(-1, 3).max(0) / _span(f)
+    say(f"  max |dedup - full| / range = {e}")
+    assert np.all(e <= 1e-5), e
