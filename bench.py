@@ -37,7 +37,7 @@ TRAFFIC_SOURCES = ["paper_1605_02164_amd/csrc/mcsf_fused_dev.h",
                    "paper_1605_02164_amd/csrc/mcsf_common.h",
                    "paper_1605_02164_amd/csrc/mcsf_fused.hip"]
 TRAFFIC = {
-    "sha256": "b64b33814168195d069cdcc98923faf142631e490951982a52d52dbaaf294760",
+    "sha256": "da6c486fd86f1c5303c2a3bd0b07aa347fad04d42cecc7b01c6459efadd2c97d",
     "fetch_factor": 1048576 / 524313.5625,
     "write_factor": 1048576 / 1048576.0,
     "fp32": {"fetch_kib": 78210137.5, "write_kib": 67108864.0, "valu_flops": 318634459136.0, "mfma_flops": 10771777978368.0},

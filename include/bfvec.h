@@ -61,7 +61,7 @@ enum {
  * FP16 products hi.hi + lo.hi + hi.lo on the matrix cores, so that it leaves
  * the FP32 datapath the horizontal pass and the modulation use.  Errors
  * against the FP64 reference measure the same as BF_FP32's.  Exists for
- * d = 3, window radius 21, 24 or 30 (the Gaussian's sigma_s 7, 8, 10) and
+ * d = 3, window radius 18, 21, 24 or 30 (the Gaussian's sigma_s 6, 7, 8, 10) and
  * W >= 32 (else BF_EUNSUPPORTED), not with valu_only; its FP16 halves need
  * the FP16 range rule of BF_FP16 (checked where the image's range is known:
  * bf_vec_ex and the server, not plans, as for BF_FP16).  (3 and 4 are not

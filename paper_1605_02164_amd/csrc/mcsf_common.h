@@ -64,13 +64,15 @@ inline constexpr bool use_mf(int TW, int prec, int R) {
 // overlaps the products with the modulation on the VALU.  Below R = 21 the
 // extra LDS would halve the resident workgroups.
 inline constexpr bool use_pipe(int prec, int R, bool mf) {
-  return mf && (prec == 0 || prec == 5) && R >= 21;
+  return mf && ((prec == 0 && R >= 21) || (prec == 5 && R >= 18));
 }
 // Variant 5 (FP32 channels, split vertical pass): the pipelined instances with
 // the horizontal-pass rows kept as FP16 pairs hi + lo and the vertical pass as
 // 16x16x32 FP16 products (hi.hi + lo.hi + hi.lo, FP32 accumulation).  They
-// exist for d = 3, 32-column strips and the compile-time radii from 21 up.
-inline constexpr bool split_radius(int R) { return R == 21 || R == 24 || R == 30; }
+// exist for d = 3, 32-column strips and the compile-time radii from 18 up
+// (at 18 the FP32 instance already runs one workgroup per CU, so the
+// pipeline's extra LDS costs no residency there).
+inline constexpr bool split_radius(int R) { return R == 18 || R == 21 || R == 24 || R == 30; }
 // Ring row padding of those instances, in floats (16 mod 32: conflict-free
 // reads of 4 rows x 16 columns).
 constexpr int kRingPadPipe = 16;

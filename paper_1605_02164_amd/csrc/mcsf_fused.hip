@@ -174,6 +174,7 @@ int fused_blocks_per_cu(int d, int R, int prec, int TW, int valu) {
   switch (prec) {
     case 5:
       switch (R) {
+        case 18: return blocks_per_cu_sp<18>();
         case 21: return blocks_per_cu_sp<21>();
         case 24: return blocks_per_cu_sp<24>();
         default: return blocks_per_cu_sp<30>();
@@ -226,8 +227,8 @@ int choose_strip_width(int d, int R, int prec, int H, int W, int requested, int*
   if (prec == 5) {
     if (d != 3 || !split_radius(R) || W < kTWMax || requested == kTW)
       return fail(BF_EUNSUPPORTED,
-                  "BF_FP32_SPLIT needs d = 3, a window radius of 21, 24 or 30 (sigma_s 7, 8 or "
-                  "10 for the Gaussian), W >= 32 and 32-column strips");
+                  "BF_FP32_SPLIT needs d = 3, a window radius of 18, 21, 24 or 30 (sigma_s 6, "
+                  "7, 8 or 10 for the Gaussian), W >= 32 and 32-column strips");
     *TW = kTWMax;
     return BF_OK;
   }

@@ -396,7 +396,7 @@ __device__ __forceinline__ float ld_const(const float* p, int i) {
 template <int D, int RC, int PREC, bool P64, int TW = kTW, bool MF = false>
 __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   static_assert(PREC >= 0 && PREC <= 5, "kernel variant");
-  static_assert(PREC != 5 || (TW == 32 && MF && D == 3 && RC >= 21),
+  static_assert(PREC != 5 || (TW == 32 && MF && D == 3 && RC >= 18),
                 "split vertical pass: pipelined 32-column FP32 instances");
   static_assert(TW == 16 || (TW == 32 && (2 * (D + 1)) % 4 == 0 && PREC != 3), "strip width");
   static_assert(PREC != 4 || (TW == 32 && MF && D == 3 && RC >= 0 && RC % 3 == 0),
@@ -408,7 +408,7 @@ __device__ __forceinline__ void fused_strip(const FusedArgs& a, int bid) {
   constexpr int NP = G::NP, NC = G::NC, NT = G::NT, MI = G::MI;
   constexpr int B = kB;
   constexpr bool MFV = MF && (PREC == 1 || PREC == 2);   // vertical pass on the matrix cores too
-  // PIPE (FP32 matrix-core instances, R >= 21): both passes on the matrix
+  // PIPE (FP32 matrix-core instances, R >= 21; variant 5 from R = 18): both passes on the matrix
   // cores, the vertical one over pairs of steps (16 output rows), and one
   // barrier per step (the loop below).  That needs two staging buffers and
   // two more ring steps: step g is written while the pair's window, steps
@@ -1569,7 +1569,7 @@ static hipError_t launch_sl_r(const A& a, int R, hipStream_t st) {
 }
 
 // Variant 5 (split vertical pass): the pipelined 32-column instances at
-// R = 21, 24 and 30 (whole pairs of 8-row steps per strip).
+// R = 18, 21, 24 and 30 (whole pairs of 8-row steps per strip).
 template <int RC, class A>
 static hipError_t launch_sp(const A& a, hipStream_t st) {
   int nwg;
@@ -1599,6 +1599,7 @@ static hipError_t launch_sp(const A& a, hipStream_t st) {
 template <class A>
 static hipError_t launch_sp_r(const A& a, int R, hipStream_t st) {
   switch (R) {
+    case 18: return launch_sp<18>(a, st);
     case 21: return launch_sp<21>(a, st);
     case 24: return launch_sp<24>(a, st);
     case 30: return launch_sp<30>(a, st);

@@ -166,7 +166,7 @@ def test_invalid_options_rejected():
     dict(valu_only=True),
 ])
 def test_split_precision_refused_before_device_work(kw):
-    # BF_FP32_SPLIT runs only the pipelined d = 3 instances at R = 21, 24, 30
+    # BF_FP32_SPLIT runs only the pipelined d = 3 instances at R = 18, 21, 24, 30
     d = kw.pop("d", 3)
     C = kw.pop("C", np.eye(3) * 0.01)
     sigma = kw.pop("sigma", 10.0)

@@ -393,7 +393,7 @@ def test_server_modes_match_standalone_bitwise(pools, policy, graph_rounds, auto
 
 
 def test_split_precision_served_equals_standalone():
-    # the split FP32 mode's batched instances (d = 3, R = 21, 24, 30): several
+    # the split FP32 mode's batched instances (d = 3, R = 18, 21, 24, 30): several
     # requests per launch, term ranges resumed across rounds, each result
     # the bits of bf_vec_ex; an unsupported radius is refused at submit
     specs = [(96, 70, 7.0), (64, 100, 8.0), (80, 96, 10.0), (64, 64, 10.0)]
