@@ -793,8 +793,8 @@ def main():
     flops = algorithmic_flops_per_pixel(d, R, K) * H * W
     precs = [args.precision] if args.only else [args.precision] + \
         [q for q in ("fp32", "fp16", "bf16") if q != args.precision] + \
-        ["fp32_split", "fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_box3",
-         "fp32_box3rs", "fp32_box3sl"]
+        ["fp32_split", "fp32_valu", "fp16_valu", "fp32_dedup", "fp16_dedup", "fp32_split_dedup",
+         "fp32_box3", "fp32_box3rs", "fp32_box3sl"]
     if args.modes:
         precs = args.modes.split(",")
         args.precision = precs[0].split("_")[0]
