@@ -16,6 +16,8 @@ held to the FP32 bounds of the other parity tests:
 * strip heights change no output bit (the pair's k-blocks are fixed relative
   to the pair), and the result stays within 1e-5 of the range of plain FP32;
 * the FP16 range rule of BF_FP16 applies to the FP16 halves;
+* edge shapes (shorter than the window, one ragged strip, odd sizes) at
+  every split radius against O3 over the whole image;
 * a plan (graph, FP64-phase instance) and bf_vec_static give bf_vec_ex's
   bits, and merged +-Y draws stay within FP32 rounding of the full sum;
 * phases beyond 2^8 turns (uncentred data near 100) take the instance with
@@ -203,3 +205,20 @@ def test_split_static_dedup_and_weighted_terms():
     e = np.abs(host(dd) - host(ref)).reshape(-1, 3).max(0) / _span(f)
     say(f"  max |dedup - full| / range = {e}")
     assert np.all(e <= 1e-5), e
+
+
+@pytest.mark.parametrize("H,W,sigma", [(17, 33, 10.0), (40, 200, 6.0), (300, 35, 8.0),
+                                       (129, 97, 7.0)])
+def test_split_edge_shapes(H, W, sigma):
+    # images shorter than the window, one ragged strip across, odd sizes
+    say(f"case split edge shape {H}x{W} sigma_s={sigma}")
+    f = voronoi_image(H, W, 3, 4, 0.0, 1.0, 0.02, seed=H * 7 + W)
+    C = 0.12 ** 2 * np.eye(3)
+    K, seed = 8, 3
+    got, N = P.bf_vec_ex(cuda(f), sigma, C, K, seed, precision="fp32_split")
+    got = host(got)
+    f64 = f.astype(np.float64)
+    Nref, w = oracle_terms(f64, C, K, seed)
+    assert N == Nref
+    ref, _, Z = O.mcsf_separable(f64, sigma, w)
+    assert_close(got, ref, f, Z / (K * O.spatial_taps(sigma).sum() ** 2))
